@@ -1,0 +1,151 @@
+/*
+ * mgq1.h - geometric multigrid V-cycle for nodal-block Q1 operators on MI355X (gfx950).
+ *
+ * The solver follows the paper's Algorithm "Geometric multigrid solver" (Sec. 2.2):
+ * GMG(l, x, b) = coarse solve on level 0; otherwise pre-smooth, restrict the residual,
+ * recurse from 0, prolongate and add, post-smooth.  The smoother is the fixed-matrix
+ * iteration x <- x + omega S (b - A x) with S the inverse of the nodal diagonal blocks
+ * (damped Jacobi for one component, nodal block-Jacobi / point-Vanka for systems), and
+ * transfers are sparse matrices with R = P^T (Sec. 4.1 "Geometric Multigrid CUDA").
+ * The V-cycle is used as a solver (defect correction) or as the preconditioner of a
+ * restarted GMRES with modified Gram-Schmidt and Givens rotations (Sec. 4.2).
+ *
+ * Data layout (Sec. 2.1, Sec. 4.1 "Storage"): vectors are node-major / component-minor,
+ * x[node * b + c]; matrices are block CSR with b x b blocks stored row-major.
+ *
+ * Levels are numbered 0 (coarsest) .. L (finest).  Level l >= 1 brings the scalar
+ * prolongation P~_l (n_l x n_{l-1}) and the constrained-DoF mask M; the library applies
+ * P = M_l (P~_l (x) I_b) M_{l-1} and R = P^T.
+ *
+ * Ownership: setup deep-copies every input (host or device) into library-owned device
+ * memory; the caller may free its arrays afterwards.  Vector arguments of the solve
+ * entry points are caller-owned device pointers (FP64, contiguous).  All device work is
+ * enqueued on the caller's HIP stream; mg_solve synchronises that stream only to read
+ * the convergence scalars.  No entry point aborts the process; errors are negative
+ * return codes with a message in mg_last_error() (thread-local).  A handle must not be
+ * used from two threads (or two streams) at once.
+ */
+#ifndef MGQ1_H
+#define MGQ1_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MG_OK = 0,
+  MG_EINVAL = -1,      /* malformed input: sizes, indices, pattern, mask rows, NaN/Inf */
+  MG_ENOMEM = -2,      /* device or host allocation failed */
+  MG_EDEVICE = -3,     /* a HIP call failed */
+  MG_ESINGULAR = -4,   /* a nodal diagonal block or the coarse matrix is singular */
+  MG_ENOCONV = -5,     /* mg_solve reached maxit (statistics are still filled) */
+  MG_ENUMERIC = -6,    /* NaN/Inf or divergence (residual > 1e6 x initial) in mg_solve */
+  MG_EUNSUPPORTED = -7 /* valid request the library does not implement (e.g. block > 4) */
+};
+
+enum { MG_COARSE_EXACT = 0, MG_COARSE_SMOOTH = 1 };
+enum { MG_OUTER_IR = 0, MG_OUTER_FGMRES = 1 };
+/* precision of the V-cycle; the outer defect, the update and the coarse solve are FP64 */
+enum { MG_PREC_FP64 = 0, MG_PREC_FP32 = 1, MG_PREC_FP32_F16VAL = 2, MG_PREC_FP32_BF16VAL = 3 };
+
+/* One level of the hierarchy (Sec. 2.2: meshes Omega_0 .. Omega_L and their spaces). */
+typedef struct {
+  int32_t n_nodes;            /* nodes on this level */
+  int32_t block;              /* components per node, 1..4 */
+  int64_t nnzb;               /* stored b x b blocks */
+  const int32_t* A_rowptr;    /* n_nodes + 1, A_rowptr[0] = 0, non-decreasing */
+  const int32_t* A_col;       /* nnzb node indices, sorted and unique per row, diagonal present */
+  const double* A_val;        /* nnzb * b * b values, block row-major */
+  int32_t p_cols;             /* nodes of level l-1 (ignored on level 0) */
+  int64_t p_nnz;
+  const int32_t* P_rowptr;    /* scalar P~: n_nodes + 1 (NULL on level 0) */
+  const int32_t* P_col;       /* p_nnz coarse node indices, sorted and unique per row */
+  const double* P_val;        /* p_nnz weights (without the masks) */
+  const uint8_t* dof_mask;    /* n_nodes * b; 1 = constrained DoF: its row and column of A
+                                 must be the identity row / column */
+} mg_level_in;
+
+typedef struct {
+  double omega;               /* smoother damping */
+  int32_t nu1, nu2;           /* pre- / post-smoothing sweeps */
+  int32_t coarse_mode;        /* MG_COARSE_EXACT (dense inverse) or MG_COARSE_SMOOTH */
+  int32_t coarse_sweeps;      /* sweeps on level 0 in MG_COARSE_SMOOTH mode */
+  int32_t precision;          /* MG_PREC_* */
+  int32_t outer;              /* MG_OUTER_IR or MG_OUTER_FGMRES */
+  int32_t gmres_m;            /* restart length, 1..64 */
+  int32_t maxit;              /* maximum number of V-cycles in mg_solve */
+  double rtol;                /* stop when ||b - A x||_2 <= rtol ||b||_2 */
+  int32_t use_graph;          /* reserved, 0 */
+} mg_config;
+
+typedef struct {
+  int32_t iters;              /* V-cycles applied */
+  int32_t restarts;           /* outer restarts (FGMRES) */
+  int32_t status;             /* MG_OK, MG_ENOCONV or MG_ENUMERIC */
+  int32_t converged;
+  double res0, res_final;     /* ||b - A x0||_2, ||b - A x||_2 (FP64, all rows) */
+  double t_solve_ms;          /* wall time of mg_solve including the final synchronisation */
+} mg_solve_stats;
+
+typedef struct mg_handle mg_handle;
+
+/* Copy a hierarchy to the device and prepare smoother blocks, R = P~^T, the coarse
+ * inverse and reduced-precision copies.  `lv[0]` is the coarsest level.
+ * inputs_on_device: 0 = host pointers, 1 = device pointers.  stream: hipStream_t or NULL. */
+int mg_setup_hierarchy(const mg_level_in* lv, int32_t n_levels, const mg_config* cfg,
+                       int32_t inputs_on_device, void* stream, mg_handle** out);
+
+/* x = GMG(L, 0, b): one V-cycle on the finest level from the initial value 0
+ * (Algorithm "Geometric multigrid solver").  b, x: device FP64, n_L * b each. */
+int mg_vcycle(mg_handle* h, const double* b, double* x, void* stream);
+
+/* Solve A_L x = b to rtol (x is the initial guess on entry, the result on exit).
+ * MG_OUTER_IR: x <- x + V(b - A x) (the MG iteration of Algorithm "Geometric multigrid
+ * solver"); MG_OUTER_FGMRES: restarted flexible GMRES(m) right-preconditioned by one
+ * V-cycle (Sec. 4.2).  `stats` may be NULL.  Returns MG_OK, MG_ENOCONV or MG_ENUMERIC. */
+int mg_solve(mg_handle* h, const double* b, double* x, mg_solve_stats* stats, void* stream);
+
+/* Same as mg_solve with the outer loop fixed to exactly `iters` V-cycles (FGMRES restarts
+ * every m); the tolerance is not tested.  Used for step-by-step comparisons. */
+int mg_solve_fixed(mg_handle* h, const double* b, double* x, int32_t iters,
+                   mg_solve_stats* stats, void* stream);
+
+/* The hot-path steps one at a time on level `level` (FP64 handles only; device FP64):
+ *   mg_level_defect   r = b - A_l x            (masked = 1: r = 0 on constrained DoFs)
+ *   mg_level_spmv     y = A_l x
+ *   mg_level_sweep    x_out = x + omega S_l (b - A_l x)      (Sec. 4.1 smoother)
+ *   mg_level_sweep0   x_out = omega S_l b                    (first sweep from 0)
+ *   mg_level_restrict d_{l-1} = R_{l-1} r = M_{l-1} P~^T M_l r
+ *   mg_level_prolong  x_l += M_l P~ M_{l-1} y_{l-1}
+ *   mg_coarse_solve   x_0 = A_0^{-1} b_0 (or coarse_sweeps sweeps from 0)          */
+int mg_level_defect(mg_handle* h, int32_t level, const double* b, const double* x, double* r,
+                    int32_t masked, void* stream);
+int mg_level_spmv(mg_handle* h, int32_t level, const double* x, double* y, void* stream);
+int mg_level_sweep(mg_handle* h, int32_t level, const double* b, const double* x, double* x_out,
+                   void* stream);
+int mg_level_sweep0(mg_handle* h, int32_t level, const double* b, double* x_out, void* stream);
+int mg_level_restrict(mg_handle* h, int32_t level, const double* r_fine, double* d_coarse,
+                      void* stream);
+int mg_level_prolong(mg_handle* h, int32_t level, const double* y_coarse, double* x_fine,
+                     void* stream);
+int mg_coarse_solve(mg_handle* h, const double* b, double* x, void* stream);
+
+/* Sizes of level `level`: nodes, block size, stored blocks. */
+int mg_level_info(const mg_handle* h, int32_t level, int32_t* n_nodes, int32_t* block,
+                  int64_t* nnzb);
+int32_t mg_num_levels(const mg_handle* h);
+
+/* Host-only structural validation of one level (and its coarser neighbour for P~);
+ * no device is touched.  Returns MG_OK or MG_EINVAL with a message. */
+int mg_validate_level(const mg_level_in* lv, const mg_level_in* coarser);
+
+void mg_destroy(mg_handle* h);
+const char* mg_status_string(int status);
+const char* mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

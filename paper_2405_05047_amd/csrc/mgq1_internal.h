@@ -1,0 +1,103 @@
+// Internal declarations shared by the HIP kernels and the host runtime of libmgq1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mgq1 {
+
+// storage kind of matrix values
+enum ValKind { VK_F64 = 0, VK_F32 = 1, VK_F16 = 2, VK_BF16 = 3 };
+// storage kind of vectors
+enum VecKind { X_F64 = 0, X_F32 = 1 };
+
+constexpr int kWave = 64;             // wavefront width on CDNA
+constexpr int kSliceWaves = 4;        // slices (one per wave) per 256-thread workgroup
+constexpr int kRedThreads = 256;
+constexpr int kMaxRedBlocks = 1024;   // grid of the last-block reductions
+
+// Sliced ELL of a block matrix: one slice = 64 lanes = R = 64/B nodes x B components;
+// lane = r*B + c handles scalar row (node slice*R + r, component c).  For block slot k of
+// the slice, the value of column component cc for lane `ln` sits at
+// val[(k*B + cc)*64 + ln] and the column node of row r at col[k*R + r] (k counts from
+// sptr[slice]).  Padding slots hold value 0 and the row's own node as column.
+struct SellDev {
+  int32_t n = 0, B = 1, R = 64, nslices = 0;
+  int64_t slots = 0;
+  const int32_t* sptr = nullptr;    // nslices + 1
+  const int32_t* col = nullptr;     // slots * R
+  const void* val = nullptr;        // slots * B * 64 values of `kind`
+  const int8_t* rexp = nullptr;     // nslices * 64 power-of-two row exponents (F16 / BF16)
+  int kind = VK_F64;
+};
+
+// scalar CSR (transfer matrices); weights stored as float when every weight is exact in
+// FP32 (dyadic), else as double
+struct CsrDev {
+  int32_t nrows = 0, ncols = 0;
+  int64_t nnz = 0;
+  const int32_t* rowptr = nullptr;
+  const int32_t* col = nullptr;
+  const void* val = nullptr;
+  int f32 = 1;
+};
+
+// deterministic grid reduction: per-block partials, the last block to finish sums them
+struct RedDev {
+  double* partials = nullptr;       // >= grid size entries
+  unsigned* counter = nullptr;      // zero between reductions
+  double* out = nullptr;            // result
+  int sqrt_out = 0;                 // write sqrt(sum) instead of sum
+};
+
+// ------------------------------------------------------------------ launchers
+// y = A x (mode 0), y = b - A x (mode 1), y = M (b - A x) with M zeroing constrained
+// DoFs (mode 2); optional sum of squares of y into red.  xk / yk: vector kinds.
+hipError_t launch_spmv(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask,
+                       int xk, int yk, int mode, const RedDev* red, hipStream_t s);
+// x_out = x + omega S (b - A x); S in lane layout, same kind as the vectors
+hipError_t launch_sweep(const SellDev& A, const void* S, const void* b, const void* x, void* xo,
+                        double omega, int xk, hipStream_t s);
+// x_out = omega S b
+hipError_t launch_sweep0(const SellDev& A, const void* S, const void* b, void* xo, double omega,
+                         int xk, hipStream_t s);
+// d = M_c P~^T M_f r; mask_f may be NULL when r is already zero on constrained fine DoFs
+hipError_t launch_restrict(const CsrDev& R, int B, const void* r, void* d, const uint8_t* mask_c,
+                           const uint8_t* mask_f, int xk, hipStream_t s);
+// x += M_f P~ M_c y
+hipError_t launch_prolong(const CsrDev& P, int B, const void* y, void* x, const uint8_t* mask_f,
+                          const uint8_t* mask_c, int xk, hipStream_t s);
+// x = Ainv b with the FP64 inverse stored transposed; b / x of kind xk
+hipError_t launch_coarse_gemv(int n, const double* AinvT, const void* b, void* x, int xk, hipStream_t s);
+// Gauss-Jordan with partial pivoting on the n x 2n augmented matrix M = [A | I]
+// (row-major, FP64); writes the inverse transposed to AinvT; flag != 0 if singular
+hipError_t launch_coarse_invert(int n, double* M, double* AinvT, double* pivbuf, int* flag,
+                                hipStream_t s);
+// nodal block inverses of the diagonal blocks of A (FP64 SELL) into S (lane layout,
+// double or float per sk); flag != 0 if a block is singular
+hipError_t launch_block_invert(const SellDev& A, void* S, int sk, int* flag, hipStream_t s);
+
+// vector kernels (n elements)
+hipError_t launch_fill(int64_t n, void* y, int yk, double v, hipStream_t s);
+hipError_t launch_convert(int64_t n, const void* x, int xk, void* y, int yk, hipStream_t s);
+hipError_t launch_axpy(int64_t n, void* y, int yk, const void* x, int xk, double sign,
+                       const double* alpha, hipStream_t s);          // y += sign * (*alpha) * x
+hipError_t launch_scale_div(int64_t n, double* y, const double* x, const double* denom,
+                            hipStream_t s);                          // y = x / *denom (if != 0)
+hipError_t launch_dot(int64_t n, const double* a, const double* b, const RedDev& red, hipStream_t s);
+hipError_t launch_nrm2(int64_t n, const double* a, const RedDev& red, hipStream_t s);
+// x += sum_{i<k} y[i] Z_i, Z_i = Z + i*ldz of kind zk
+hipError_t launch_update_x(int64_t n, double* x, const void* Z, int zk, int64_t ldz, const double* y,
+                           int k, hipStream_t s);
+// Givens step j of GMRES on the (m+1) x m Hessenberg H (column-major, ld = m+1):
+// rotate column j by the previous rotations, form rotation j, update g.
+// st[0] = |g[j+1]|, st[1] = 1 if H[j+1][j] was 0 before the rotation
+hipError_t launch_givens(int j, int m, double* H, double* cs, double* sn, double* g, double* st,
+                         hipStream_t s);
+// y = H[:k,:k]^{-1} g[:k] (upper triangular)
+hipError_t launch_backsolve(int k, int m, const double* H, const double* g, double* y, hipStream_t s);
+// g = (beta, 0, ..., 0), beta read from the device
+hipError_t launch_init_g(int m, double* g, const double* beta, hipStream_t s);
+
+}  // namespace mgq1

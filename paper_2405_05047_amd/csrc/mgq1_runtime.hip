@@ -1,0 +1,855 @@
+// Host runtime and C ABI of libmgq1: hierarchy setup on the device, the V-cycle driver
+// (Algorithm "Geometric multigrid solver", Sec. 2.2), defect-correction and flexible
+// GMRES outer loops (Sec. 4.2), and the step-wise entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mgq1.h"
+#include "mgq1_internal.h"
+
+using namespace mgq1;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define MG_HIP(call)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) return fail(MG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------- host-side helpers
+struct HostLevel {
+  int32_t n = 0, B = 1;
+  int64_t nnzb = 0;
+  std::vector<int32_t> rowptr, col;
+  std::vector<double> val;
+  int32_t pc = 0;
+  std::vector<int32_t> prow, pcol;
+  std::vector<double> pval;
+  std::vector<uint8_t> mask;
+};
+
+template <class T>
+int fetch(std::vector<T>& dst, const T* src, size_t n, bool on_device) {
+  dst.resize(n);
+  if (n == 0) return MG_OK;
+  if (!src) return fail(MG_EINVAL, "null input array");
+  if (on_device) MG_HIP(hipMemcpy(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost));
+  else std::memcpy(dst.data(), src, n * sizeof(T));
+  return MG_OK;
+}
+
+int validate_host(const HostLevel& L, const HostLevel* C, int level) {
+  const std::string at = "level " + std::to_string(level) + ": ";
+  const int B = L.B;
+  if (L.n <= 0) return fail(MG_EINVAL, at + "n_nodes must be positive");
+  if (B < 1 || B > 8) return fail(MG_EINVAL, at + "block must be 1..8");
+  if (int64_t(L.n) * B >= (int64_t(1) << 31)) return fail(MG_EINVAL, at + "too many DoFs for int32 indices");
+  if (L.rowptr[0] != 0) return fail(MG_EINVAL, at + "rowptr[0] != 0");
+  for (int32_t i = 0; i < L.n; ++i)
+    if (L.rowptr[i + 1] < L.rowptr[i]) return fail(MG_EINVAL, at + "rowptr not monotone");
+  if (L.rowptr[L.n] != L.nnzb) return fail(MG_EINVAL, at + "rowptr[n] != nnzb");
+  for (int32_t i = 0; i < L.n; ++i) {
+    bool diag = false;
+    for (int32_t k = L.rowptr[i]; k < L.rowptr[i + 1]; ++k) {
+      const int32_t j = L.col[k];
+      if (j < 0 || j >= L.n) return fail(MG_EINVAL, at + "column index out of range");
+      if (k > L.rowptr[i] && L.col[k - 1] >= j) return fail(MG_EINVAL, at + "columns not sorted/unique");
+      diag |= (j == i);
+      for (int z = 0; z < B * B; ++z) {
+        const double v = L.val[size_t(k) * B * B + z];
+        if (!std::isfinite(v)) return fail(MG_EINVAL, at + "non-finite matrix value");
+        const int c = z / B, cc = z % B;
+        const bool mr = L.mask[size_t(i) * B + c], mc = L.mask[size_t(j) * B + cc];
+        if (mr || mc) {
+          const double want = (i == j && c == cc && mr) ? 1.0 : 0.0;
+          if (v != want) return fail(MG_EINVAL, at + "constrained DoF row/column is not an identity row/column");
+        }
+      }
+    }
+    if (!diag) return fail(MG_EINVAL, at + "missing diagonal block");
+  }
+  if (C) {
+    if (C->B != B) return fail(MG_EINVAL, at + "block size differs between levels");
+    if (L.pc != C->n) return fail(MG_EINVAL, at + "p_cols != n_nodes of the coarser level");
+    if (L.prow.size() != size_t(L.n) + 1 || L.prow[0] != 0) return fail(MG_EINVAL, at + "bad P rowptr");
+    for (int32_t i = 0; i < L.n; ++i) {
+      if (L.prow[i + 1] < L.prow[i]) return fail(MG_EINVAL, at + "P rowptr not monotone");
+      for (int32_t k = L.prow[i]; k < L.prow[i + 1]; ++k) {
+        const int32_t j = L.pcol[k];
+        if (j < 0 || j >= C->n) return fail(MG_EINVAL, at + "P column out of range");
+        if (k > L.prow[i] && L.pcol[k - 1] >= j) return fail(MG_EINVAL, at + "P columns not sorted/unique");
+        if (!std::isfinite(L.pval[k])) return fail(MG_EINVAL, at + "non-finite P weight");
+      }
+    }
+  }
+  return MG_OK;
+}
+
+int load_level(const mg_level_in& in, bool on_dev, bool want_p, HostLevel& L) {
+  L.n = in.n_nodes;
+  L.B = in.block;
+  L.nnzb = in.nnzb;
+  if (L.n <= 0 || L.B < 1 || L.B > 8 || L.nnzb < L.n) return fail(MG_EINVAL, "bad level sizes");
+  int rc;
+  if ((rc = fetch(L.rowptr, in.A_rowptr, size_t(L.n) + 1, on_dev))) return rc;
+  if ((rc = fetch(L.col, in.A_col, size_t(L.nnzb), on_dev))) return rc;
+  if ((rc = fetch(L.val, in.A_val, size_t(L.nnzb) * L.B * L.B, on_dev))) return rc;
+  if ((rc = fetch(L.mask, in.dof_mask, size_t(L.n) * L.B, on_dev))) return rc;
+  if (want_p) {
+    L.pc = in.p_cols;
+    if (!in.P_rowptr) return fail(MG_EINVAL, "missing P on a level above 0");
+    if ((rc = fetch(L.prow, in.P_rowptr, size_t(L.n) + 1, on_dev))) return rc;
+    if (L.prow[L.n] != in.p_nnz || in.p_nnz < 0) return fail(MG_EINVAL, "P rowptr[n] != p_nnz");
+    if ((rc = fetch(L.pcol, in.P_col, size_t(in.p_nnz), on_dev))) return rc;
+    if ((rc = fetch(L.pval, in.P_val, size_t(in.p_nnz), on_dev))) return rc;
+  }
+  return MG_OK;
+}
+
+// smallest e with max |a| <= 2^e (0 for a zero row)
+int row_exponent(double mx) {
+  if (mx == 0.0) return 0;
+  int e;
+  const double m = std::frexp(mx, &e);
+  return m == 0.5 ? e - 1 : e;
+}
+
+// round an FP64 value to FP16 (RNE, straight from FP64) and return the bits
+uint16_t to_f16_bits(double v) {
+  if (v == 0.0) return std::signbit(v) ? 0x8000 : 0;
+  const double a = std::fabs(v);
+  double r;
+  if (a >= 0x1p-14) {
+    int e;
+    const double m = std::frexp(a, &e);            // a = m 2^e, m in [0.5, 1)
+    r = std::ldexp(std::nearbyint(std::ldexp(m, 11)), e - 11);
+  } else {
+    r = std::ldexp(std::nearbyint(std::ldexp(a, 24)), -24);
+  }
+  // r is exactly representable in FP16; build its bits
+  uint16_t bits;
+  if (r == 0.0) {
+    bits = 0;
+  } else if (r < 0x1p-14) {
+    bits = uint16_t(std::ldexp(r, 24));
+  } else {
+    int e;
+    const double m = std::frexp(r, &e);
+    const int E = e - 1 + 15;                       // r = 1.f 2^(e-1)
+    if (E >= 31) bits = 0x7c00;                      // overflow -> inf (not reached for |q| <= 1)
+    else bits = uint16_t((E << 10) | (uint32_t(std::ldexp(m, 11)) & 0x3ff));
+  }
+  return std::signbit(v) ? uint16_t(bits | 0x8000) : bits;
+}
+
+uint16_t to_bf16_bits(double v) {
+  if (v == 0.0) return std::signbit(v) ? 0x8000 : 0;
+  int e;
+  const double m = std::frexp(v, &e);
+  const double r = std::ldexp(std::nearbyint(std::ldexp(m, 8)), e - 8);
+  const float f = float(r);                         // exact
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return uint16_t(u >> 16);
+}
+
+struct HostSell {
+  int32_t n = 0, B = 1, R = 64, nslices = 0;
+  int64_t slots = 0;
+  std::vector<int32_t> sptr, col;
+  std::vector<double> val;                          // slots * B * 64
+  std::vector<int8_t> rexp;                         // nslices * 64
+};
+
+HostSell build_sell(const HostLevel& L) {
+  HostSell S;
+  S.n = L.n;
+  S.B = L.B;
+  S.R = kWave / L.B;
+  S.nslices = (L.n + S.R - 1) / S.R;
+  S.sptr.assign(size_t(S.nslices) + 1, 0);
+  for (int32_t s = 0; s < S.nslices; ++s) {
+    int32_t w = 0;
+    for (int r = 0; r < S.R; ++r) {
+      const int64_t i = int64_t(s) * S.R + r;
+      if (i < L.n) w = std::max(w, L.rowptr[i + 1] - L.rowptr[i]);
+    }
+    S.sptr[s + 1] = S.sptr[s] + w;
+  }
+  S.slots = S.sptr[S.nslices];
+  const int B = L.B;
+  S.col.assign(size_t(S.slots) * S.R, 0);
+  S.val.assign(size_t(S.slots) * B * kWave, 0.0);
+  S.rexp.assign(size_t(S.nslices) * kWave, 0);
+  for (int32_t s = 0; s < S.nslices; ++s) {
+    const int32_t w = S.sptr[s + 1] - S.sptr[s];
+    for (int r = 0; r < S.R; ++r) {
+      const int64_t i = int64_t(s) * S.R + r;
+      if (i >= L.n) continue;
+      const int32_t len = L.rowptr[i + 1] - L.rowptr[i];
+      std::vector<double> mx(B, 0.0);
+      for (int32_t k = 0; k < w; ++k) {
+        const int64_t slot = int64_t(S.sptr[s]) + k;
+        if (k < len) {
+          const int64_t src = int64_t(L.rowptr[i]) + k;
+          S.col[slot * S.R + r] = L.col[src];
+          for (int c = 0; c < B; ++c)
+            for (int cc = 0; cc < B; ++cc) {
+              const double v = L.val[size_t(src) * B * B + c * B + cc];
+              S.val[(slot * B + cc) * kWave + r * B + c] = v;
+              mx[c] = std::max(mx[c], std::fabs(v));
+            }
+        } else {
+          S.col[slot * S.R + r] = int32_t(i);
+        }
+      }
+      for (int c = 0; c < B; ++c) S.rexp[size_t(s) * kWave + r * B + c] = int8_t(row_exponent(mx[c]));
+    }
+  }
+  return S;
+}
+
+struct CsrHost {
+  int32_t nrows = 0, ncols = 0;
+  std::vector<int32_t> rowptr, col;
+  std::vector<double> val;
+};
+
+CsrHost transpose(int32_t nrows, int32_t ncols, const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
+                  const std::vector<double>& v) {
+  CsrHost T;
+  T.nrows = ncols;
+  T.ncols = nrows;
+  T.rowptr.assign(size_t(ncols) + 1, 0);
+  for (int32_t c : ci) ++T.rowptr[c + 1];
+  for (int32_t j = 0; j < ncols; ++j) T.rowptr[j + 1] += T.rowptr[j];
+  T.col.resize(ci.size());
+  T.val.resize(ci.size());
+  std::vector<int32_t> fill(T.rowptr.begin(), T.rowptr.end() - 1);
+  for (int32_t i = 0; i < nrows; ++i)
+    for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int32_t q = fill[ci[k]]++;
+      T.col[q] = i;
+      T.val[q] = v[k];
+    }
+  return T;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- handle
+struct LevelDev {
+  int32_t n = 0, B = 1;
+  int64_t N = 0, nnzb = 0;
+  SellDev A64;            // FP64 operator (all levels in FP64 mode; finest level in mixed mode)
+  SellDev Ac;             // operator used inside the cycle (== A64 in FP64 mode)
+  void* S = nullptr;      // smoother blocks, lane layout, cycle precision
+  uint8_t* mask = nullptr;
+  CsrDev P, R;            // from level l-1 (l >= 1)
+  void *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;   // cycle vectors
+};
+
+struct mg_handle {
+  mg_config cfg{};
+  int L = 0;
+  int xk = X_F64;         // vector kind inside the cycle
+  std::vector<LevelDev> lv;
+  double* AinvT = nullptr;
+  int n0 = 0;
+  // outer loop
+  double* V = nullptr;    // (m+1) x N_L FP64
+  void* Z = nullptr;      // m x N_L, cycle precision
+  void* e = nullptr;      // correction (cycle precision), N_L
+  double* rout = nullptr; // FP64 outer residual, N_L
+  void* bcyc = nullptr;   // cycle-precision copy of the cycle input (mixed mode)
+  double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
+  double* dsc = nullptr;  // device scalars: [0] norm, [1] one, [2..3] givens status
+  double* partials = nullptr;
+  unsigned* counter = nullptr;
+  int* dflag = nullptr;
+  double* hs = nullptr;   // pinned host scalars
+  std::vector<void*> allocs;
+  ~mg_handle() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (hs) (void)hipHostFree(hs);
+  }
+};
+
+namespace {
+
+template <class T>
+int dalloc(mg_handle* h, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return fail(MG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  h->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return MG_OK;
+}
+
+template <class T>
+int upload(mg_handle* h, T** p, const std::vector<T>& src, hipStream_t s) {
+  int rc = dalloc(h, p, src.size());
+  if (rc) return rc;
+  if (!src.empty()) MG_HIP(hipMemcpyAsync(*p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return MG_OK;
+}
+
+size_t xsize(int xk) { return xk == X_F64 ? 8 : 4; }
+
+int upload_sell(mg_handle* h, const HostSell& S, int kind, SellDev& D, hipStream_t s) {
+  D.n = S.n;
+  D.B = S.B;
+  D.R = S.R;
+  D.nslices = S.nslices;
+  D.slots = S.slots;
+  D.kind = kind;
+  int rc;
+  int32_t* sp;
+  int32_t* cl;
+  if ((rc = upload(h, &sp, S.sptr, s))) return rc;
+  if ((rc = upload(h, &cl, S.col, s))) return rc;
+  D.sptr = sp;
+  D.col = cl;
+  const size_t nv = S.val.size();
+  if (kind == VK_F64) {
+    double* v;
+    if ((rc = upload(h, &v, S.val, s))) return rc;
+    D.val = v;
+  } else if (kind == VK_F32) {
+    std::vector<float> f(nv);
+    for (size_t i = 0; i < nv; ++i) f[i] = float(S.val[i]);
+    float* v;
+    if ((rc = upload(h, &v, f, s))) return rc;
+    MG_HIP(hipStreamSynchronize(s));
+    D.val = v;
+  } else {
+    std::vector<uint16_t> q(nv);
+    for (int32_t sl = 0; sl < S.nslices; ++sl)
+      for (int32_t k = S.sptr[sl]; k < S.sptr[sl + 1]; ++k)
+        for (int cc = 0; cc < S.B; ++cc)
+          for (int ln = 0; ln < kWave; ++ln) {
+            const size_t idx = (size_t(k) * S.B + cc) * kWave + ln;
+            const double sc = std::ldexp(S.val[idx], -int(S.rexp[size_t(sl) * kWave + ln]));
+            q[idx] = kind == VK_F16 ? to_f16_bits(sc) : to_bf16_bits(sc);
+          }
+    uint16_t* v;
+    if ((rc = upload(h, &v, q, s))) return rc;
+    int8_t* re;
+    if ((rc = upload(h, &re, S.rexp, s))) return rc;
+    MG_HIP(hipStreamSynchronize(s));
+    D.val = v;
+    D.rexp = re;
+  }
+  return MG_OK;
+}
+
+int upload_csr(mg_handle* h, const CsrHost& C, CsrDev& D, hipStream_t s) {
+  D.nrows = C.nrows;
+  D.ncols = C.ncols;
+  D.nnz = int64_t(C.col.size());
+  bool exact = true;
+  for (double w : C.val) exact = exact && (double(float(w)) == w);
+  D.f32 = exact;
+  int rc;
+  int32_t *rp, *cl;
+  if ((rc = upload(h, &rp, C.rowptr, s))) return rc;
+  if ((rc = upload(h, &cl, C.col, s))) return rc;
+  D.rowptr = rp;
+  D.col = cl;
+  if (exact) {
+    std::vector<float> f(C.val.begin(), C.val.end());
+    float* v;
+    if ((rc = upload(h, &v, f, s))) return rc;
+    MG_HIP(hipStreamSynchronize(s));
+    D.val = v;
+  } else {
+    double* v;
+    if ((rc = upload(h, &v, C.val, s))) return rc;
+    D.val = v;
+  }
+  return MG_OK;
+}
+
+RedDev red_of(mg_handle* h, double* out) {
+  RedDev r;
+  r.partials = h->partials;
+  r.counter = h->counter;
+  r.out = out;
+  return r;
+}
+
+// ---------------------------------------------------------------- V-cycle
+int smooth_level(mg_handle* h, int l, const void* b, void*& cur, void*& other, int sweeps, hipStream_t s) {
+  LevelDev& L = h->lv[l];
+  for (int q = 0; q < sweeps; ++q) {
+    MG_HIP(launch_sweep(L.Ac, L.S, b, cur, other, h->cfg.omega, h->xk, s));
+    std::swap(cur, other);
+  }
+  return MG_OK;
+}
+
+// x = GMG(L, 0, b) with b, x in cycle precision; x must not alias b
+int vcycle_cycle(mg_handle* h, const void* bL, void* xL, hipStream_t s) {
+  const int L = h->L;
+  const mg_config& c = h->cfg;
+  std::vector<const void*> bb(L + 1);
+  std::vector<void*> cur(L + 1), oth(L + 1);
+  for (int l = 0; l <= L; ++l) bb[l] = h->lv[l].b;
+  bb[L] = bL;
+  // choose the first buffer so that the ping-pong ends in the level's own x (or xL)
+  auto first_buffers = [&](int l, int pingpongs) {
+    void* own = (l == L) ? xL : h->lv[l].x;
+    void* tmp = h->lv[l].t;
+    if (pingpongs % 2 == 0) { cur[l] = own; oth[l] = tmp; }
+    else { cur[l] = tmp; oth[l] = own; }
+  };
+  for (int l = L; l >= 1; --l) {
+    LevelDev& Lv = h->lv[l];
+    const int pre_pp = c.nu1 >= 1 ? c.nu1 - 1 : 0;
+    first_buffers(l, pre_pp + c.nu2);
+    if (c.nu1 >= 1) {
+      MG_HIP(launch_sweep0(Lv.Ac, Lv.S, bb[l], cur[l], c.omega, h->xk, s));
+      int rc = smooth_level(h, l, bb[l], cur[l], oth[l], c.nu1 - 1, s);
+      if (rc) return rc;
+    } else {
+      MG_HIP(launch_fill(Lv.N, cur[l], h->xk, 0.0, s));
+    }
+    MG_HIP(launch_spmv(Lv.Ac, bb[l], cur[l], Lv.r, Lv.mask, h->xk, h->xk, 2, nullptr, s));
+    MG_HIP(launch_restrict(Lv.R, Lv.B, Lv.r, h->lv[l - 1].b, h->lv[l - 1].mask, nullptr, h->xk, s));
+  }
+  LevelDev& C0 = h->lv[0];
+  void* x0 = (L == 0) ? xL : C0.x;
+  if (c.coarse_mode == MG_COARSE_EXACT) {
+    MG_HIP(launch_coarse_gemv(h->n0, h->AinvT, bb[0], x0, h->xk, s));
+  } else {
+    const int k = std::max(1, c.coarse_sweeps);
+    void* cu = ((k - 1) % 2 == 0) ? x0 : C0.t;
+    void* ot = ((k - 1) % 2 == 0) ? C0.t : x0;
+    MG_HIP(launch_sweep0(C0.Ac, C0.S, bb[0], cu, c.omega, h->xk, s));
+    int rc = smooth_level(h, 0, bb[0], cu, ot, k - 1, s);
+    if (rc) return rc;
+  }
+  for (int l = 1; l <= L; ++l) {
+    LevelDev& Lv = h->lv[l];
+    const void* y = (l - 1 == 0) ? x0 : cur[l - 1];
+    MG_HIP(launch_prolong(Lv.P, Lv.B, y, cur[l], Lv.mask, h->lv[l - 1].mask, h->xk, s));
+    int rc = smooth_level(h, l, bb[l], cur[l], oth[l], c.nu2, s);
+    if (rc) return rc;
+  }
+  return MG_OK;
+}
+
+// z = V(v) with v FP64 (finest), z in cycle precision
+int precond(mg_handle* h, const double* v, void* z, hipStream_t s) {
+  if (h->xk == X_F64) return vcycle_cycle(h, v, z, s);
+  MG_HIP(launch_convert(h->lv[h->L].N, v, X_F64, h->bcyc, h->xk, s));
+  return vcycle_cycle(h, h->bcyc, z, s);
+}
+
+int read_scalars(mg_handle* h, const double* d, int k, hipStream_t s) {
+  MG_HIP(hipMemcpyAsync(h->hs, d, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  return MG_OK;
+}
+
+// r = b - A x, h->hs[0] = ||r||
+int outer_defect(mg_handle* h, const double* b, const double* x, hipStream_t s) {
+  LevelDev& T = h->lv[h->L];
+  RedDev red = red_of(h, h->dsc + 0);
+  red.sqrt_out = 1;
+  MG_HIP(launch_spmv(T.A64, b, x, h->rout, nullptr, X_F64, X_F64, 1, &red, s));
+  return read_scalars(h, h->dsc, 1, s);
+}
+
+int solve_impl(mg_handle* h, const double* b, double* x, mg_solve_stats* st, void* stream, int fixed) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const mg_config& c = h->cfg;
+  LevelDev& T = h->lv[h->L];
+  const int64_t N = T.N;
+  mg_solve_stats S{};
+  int rc;
+  // ||b||
+  {
+    RedDev red = red_of(h, h->dsc + 0);
+    MG_HIP(launch_nrm2(N, b, red, s));
+    if ((rc = read_scalars(h, h->dsc, 1, s))) return rc;
+  }
+  const double bn = h->hs[0];
+  const double tol = c.rtol * bn;
+  const int limit = fixed > 0 ? fixed : c.maxit;
+  if ((rc = outer_defect(h, b, x, s))) return rc;
+  double beta = h->hs[0];
+  S.res0 = beta;
+  int status = MG_OK;
+  if (c.outer == MG_OUTER_IR) {
+    while (true) {
+      if (!std::isfinite(beta) || beta > 1e6 * std::max(S.res0, 1e-300)) { status = MG_ENUMERIC; break; }
+      if (fixed <= 0 && beta <= tol) { S.converged = 1; break; }
+      if (S.iters >= limit) { status = fixed > 0 ? MG_OK : MG_ENOCONV; break; }
+      if ((rc = precond(h, h->rout, h->e, s))) return rc;
+      MG_HIP(launch_axpy(N, x, X_F64, h->e, h->xk, 1.0, h->dsc + 1, s));
+      ++S.iters;
+      if ((rc = outer_defect(h, b, x, s))) return rc;
+      beta = h->hs[0];
+    }
+  } else {
+    const int m = c.gmres_m;
+    const size_t zs = xsize(h->xk);
+    while (true) {
+      if (!std::isfinite(beta) || beta > 1e6 * std::max(S.res0, 1e-300)) { status = MG_ENUMERIC; break; }
+      if (fixed <= 0 && beta <= tol) { S.converged = 1; break; }
+      if (S.iters >= limit || beta == 0.0) { status = (fixed > 0 || beta == 0.0) ? MG_OK : MG_ENOCONV; break; }
+      MG_HIP(launch_scale_div(N, h->V, h->rout, h->dsc + 0, s));
+      MG_HIP(launch_init_g(m, h->g, h->dsc + 0, s));
+      int k = 0;
+      for (int j = 0; j < m; ++j) {
+        double* vj = h->V + int64_t(j) * N;
+        double* w = h->V + int64_t(j + 1) * N;
+        void* zj = static_cast<char*>(h->Z) + size_t(j) * N * zs;
+        if ((rc = precond(h, vj, zj, s))) return rc;
+        ++S.iters;
+        MG_HIP(launch_spmv(T.A64, nullptr, zj, w, nullptr, h->xk, X_F64, 0, nullptr, s));
+        double* Hj = h->H + int64_t(j) * (m + 1);
+        for (int i = 0; i <= j; ++i) {           // modified Gram-Schmidt
+          const double* vi = h->V + int64_t(i) * N;
+          MG_HIP(launch_dot(N, w, vi, red_of(h, Hj + i), s));
+          MG_HIP(launch_axpy(N, w, X_F64, vi, X_F64, -1.0, Hj + i, s));
+        }
+        {
+          RedDev red = red_of(h, Hj + j + 1);
+          MG_HIP(launch_nrm2(N, w, red, s));
+        }
+        MG_HIP(launch_scale_div(N, w, w, Hj + j + 1, s));
+        MG_HIP(launch_givens(j, m, h->H, h->cs, h->sn, h->g, h->dsc + 2, s));
+        if ((rc = read_scalars(h, h->dsc + 2, 2, s))) return rc;
+        k = j + 1;
+        const double est = h->hs[0];
+        const bool breakdown = h->hs[1] != 0.0;
+        if (!std::isfinite(est)) { status = MG_ENUMERIC; break; }
+        if (breakdown || S.iters >= limit) break;
+        if (fixed <= 0 && est <= tol) break;
+      }
+      if (status == MG_ENUMERIC) break;
+      MG_HIP(launch_backsolve(k, m, h->H, h->g, h->y, s));
+      MG_HIP(launch_update_x(N, x, h->Z, h->xk, N, h->y, k, s));
+      ++S.restarts;
+      if ((rc = outer_defect(h, b, x, s))) return rc;
+      beta = h->hs[0];
+    }
+    if (status == MG_OK && fixed <= 0 && beta > tol) status = MG_ENOCONV;
+  }
+  S.res_final = beta;
+  S.converged = (beta <= tol) ? 1 : 0;
+  if (status == MG_OK && fixed <= 0 && !S.converged) status = MG_ENOCONV;
+  S.status = status;
+  MG_HIP(hipStreamSynchronize(s));
+  S.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (st) *st = S;
+  if (status == MG_ENUMERIC) return fail(MG_ENUMERIC, "non-finite or diverging residual");
+  if (status == MG_ENOCONV) return fail(MG_ENOCONV, "maxit reached before rtol");
+  return MG_OK;
+}
+
+int check_level(const mg_handle* h, int level) {
+  if (!h) return fail(MG_EINVAL, "null handle");
+  if (level < 0 || level > h->L) return fail(MG_EINVAL, "level out of range");
+  if (h->xk != X_F64) return fail(MG_EUNSUPPORTED, "step-wise entry points need an FP64 handle");
+  return MG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+int mg_validate_level(const mg_level_in* lv, const mg_level_in* coarser) {
+  if (!lv) return fail(MG_EINVAL, "null level");
+  HostLevel L, C;
+  int rc = load_level(*lv, false, coarser != nullptr, L);
+  if (rc) return rc;
+  if (coarser) {
+    rc = load_level(*coarser, false, false, C);
+    if (rc) return rc;
+  }
+  return validate_host(L, coarser ? &C : nullptr, coarser ? 1 : 0);
+}
+
+int mg_setup_hierarchy(const mg_level_in* lv, int32_t n_levels, const mg_config* cfg, int32_t inputs_on_device,
+                       void* stream, mg_handle** out) {
+  if (!lv || !cfg || !out || n_levels < 1) return fail(MG_EINVAL, "null argument or no levels");
+  *out = nullptr;
+  const mg_config& c = *cfg;
+  if (!(c.omega > 0.0) || c.nu1 < 0 || c.nu2 < 0 || c.nu1 + c.nu2 < 1 || c.gmres_m < 1 || c.gmres_m > 64 ||
+      c.maxit < 0 || !(c.rtol >= 0.0) || c.precision < MG_PREC_FP64 || c.precision > MG_PREC_FP32_BF16VAL ||
+      (c.outer != MG_OUTER_IR && c.outer != MG_OUTER_FGMRES) ||
+      (c.coarse_mode != MG_COARSE_EXACT && c.coarse_mode != MG_COARSE_SMOOTH))
+    return fail(MG_EINVAL, "invalid configuration");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<HostLevel> H(n_levels);
+  try {
+    for (int l = 0; l < n_levels; ++l) {
+      int rc = load_level(lv[l], inputs_on_device != 0, l > 0, H[l]);
+      if (rc) return rc;
+      rc = validate_host(H[l], l > 0 ? &H[l - 1] : nullptr, l);
+      if (rc) return rc;
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(MG_ENOMEM, "host allocation failed");
+  }
+  const int B = H[0].B;
+  if (B > 4) return fail(MG_EUNSUPPORTED, "block sizes above 4 are not implemented");
+  if (int64_t(H[0].n) * B > 4096) return fail(MG_EUNSUPPORTED, "coarse problem above 4096 DoFs");
+  mg_handle* h = new (std::nothrow) mg_handle();
+  if (!h) return fail(MG_ENOMEM, "host allocation failed");
+  h->cfg = c;
+  h->L = n_levels - 1;
+  h->xk = c.precision == MG_PREC_FP64 ? X_F64 : X_F32;
+  h->lv.resize(n_levels);
+  auto bail = [&](int rc) {
+    delete h;
+    return rc;
+  };
+  int rc;
+  int* flag;
+  if ((rc = dalloc(h, &flag, 1))) return bail(rc);
+  h->dflag = flag;
+  MG_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+  try {
+    for (int l = 0; l < n_levels; ++l) {
+      LevelDev& D = h->lv[l];
+      const HostLevel& L = H[l];
+      D.n = L.n;
+      D.B = L.B;
+      D.N = int64_t(L.n) * L.B;
+      D.nnzb = L.nnzb;
+      HostSell S = build_sell(L);
+      if ((rc = upload_sell(h, S, VK_F64, D.A64, s))) return bail(rc);
+      const int kind = c.precision == MG_PREC_FP64 ? VK_F64
+                       : c.precision == MG_PREC_FP32 ? VK_F32
+                       : c.precision == MG_PREC_FP32_F16VAL ? VK_F16 : VK_BF16;
+      if (kind == VK_F64) D.Ac = D.A64;
+      else if ((rc = upload_sell(h, S, kind, D.Ac, s))) return bail(rc);
+      const size_t sblk = size_t(S.nslices) * B * kWave;
+      if ((rc = dalloc(h, reinterpret_cast<char**>(&D.S), sblk * xsize(h->xk)))) return bail(rc);
+      MG_HIP(launch_fill(int64_t(sblk), D.S, h->xk, 0.0, s));
+      MG_HIP(launch_block_invert(D.A64, D.S, h->xk, flag, s));
+      if ((rc = upload(h, &D.mask, L.mask, s))) return bail(rc);
+      if (l > 0) {
+        CsrHost P;
+        P.nrows = L.n;
+        P.ncols = L.pc;
+        P.rowptr = L.prow;
+        P.col = L.pcol;
+        P.val = L.pval;
+        if ((rc = upload_csr(h, P, D.P, s))) return bail(rc);
+        CsrHost R = transpose(L.n, L.pc, L.prow, L.pcol, L.pval);
+        if ((rc = upload_csr(h, R, D.R, s))) return bail(rc);
+      }
+      const size_t vb = size_t(D.N) * xsize(h->xk);
+      char* p;
+      for (void** v : {&D.x, &D.b, &D.r, &D.t}) {
+        if ((rc = dalloc(h, &p, vb))) return bail(rc);
+        *v = p;
+      }
+      // mixed mode: the FP64 operator is only needed on the finest level
+      MG_HIP(hipStreamSynchronize(s));
+    }
+    // coarse inverse
+    {
+      const HostLevel& C0 = H[0];
+      const int n0 = C0.n * B;
+      h->n0 = n0;
+      std::vector<double> M(size_t(n0) * 2 * n0, 0.0);
+      for (int32_t i = 0; i < C0.n; ++i)
+        for (int32_t k = C0.rowptr[i]; k < C0.rowptr[i + 1]; ++k)
+          for (int c1 = 0; c1 < B; ++c1)
+            for (int c2 = 0; c2 < B; ++c2)
+              M[size_t(i * B + c1) * 2 * n0 + size_t(C0.col[k]) * B + c2] = C0.val[size_t(k) * B * B + c1 * B + c2];
+      for (int i = 0; i < n0; ++i) M[size_t(i) * 2 * n0 + n0 + i] = 1.0;
+      double *dM, *piv;
+      if ((rc = upload(h, &dM, M, s))) return bail(rc);
+      MG_HIP(hipStreamSynchronize(s));
+      if ((rc = dalloc(h, &piv, size_t(2) * n0))) return bail(rc);
+      if ((rc = dalloc(h, &h->AinvT, size_t(n0) * n0))) return bail(rc);
+      MG_HIP(launch_coarse_invert(n0, dM, h->AinvT, piv, flag, s));
+    }
+    int hflag = 0;
+    MG_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    if (hflag) return bail(fail(MG_ESINGULAR, "singular nodal diagonal block or coarse matrix"));
+    // outer-loop storage
+    const int64_t N = h->lv[h->L].N;
+    const int m = c.gmres_m;
+    if ((rc = dalloc(h, &h->rout, size_t(N)))) return bail(rc);
+    char* p;
+    if ((rc = dalloc(h, &p, size_t(N) * xsize(h->xk)))) return bail(rc);
+    h->e = p;
+    if ((rc = dalloc(h, &p, size_t(N) * xsize(h->xk)))) return bail(rc);
+    h->bcyc = p;
+    if (c.outer == MG_OUTER_FGMRES) {
+      if ((rc = dalloc(h, &h->V, size_t(m + 1) * N))) return bail(rc);
+      if ((rc = dalloc(h, &p, size_t(m) * N * xsize(h->xk)))) return bail(rc);
+      h->Z = p;
+    }
+    if ((rc = dalloc(h, &h->H, size_t(m + 1) * m))) return bail(rc);
+    if ((rc = dalloc(h, &h->cs, size_t(m)))) return bail(rc);
+    if ((rc = dalloc(h, &h->sn, size_t(m)))) return bail(rc);
+    if ((rc = dalloc(h, &h->g, size_t(m) + 1))) return bail(rc);
+    if ((rc = dalloc(h, &h->y, size_t(m)))) return bail(rc);
+    if ((rc = dalloc(h, &h->dsc, 8))) return bail(rc);
+    MG_HIP(launch_fill(8, h->dsc, X_F64, 0.0, s));
+    MG_HIP(launch_fill(1, h->dsc + 1, X_F64, 1.0, s));
+    int64_t maxgrid = kMaxRedBlocks;
+    for (const LevelDev& D : h->lv) maxgrid = std::max<int64_t>(maxgrid, (D.A64.nslices + kSliceWaves - 1) / kSliceWaves);
+    if ((rc = dalloc(h, &h->partials, size_t(maxgrid)))) return bail(rc);
+    if ((rc = dalloc(h, &h->counter, 1))) return bail(rc);
+    MG_HIP(hipMemsetAsync(h->counter, 0, sizeof(unsigned), s));
+    MG_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hs), 16 * sizeof(double), hipHostMallocDefault));
+    MG_HIP(hipStreamSynchronize(s));
+  } catch (const std::bad_alloc&) {
+    return bail(fail(MG_ENOMEM, "host allocation failed"));
+  }
+  *out = h;
+  return MG_OK;
+}
+
+int mg_vcycle(mg_handle* h, const double* b, double* x, void* stream) {
+  if (!h || !b || !x) return fail(MG_EINVAL, "null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (h->xk == X_F64) return vcycle_cycle(h, b, x, s);
+  int rc = precond(h, b, h->e, s);
+  if (rc) return rc;
+  MG_HIP(launch_convert(h->lv[h->L].N, h->e, h->xk, x, X_F64, s));
+  return MG_OK;
+}
+
+int mg_solve(mg_handle* h, const double* b, double* x, mg_solve_stats* st, void* stream) {
+  if (!h || !b || !x) return fail(MG_EINVAL, "null argument");
+  return solve_impl(h, b, x, st, stream, 0);
+}
+
+int mg_solve_fixed(mg_handle* h, const double* b, double* x, int32_t iters, mg_solve_stats* st, void* stream) {
+  if (!h || !b || !x || iters < 1) return fail(MG_EINVAL, "null argument or iters < 1");
+  return solve_impl(h, b, x, st, stream, iters);
+}
+
+int mg_level_defect(mg_handle* h, int32_t level, const double* b, const double* x, double* r, int32_t masked,
+                    void* stream) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  LevelDev& L = h->lv[level];
+  MG_HIP(launch_spmv(L.A64, b, x, r, L.mask, X_F64, X_F64, masked ? 2 : 1, nullptr, static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
+int mg_level_spmv(mg_handle* h, int32_t level, const double* x, double* y, void* stream) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  LevelDev& L = h->lv[level];
+  MG_HIP(launch_spmv(L.A64, nullptr, x, y, nullptr, X_F64, X_F64, 0, nullptr, static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
+int mg_level_sweep(mg_handle* h, int32_t level, const double* b, const double* x, double* x_out, void* stream) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (x == x_out) return fail(MG_EINVAL, "sweep output must not alias its input");
+  LevelDev& L = h->lv[level];
+  MG_HIP(launch_sweep(L.Ac, L.S, b, x, x_out, h->cfg.omega, X_F64, static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
+int mg_level_sweep0(mg_handle* h, int32_t level, const double* b, double* x_out, void* stream) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  LevelDev& L = h->lv[level];
+  MG_HIP(launch_sweep0(L.Ac, L.S, b, x_out, h->cfg.omega, X_F64, static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
+int mg_level_restrict(mg_handle* h, int32_t level, const double* r_fine, double* d_coarse, void* stream) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (level < 1) return fail(MG_EINVAL, "restriction needs level >= 1");
+  LevelDev& L = h->lv[level];
+  MG_HIP(launch_restrict(L.R, L.B, r_fine, d_coarse, h->lv[level - 1].mask, L.mask, X_F64,
+                         static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
+int mg_level_prolong(mg_handle* h, int32_t level, const double* y_coarse, double* x_fine, void* stream) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (level < 1) return fail(MG_EINVAL, "prolongation needs level >= 1");
+  LevelDev& L = h->lv[level];
+  MG_HIP(launch_prolong(L.P, L.B, y_coarse, x_fine, L.mask, h->lv[level - 1].mask, X_F64,
+                        static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
+int mg_coarse_solve(mg_handle* h, const double* b, double* x, void* stream) {
+  int rc = check_level(h, 0);
+  if (rc) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (h->cfg.coarse_mode == MG_COARSE_EXACT) {
+    MG_HIP(launch_coarse_gemv(h->n0, h->AinvT, b, x, X_F64, s));
+    return MG_OK;
+  }
+  LevelDev& C0 = h->lv[0];
+  const int k = std::max(1, h->cfg.coarse_sweeps);
+  void* cu = ((k - 1) % 2 == 0) ? static_cast<void*>(x) : C0.t;
+  void* ot = ((k - 1) % 2 == 0) ? C0.t : static_cast<void*>(x);
+  MG_HIP(launch_sweep0(C0.Ac, C0.S, b, cu, h->cfg.omega, X_F64, s));
+  return smooth_level(h, 0, b, cu, ot, k - 1, s);
+}
+
+int mg_level_info(const mg_handle* h, int32_t level, int32_t* n_nodes, int32_t* block, int64_t* nnzb) {
+  if (!h || level < 0 || level > h->L) return fail(MG_EINVAL, "bad handle or level");
+  const LevelDev& L = h->lv[level];
+  if (n_nodes) *n_nodes = L.n;
+  if (block) *block = L.B;
+  if (nnzb) *nnzb = L.nnzb;
+  return MG_OK;
+}
+
+int32_t mg_num_levels(const mg_handle* h) { return h ? h->L + 1 : 0; }
+
+void mg_destroy(mg_handle* h) { delete h; }
+
+const char* mg_status_string(int status) {
+  switch (status) {
+    case MG_OK: return "ok";
+    case MG_EINVAL: return "invalid argument or malformed input";
+    case MG_ENOMEM: return "out of memory";
+    case MG_EDEVICE: return "HIP runtime error";
+    case MG_ESINGULAR: return "singular diagonal block or coarse matrix";
+    case MG_ENOCONV: return "not converged within maxit";
+    case MG_ENUMERIC: return "non-finite or diverging residual";
+    case MG_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+const char* mg_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,201 @@
+"""ctypes binding of the native problem generator (libmggen.so, include/mggen.h).
+
+Argument marshalling only: the meshing, coarsening, assembly and transfer construction
+all run in the C++ library.  `build(wl)` returns a `Problem` whose levels hold numpy
+copies of the library's arrays (level 0 = coarsest).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+import workloads as W
+from ._native import load
+
+_lib = None
+
+
+class Round(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("axes", C.c_int32), ("p", C.c_double * 4)]
+
+
+class Config(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("coarse", C.c_int32 * 3), ("h0", C.c_double),
+                ("n_rounds", C.c_int32), ("rounds", C.POINTER(Round)),
+                ("pde", C.c_int32), ("block", C.c_int32), ("eps", C.c_double),
+                ("bvec", C.c_double * 3), ("lam", C.c_double), ("mu", C.c_double),
+                ("nu", C.c_double), ("dt", C.c_double), ("pspg_alpha", C.c_double),
+                ("dir_faces", C.c_int32), ("dir_comps", C.c_int32), ("rhs", C.c_int32),
+                ("rhs_const", C.c_double * 4),
+                ("kappa", (C.c_double * 3) * 8), ("a", C.c_double * 8), ("phi", C.c_double * 8),
+                ("scale", C.c_double), ("j", C.c_int32 * 8),
+                ("fk", (C.c_double * 3) * 4), ("fc", C.c_double * 4), ("fphi", C.c_double * 4),
+                ("fi", C.c_int32 * 4)]
+
+
+class LevelView(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("block", C.c_int32), ("nnzb", C.c_int64),
+                ("rowptr", C.POINTER(C.c_int32)), ("col", C.POINTER(C.c_int32)),
+                ("val", C.POINTER(C.c_double)), ("p_cols", C.c_int32), ("p_nnz", C.c_int64),
+                ("p_rowptr", C.POINTER(C.c_int32)), ("p_col", C.POINTER(C.c_int32)),
+                ("p_val", C.POINTER(C.c_double)), ("dof_mask", C.POINTER(C.c_uint8)),
+                ("n_hanging", C.c_int32), ("hang_node", C.POINTER(C.c_int32)),
+                ("hang_master", C.POINTER(C.c_int32)), ("hang_weight", C.POINTER(C.c_double)),
+                ("node_lattice", C.POINTER(C.c_int32)), ("max_depth", C.c_int32)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = load("libmggen.so")
+        L.mggen_build.argtypes = [C.POINTER(Config), C.POINTER(C.c_void_p)]
+        L.mggen_build.restype = C.c_int
+        L.mggen_num_levels.argtypes = [C.c_void_p]
+        L.mggen_num_levels.restype = C.c_int32
+        L.mggen_level.argtypes = [C.c_void_p, C.c_int32, C.POINTER(LevelView)]
+        L.mggen_level.restype = C.c_int
+        L.mggen_rhs.argtypes = [C.c_void_p]
+        L.mggen_rhs.restype = C.POINTER(C.c_double)
+        L.mggen_rhs_noise.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double)]
+        L.mggen_rhs_noise.restype = C.c_int
+        L.mggen_free.argtypes = [C.c_void_p]
+        L.mggen_free.restype = None
+        L.mggen_last_error.argtypes = []
+        L.mggen_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _arr(ptr, n, dtype):
+    if n == 0 or not ptr:
+        return np.zeros(0, dtype)
+    return np.ctypeslib.as_array(ptr, shape=(n,)).astype(dtype, copy=True)
+
+
+@dataclasses.dataclass
+class GenLevel:
+    n: int
+    block: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray              # (nnzb, b, b)
+    p_cols: int
+    p_rowptr: Optional[np.ndarray]
+    p_col: Optional[np.ndarray]
+    p_val: Optional[np.ndarray]
+    mask: np.ndarray             # (n, b) uint8
+    hang_node: np.ndarray
+    hang_master: np.ndarray      # (k, 4)
+    hang_weight: np.ndarray      # (k, 4)
+    lattice: np.ndarray          # (n, 3)
+    max_depth: int
+
+    @property
+    def nnzb(self):
+        return len(self.col)
+
+
+@dataclasses.dataclass
+class Problem:
+    wl: W.Workload
+    levels: List[GenLevel]
+    b: Optional[np.ndarray]      # finest rhs (n*b,), None for noise problems
+    _handle: Optional[int] = None
+
+    @property
+    def finest(self):
+        return self.levels[-1]
+
+
+def config_of(wl: W.Workload):
+    cfg = Config()
+    cfg.dim = wl.dim
+    for a in range(3):
+        cfg.coarse[a] = wl.coarse[a] if a < wl.dim else 1
+    cfg.h0 = wl.h0
+    rounds = (Round * max(1, wl.n_rounds))()
+    for k, r in enumerate(wl.rounds):
+        if r[0] == "uniform":
+            rounds[k].kind = 0
+        elif r[0] == "band":
+            rounds[k].kind = 1
+            for q in range(4):
+                rounds[k].p[q] = r[1 + q]
+        elif r[0] == "corner":
+            rounds[k].kind = 2
+            rounds[k].axes = r[1]
+            rounds[k].p[0] = r[2]
+        else:
+            raise ValueError(r)
+    cfg.n_rounds = wl.n_rounds
+    cfg.rounds = C.cast(rounds, C.POINTER(Round))
+    cfg.pde = wl.pde
+    cfg.block = wl.block
+    cfg.eps = wl.eps
+    for a in range(len(wl.bvec)):
+        cfg.bvec[a] = wl.bvec[a]
+    cfg.lam, cfg.mu, cfg.nu, cfg.dt, cfg.pspg_alpha = wl.lam, wl.mu, wl.nu, wl.dt, wl.pspg_alpha
+    cfg.dir_faces, cfg.dir_comps, cfg.rhs = wl.dir_faces, wl.dir_comps, wl.rhs
+    for a in range(len(wl.rhs_const)):
+        cfg.rhs_const[a] = wl.rhs_const[a]
+    if wl.pde == W.PDE_OSEEN or wl.rhs == W.RHS_FIELD:
+        f = W.oseen_fields(wl.seed)
+        for k in range(8):
+            for q in range(3):
+                cfg.kappa[k][q] = f["kappa"][k, q]
+            cfg.a[k], cfg.phi[k], cfg.j[k] = f["a"][k], f["phi"][k], int(f["j"][k])
+        cfg.scale = f["scale"]
+        for m in range(4):
+            for q in range(3):
+                cfg.fk[m][q] = f["fk"][m, q]
+            cfg.fc[m], cfg.fphi[m], cfg.fi[m] = f["fc"][m], f["fphi"][m], int(f["fi"][m])
+    return cfg, rounds
+
+
+def build(wl: W.Workload, nrhs: int = 1) -> Problem:
+    L = lib()
+    cfg, keep = config_of(wl)
+    h = C.c_void_p()
+    rc = L.mggen_build(C.byref(cfg), C.byref(h))
+    if rc != 0:
+        raise RuntimeError(f"mggen_build failed ({rc}): {L.mggen_last_error().decode()}")
+    try:
+        levels = []
+        for l in range(L.mggen_num_levels(h)):
+            v = LevelView()
+            rc = L.mggen_level(h, l, C.byref(v))
+            if rc != 0:
+                raise RuntimeError(L.mggen_last_error().decode())
+            n, b, nnzb = v.n_nodes, v.block, v.nnzb
+            has_p = bool(v.p_rowptr)
+            levels.append(GenLevel(
+                n=n, block=b,
+                rowptr=_arr(v.rowptr, n + 1, np.int32), col=_arr(v.col, nnzb, np.int32),
+                val=_arr(v.val, nnzb * b * b, np.float64).reshape(nnzb, b, b),
+                p_cols=v.p_cols,
+                p_rowptr=_arr(v.p_rowptr, n + 1, np.int32) if has_p else None,
+                p_col=_arr(v.p_col, v.p_nnz, np.int32) if has_p else None,
+                p_val=_arr(v.p_val, v.p_nnz, np.float64) if has_p else None,
+                mask=_arr(v.dof_mask, n * b, np.uint8).reshape(n, b),
+                hang_node=_arr(v.hang_node, v.n_hanging, np.int32),
+                hang_master=_arr(v.hang_master, 4 * v.n_hanging, np.int32).reshape(-1, 4),
+                hang_weight=_arr(v.hang_weight, 4 * v.n_hanging, np.float64).reshape(-1, 4),
+                lattice=_arr(v.node_lattice, 3 * n, np.int32).reshape(n, 3),
+                max_depth=v.max_depth))
+        top = levels[-1]
+        if wl.rhs == W.RHS_NOISE:
+            xi = np.ascontiguousarray(W.noise(wl.seed, top.n, nrhs))
+            out = np.zeros((top.n, nrhs))
+            rc = L.mggen_rhs_noise(h, xi.ctypes.data_as(C.POINTER(C.c_double)), nrhs,
+                                   out.ctypes.data_as(C.POINTER(C.c_double)))
+            if rc != 0:
+                raise RuntimeError(L.mggen_last_error().decode())
+            b = out[:, 0].copy() if nrhs == 1 else out
+        else:
+            b = _arr(L.mggen_rhs(h), top.n * top.block, np.float64)
+        return Problem(wl, levels, b)
+    finally:
+        L.mggen_free(h)

@@ -1,0 +1,230 @@
+"""ctypes binding of the HIP solver library (libmgq1.so, include/mgq1.h).
+
+Argument marshalling only: every step of the V-cycle and of the outer loops runs in the
+library's HIP kernels.  Device vectors are torch tensors (FP64, contiguous, on the
+current device); PyTorch provides only memory and the stream.  There is no fallback:
+a missing library raises at load time.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import numpy as np
+
+import workloads as W
+from ._native import load
+
+_lib = None
+
+PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
+
+
+class LevelIn(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("block", C.c_int32), ("nnzb", C.c_int64),
+                ("A_rowptr", C.c_void_p), ("A_col", C.c_void_p), ("A_val", C.c_void_p),
+                ("p_cols", C.c_int32), ("p_nnz", C.c_int64),
+                ("P_rowptr", C.c_void_p), ("P_col", C.c_void_p), ("P_val", C.c_void_p),
+                ("dof_mask", C.c_void_p)]
+
+
+class Config(C.Structure):
+    _fields_ = [("omega", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32),
+                ("coarse_mode", C.c_int32), ("coarse_sweeps", C.c_int32),
+                ("precision", C.c_int32), ("outer", C.c_int32), ("gmres_m", C.c_int32),
+                ("maxit", C.c_int32), ("rtol", C.c_double), ("use_graph", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32),
+                ("converged", C.c_int32), ("res0", C.c_double), ("res_final", C.c_double),
+                ("t_solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+SYMBOLS = ["mg_setup_hierarchy", "mg_vcycle", "mg_solve", "mg_solve_fixed", "mg_level_defect",
+           "mg_level_spmv", "mg_level_sweep", "mg_level_sweep0", "mg_level_restrict",
+           "mg_level_prolong", "mg_coarse_solve", "mg_level_info", "mg_num_levels",
+           "mg_validate_level", "mg_destroy", "mg_status_string", "mg_last_error"]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = load("libmgq1.so")
+        vp, i32 = C.c_void_p, C.c_int32
+        L.mg_setup_hierarchy.argtypes = [C.POINTER(LevelIn), i32, C.POINTER(Config), i32, vp, C.POINTER(vp)]
+        L.mg_vcycle.argtypes = [vp, vp, vp, vp]
+        L.mg_solve.argtypes = [vp, vp, vp, C.POINTER(Stats), vp]
+        L.mg_solve_fixed.argtypes = [vp, vp, vp, i32, C.POINTER(Stats), vp]
+        L.mg_level_defect.argtypes = [vp, i32, vp, vp, vp, i32, vp]
+        L.mg_level_spmv.argtypes = [vp, i32, vp, vp, vp]
+        L.mg_level_sweep.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.mg_level_sweep0.argtypes = [vp, i32, vp, vp, vp]
+        L.mg_level_restrict.argtypes = [vp, i32, vp, vp, vp]
+        L.mg_level_prolong.argtypes = [vp, i32, vp, vp, vp]
+        L.mg_coarse_solve.argtypes = [vp, vp, vp, vp]
+        L.mg_level_info.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_int64)]
+        L.mg_num_levels.argtypes = [vp]
+        L.mg_num_levels.restype = i32
+        L.mg_validate_level.argtypes = [C.POINTER(LevelIn), C.POINTER(LevelIn)]
+        L.mg_destroy.argtypes = [vp]
+        L.mg_destroy.restype = None
+        L.mg_status_string.argtypes = [C.c_int]
+        L.mg_status_string.restype = C.c_char_p
+        L.mg_last_error.argtypes = []
+        L.mg_last_error.restype = C.c_char_p
+        for name in SYMBOLS:
+            if name not in ("mg_destroy", "mg_status_string", "mg_last_error", "mg_num_levels"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class MGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+def _check(rc):
+    if rc != 0:
+        L = lib()
+        raise MGError(rc, L.mg_last_error().decode())
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"]
+        return a.ctypes.data
+    assert a.is_contiguous(), "device arrays must be contiguous"
+    return a.data_ptr()
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def level_structs(levels):
+    """mg_level_in array from host levels (objects with rowptr, col, val, p_*, mask)."""
+    keep = []
+    arr = (LevelIn * len(levels))()
+    for l, lv in enumerate(levels):
+        parts = [np.ascontiguousarray(lv.rowptr, np.int32), np.ascontiguousarray(lv.col, np.int32),
+                 np.ascontiguousarray(lv.val, np.float64), np.ascontiguousarray(lv.mask, np.uint8)]
+        keep += parts
+        s = arr[l]
+        s.n_nodes, s.block, s.nnzb = lv.n, lv.block, len(parts[1])
+        s.A_rowptr, s.A_col, s.A_val, s.dof_mask = (p.ctypes.data for p in parts)
+        if l > 0 and lv.p_rowptr is not None:
+            pp = [np.ascontiguousarray(lv.p_rowptr, np.int32), np.ascontiguousarray(lv.p_col, np.int32),
+                  np.ascontiguousarray(lv.p_val, np.float64)]
+            keep += pp
+            s.p_cols, s.p_nnz = lv.p_cols, len(pp[1])
+            s.P_rowptr, s.P_col, s.P_val = (p.ctypes.data for p in pp)
+    return arr, keep
+
+
+def config_from(wl: W.Workload, precision="fp64", **over) -> Config:
+    c = Config()
+    c.omega = over.get("omega", wl.omega)
+    c.nu1 = over.get("nu1", wl.nu1)
+    c.nu2 = over.get("nu2", wl.nu2)
+    c.coarse_mode = over.get("coarse_mode", wl.coarse_mode)
+    c.coarse_sweeps = over.get("coarse_sweeps", wl.coarse_sweeps)
+    c.precision = PREC[precision]
+    c.outer = over.get("outer", wl.outer)
+    c.gmres_m = over.get("gmres_m", wl.gmres_m)
+    c.maxit = over.get("maxit", wl.maxit)
+    c.rtol = over.get("rtol", wl.rtol)
+    c.use_graph = 0
+    return c
+
+
+class Hierarchy:
+    """A device-resident multigrid hierarchy (library handle)."""
+
+    def __init__(self, levels, cfg: Config, stream=None):
+        L = lib()
+        arr, keep = level_structs(levels)
+        h = C.c_void_p()
+        self.cfg = cfg
+        _check(L.mg_setup_hierarchy(arr, len(levels), C.byref(cfg), 0, _stream(stream), C.byref(h)))
+        self.h = h
+        self.n_levels = L.mg_num_levels(h)
+        self.sizes = [self.level_info(l) for l in range(self.n_levels)]
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_info(self, l):
+        n, b, nnzb = C.c_int32(), C.c_int32(), C.c_int64()
+        _check(lib().mg_level_info(self.h, l, C.byref(n), C.byref(b), C.byref(nnzb)))
+        return n.value, b.value, nnzb.value
+
+    def ndof(self, l=-1):
+        n, b, _ = self.sizes[l]
+        return n * b
+
+    # -- whole-path entry points
+    def vcycle(self, b, x, stream=None):
+        _check(lib().mg_vcycle(self.h, _ptr(b), _ptr(x), _stream(stream)))
+
+    def solve(self, b, x, stream=None, fixed=None):
+        st = Stats()
+        if fixed is None:
+            rc = lib().mg_solve(self.h, _ptr(b), _ptr(x), C.byref(st), _stream(stream))
+        else:
+            rc = lib().mg_solve_fixed(self.h, _ptr(b), _ptr(x), int(fixed), C.byref(st), _stream(stream))
+        if rc not in (0, -5):
+            _check(rc)
+        return st.as_dict()
+
+    # -- step-wise entry points
+    def defect(self, l, b, x, r, masked=False, stream=None):
+        _check(lib().mg_level_defect(self.h, l, _ptr(b), _ptr(x), _ptr(r), int(masked), _stream(stream)))
+
+    def spmv(self, l, x, y, stream=None):
+        _check(lib().mg_level_spmv(self.h, l, _ptr(x), _ptr(y), _stream(stream)))
+
+    def sweep(self, l, b, x, xo, stream=None):
+        _check(lib().mg_level_sweep(self.h, l, _ptr(b), _ptr(x), _ptr(xo), _stream(stream)))
+
+    def sweep0(self, l, b, xo, stream=None):
+        _check(lib().mg_level_sweep0(self.h, l, _ptr(b), _ptr(xo), _stream(stream)))
+
+    def restrict(self, l, r, d, stream=None):
+        _check(lib().mg_level_restrict(self.h, l, _ptr(r), _ptr(d), _stream(stream)))
+
+    def prolong(self, l, y, x, stream=None):
+        _check(lib().mg_level_prolong(self.h, l, _ptr(y), _ptr(x), _stream(stream)))
+
+    def coarse_solve(self, b, x, stream=None):
+        _check(lib().mg_coarse_solve(self.h, _ptr(b), _ptr(x), _stream(stream)))
+
+
+def validate_level(level, coarser=None) -> int:
+    """Host-only structural validation; returns the status code (0 = valid)."""
+    arr, keep = level_structs([coarser, level] if coarser is not None else [level])
+    if coarser is not None:
+        return lib().mg_validate_level(C.byref(arr[1]), C.byref(arr[0]))
+    return lib().mg_validate_level(C.byref(arr[0]), None)
+
+
+def last_error() -> str:
+    return lib().mg_last_error().decode()

@@ -1,0 +1,80 @@
+"""Host-side checks of the C ABI (no GPU): every symbol declared in include/*.h is
+exported, and the host validator rejects malformed inputs with MG_EINVAL."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2405_05047_amd import gen, mg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    txt = open(os.path.join(ROOT, "include", header)).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)          # drop comments
+    return sorted(set(re.findall(r"\b((?:mg|mggen)_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.mark.parametrize("header,lib", [("mgq1.h", "libmgq1.so"), ("mggen.h", "libmggen.so")])
+def test_symbols_exported(header, lib):
+    path = os.path.join(ROOT, "paper_2405_05047_amd", lib)
+    out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True, check=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    missing = [s for s in _declared(header) if s not in exported]
+    assert not missing, missing
+
+
+@pytest.fixture(scope="module")
+def levels():
+    return gen.build(W.c2_td(band_rounds=2, uniform_rounds=1)).levels
+
+
+def _copy(lv):
+    import copy
+    return copy.deepcopy(lv)
+
+
+def test_valid_levels_pass(levels):
+    for l in range(len(levels)):
+        assert mg.validate_level(levels[l], levels[l - 1] if l else None) == 0
+
+
+@pytest.mark.parametrize("breakage", ["rowptr", "col_range", "col_order", "missing_diag", "mask_row",
+                                      "mask_col", "nan", "p_col", "p_cols"])
+def test_malformed_rejected(levels, breakage):
+    lv = _copy(levels[-1])
+    co = levels[-2]
+    if breakage == "rowptr":
+        lv.rowptr[5] = lv.rowptr[6] + 1
+    elif breakage == "col_range":
+        lv.col[3] = lv.n
+    elif breakage == "col_order":
+        k = lv.rowptr[100]
+        lv.col[k], lv.col[k + 1] = lv.col[k + 1], lv.col[k]
+    elif breakage == "missing_diag":
+        i = int(np.nonzero(lv.mask[:, 0] == 0)[0][0])
+        k = lv.rowptr[i] + int(np.nonzero(lv.col[lv.rowptr[i]:lv.rowptr[i + 1]] == i)[0][0])
+        lv.col[k] = lv.col[k] + (1 if k + 1 < lv.rowptr[i + 1] else -1)
+    elif breakage == "mask_row":
+        i = int(np.nonzero(lv.mask[:, 0])[0][0])
+        k = lv.rowptr[i]
+        lv.val[k, 0, 0] = 2.0
+    elif breakage == "mask_col":
+        j = int(np.nonzero(lv.mask[:, 0])[0][0])
+        rows = np.repeat(np.arange(lv.n), np.diff(lv.rowptr))
+        ks = np.nonzero((lv.col == j) & (rows != j))[0]
+        if len(ks) == 0:
+            pytest.skip("no off-diagonal reference to a constrained node")
+        lv.val[ks[0], 0, 0] = 0.5
+    elif breakage == "nan":
+        lv.val[7, 0, 0] = np.nan
+    elif breakage == "p_col":
+        lv.p_col[0] = co.n
+    elif breakage == "p_cols":
+        lv.p_cols = co.n + 1
+    assert mg.validate_level(lv, co) == -1
+    assert mg.last_error()

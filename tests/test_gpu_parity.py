@@ -1,0 +1,220 @@
+"""GPU parity: the HIP library (through its C ABI) against the oracle, element by element.
+
+Both sides build their operators independently from the same seeded workload (the
+library side through the native generator).  Tolerances (derived from the arithmetic):
+  * one SpMV / defect / sweep / transfer step: |gpu - oracle| <= 1e-12 * scale, scale the
+    infinity norm of |A||x| (plus |b|, |x| where they enter); a row sum of <= 27 blocks
+    in FP64 with operands equal to 1e-15 relative is accurate to ~1e-14 of that scale;
+  * one V-cycle: 1e-12 relative (normwise);
+  * solutions: 1e-10 relative after the same number of cycles (fixed-count runs) and for
+    converged solves (the iteration counts are asserted equal).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hierarchy as Hh, multigrid as MG
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _log(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    "poisson33": W.c1_poisson(4),
+    "td_band": W.c2_td(band_rounds=3, uniform_rounds=1),
+    "elast17": W.c3_elasticity(3),
+    "oseen17": W.c4_oseen(3),
+    "edge4": W.c3_adaptive("edge", 4),
+    "oseen_tall": W.c4_oseen(2, tall=True),
+}
+
+_cache = {}
+
+
+def _pair(name):
+    if name not in _cache:
+        from paper_2405_05047_amd import gen, mg
+        wl = CASES[name]
+        _log("building", name)
+        o = Hh.build(wl)
+        p = gen.build(wl)
+        h = mg.Hierarchy(p.levels, mg.config_from(wl))
+        _cache[name] = (wl, o, MG.Multigrid(o), p, h)
+    return _cache[name]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rand(seed, n):
+    return W.rand_vec(seed, n)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_level_structure(name):
+    wl, o, mgo, p, h = _pair(name)
+    assert h.n_levels == len(o.levels)
+    for l, lv in enumerate(o.levels):
+        n, b, nnzb = h.sizes[l]
+        assert (n, b) == (lv.n, wl.block) and nnzb == len(lv.col)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_spmv_defect_parity(name):
+    wl, o, mgo, p, h = _pair(name)
+    for l, lv in enumerate(o.levels):
+        _log(name, "spmv level", l)
+        x = _rand(100 + l, lv.ndof)
+        b = _rand(200 + l, lv.ndof)
+        scale = max(np.abs(abs(lv.A) @ np.abs(x)).max(), np.abs(b).max())
+        y = torch.zeros(lv.ndof, dtype=torch.float64, device="cuda")
+        h.spmv(l, dev(x), y)
+        assert np.abs(host(y) - lv.A @ x).max() <= 1e-12 * scale
+        r = torch.zeros_like(y)
+        h.defect(l, dev(b), dev(x), r)
+        assert np.abs(host(r) - (b - lv.A @ x)).max() <= 1e-12 * scale
+        h.defect(l, dev(b), dev(x), r, masked=True)
+        ref = b - lv.A @ x
+        ref[lv.mask.ravel()] = 0.0
+        got = host(r)
+        assert np.all(got[lv.mask.ravel()] == 0.0)
+        assert np.abs(got - ref).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_smoother_parity(name):
+    wl, o, mgo, p, h = _pair(name)
+    for l, lv in enumerate(o.levels):
+        _log(name, "sweep level", l)
+        x = _rand(300 + l, lv.ndof)
+        b = _rand(400 + l, lv.ndof)
+        ref = mgo.smooth(l, x, b)
+        xo = torch.zeros(lv.ndof, dtype=torch.float64, device="cuda")
+        h.sweep(l, dev(b), dev(x), xo)
+        scale = np.abs(ref).max() + np.abs(abs(lv.A) @ np.abs(x)).max()
+        assert np.abs(host(xo) - ref).max() <= 1e-12 * scale
+        h.sweep0(l, dev(b), xo)
+        ref0 = mgo.smooth(l, np.zeros_like(b), b)
+        assert np.abs(host(xo) - ref0).max() <= 1e-12 * np.abs(ref0).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_transfer_parity(name):
+    wl, o, mgo, p, h = _pair(name)
+    for l in range(1, len(o.levels)):
+        _log(name, "transfer level", l)
+        f, c = o.levels[l], o.levels[l - 1]
+        r = _rand(500 + l, f.ndof)
+        d = torch.zeros(c.ndof, dtype=torch.float64, device="cuda")
+        h.restrict(l, dev(r), d)
+        ref = f.R @ r
+        got = host(d)
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(r).max() * 8
+        assert np.all(got[c.mask.ravel()] == 0.0)
+        y = _rand(600 + l, c.ndof)
+        x = _rand(700 + l, f.ndof)
+        xt = dev(x)
+        h.prolong(l, dev(y), xt)
+        ref = x + f.P @ y
+        assert np.abs(host(xt) - ref).max() <= 1e-13 * (np.abs(x).max() + np.abs(y).max())
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_coarse_solve_parity(name):
+    wl, o, mgo, p, h = _pair(name)
+    b = _rand(800, o.levels[0].ndof)
+    b[o.levels[0].mask.ravel()] = 0.0
+    x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+    h.coarse_solve(dev(b), x)
+    ref = mgo.coarse_solve(b)
+    assert np.abs(host(x) - ref).max() <= 1e-12 * np.abs(ref).max() * max(1.0, np.linalg.cond(mgo.A0) / 1e3)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_vcycle_parity_and_determinism(name):
+    wl, o, mgo, p, h = _pair(name)
+    _log(name, "vcycle")
+    b = o.b.copy()
+    ref = mgo.vcycle(b)
+    x1 = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+    x2 = torch.zeros_like(x1)
+    h.vcycle(dev(b), x1)
+    h.vcycle(dev(b), x2)
+    g1, g2 = host(x1), host(x2)
+    assert np.array_equal(g1, g2)                       # bitwise deterministic
+    assert np.abs(g1 - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fixed_cycles_parity(name):
+    wl, o, mgo, p, h = _pair(name)
+    _log(name, "fixed cycles")
+    k = 6
+    ref, st_ref = mgo.solve(o.b, fixed_iters=k)
+    x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+    st = h.solve(dev(o.b), x, fixed=k)
+    assert st["iters"] == st_ref.iters == k
+    assert np.linalg.norm(host(x) - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_converged_solution_parity(name):
+    wl, o, mgo, p, h = _pair(name)
+    _log(name, "solve")
+    ref, st_ref = mgo.solve(o.b)
+    x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+    st = h.solve(dev(o.b), x)
+    _log(name, "gpu", st, "oracle iters", st_ref.iters)
+    assert st["converged"] == 1 and st_ref.converged
+    assert st["iters"] == st_ref.iters
+    got = host(x)
+    assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+    res = np.linalg.norm(o.b - o.finest.A @ got)
+    assert res <= wl.rtol * np.linalg.norm(o.b) * (1 + 1e-9)
+
+
+def test_single_level_hierarchy():
+    from paper_2405_05047_amd import gen, mg
+    wl = W.c1_poisson(0)
+    o = Hh.build(wl)
+    p = gen.build(wl)
+    h = mg.Hierarchy(p.levels, mg.config_from(wl))
+    assert h.n_levels == 1
+    b = _rand(900, o.finest.ndof)
+    b[o.finest.mask.ravel()] = 0
+    x = torch.zeros(len(b), dtype=torch.float64, device="cuda")
+    h.vcycle(dev(b), x)
+    assert np.abs(host(x) - MG.Multigrid(o).vcycle(b)).max() <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("name", ["td_band", "elast17", "oseen17"])
+def test_mixed_precision_reaches_fp64_tolerance(name, prec):
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    _log(name, "mixed", prec)
+    h = mg.Hierarchy(p.levels, mg.config_from(wl, precision=prec))
+    x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+    st = h.solve(dev(o.b), x)
+    got = host(x)
+    res = np.linalg.norm(o.b - o.finest.A @ got)
+    ref, st_ref = mgo.solve(o.b)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    _log(name, prec, "iters", st["iters"], "fp64 iters", st_ref.iters, "rel err vs fp64 oracle", err)
+    assert st["converged"] == 1
+    assert res <= wl.rtol * np.linalg.norm(o.b) * (1 + 1e-9)
+    assert err <= 1e-6
