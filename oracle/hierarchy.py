@@ -66,6 +66,8 @@ def build_level(wl, forest) -> Level:
 def build(wl: W.Workload, nrhs: int = 1) -> Hierarchy:
     finest = M.build_forest(wl)
     forests = M.hierarchy_forests(finest)
+    # the coarse mesh may be any level of the hierarchy (Sec. 2.2); levels below it are unused
+    forests = forests[min(wl.coarse_level, len(forests) - 1):]
     levels = [build_level(wl, f) for f in forests]
     for l in range(1, len(levels)):
         fine, coarse = levels[l], levels[l - 1]

@@ -15,7 +15,7 @@ enum VecKind { X_F64 = 0, X_F32 = 1 };
 constexpr int kWave = 64;             // wavefront width on CDNA
 constexpr int kSliceWaves = 4;        // slices (one per wave) per 256-thread workgroup
 constexpr int kRedThreads = 256;
-constexpr int kMaxRedBlocks = 1024;   // grid of the last-block reductions
+constexpr int kMaxRedBlocks = 512;    // grid (= partial count) of the vector reductions
 
 // Sliced ELL of a block matrix: one slice = 64 lanes = R = 64/B nodes x B components;
 // lane = r*B + c handles scalar row (node slice*R + r, component c).  For block slot k of
@@ -43,19 +43,31 @@ struct CsrDev {
   int f32 = 1;
 };
 
-// deterministic grid reduction: per-block partials, the last block to finish sums them
-struct RedDev {
-  double* partials = nullptr;       // >= grid size entries
-  unsigned* counter = nullptr;      // zero between reductions
-  double* out = nullptr;            // result
-  int sqrt_out = 0;                 // write sqrt(sum) instead of sum
+// one level of the single-workgroup tail of the V-cycle (device-resident array)
+struct TailLevel {
+  SellDev A;                        // cycle operator
+  const void* S = nullptr;          // smoother blocks (lane layout, cycle precision)
+  const uint8_t* mask = nullptr;    // constrained DoFs
+  CsrDev P, R;                      // from level l-1 (unused on level 0)
+  void *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;
+};
+
+struct TailParams {
+  int top = 0;                      // highest level handled by the tail
+  int nu1 = 2, nu2 = 2;
+  double omega = 1.0;
+  const double* Ainv = nullptr;     // coarse inverse, row-major FP64
+  int n0 = 0;
+  int coarse_mode = 0, coarse_sweeps = 1;
 };
 
 // ------------------------------------------------------------------ launchers
 // y = A x (mode 0), y = b - A x (mode 1), y = M (b - A x) with M zeroing constrained
-// DoFs (mode 2); optional sum of squares of y into red.  xk / yk: vector kinds.
+// DoFs (mode 2); with `partials` != NULL every block also writes the sum of squares of
+// its y entries to partials[block] (spmv_grid(A) entries).  xk / yk: vector kinds.
 hipError_t launch_spmv(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask,
-                       int xk, int yk, int mode, const RedDev* red, hipStream_t s);
+                       int xk, int yk, int mode, double* partials, hipStream_t s);
+int spmv_grid(const SellDev& A);
 // x_out = x + omega S (b - A x); S in lane layout, same kind as the vectors
 hipError_t launch_sweep(const SellDev& A, const void* S, const void* b, const void* x, void* xo,
                         double omega, int xk, hipStream_t s);
@@ -68,12 +80,14 @@ hipError_t launch_restrict(const CsrDev& R, int B, const void* r, void* d, const
 // x += M_f P~ M_c y
 hipError_t launch_prolong(const CsrDev& P, int B, const void* y, void* x, const uint8_t* mask_f,
                           const uint8_t* mask_c, int xk, hipStream_t s);
-// x = Ainv b with the FP64 inverse stored transposed; b / x of kind xk
-hipError_t launch_coarse_gemv(int n, const double* AinvT, const void* b, void* x, int xk, hipStream_t s);
+// x = Ainv b with the FP64 inverse stored row-major; b / x of kind xk
+hipError_t launch_coarse_gemv(int n, const double* Ainv, const void* b, void* x, int xk, hipStream_t s);
 // Gauss-Jordan with partial pivoting on the n x 2n augmented matrix M = [A | I]
-// (row-major, FP64); writes the inverse transposed to AinvT; flag != 0 if singular
-hipError_t launch_coarse_invert(int n, double* M, double* AinvT, double* pivbuf, int* flag,
+// (row-major, FP64); writes the inverse (row-major) to Ainv; flag != 0 if singular
+hipError_t launch_coarse_invert(int n, double* M, double* Ainv, double* pivbuf, int* flag,
                                 hipStream_t s);
+// levels p.top .. 1 and the coarse solve of one V-cycle in one workgroup
+hipError_t launch_tail(const TailLevel* lv, int B, int kind, int xk, const TailParams& p, hipStream_t s);
 // nodal block inverses of the diagonal blocks of A (FP64 SELL) into S (lane layout,
 // double or float per sk); flag != 0 if a block is singular
 hipError_t launch_block_invert(const SellDev& A, void* S, int sk, int* flag, hipStream_t s);
@@ -85,8 +99,16 @@ hipError_t launch_axpy(int64_t n, void* y, int yk, const void* x, int xk, double
                        const double* alpha, hipStream_t s);          // y += sign * (*alpha) * x
 hipError_t launch_scale_div(int64_t n, double* y, const double* x, const double* denom,
                             hipStream_t s);                          // y = x / *denom (if != 0)
-hipError_t launch_dot(int64_t n, const double* a, const double* b, const RedDev& red, hipStream_t s);
-hipError_t launch_nrm2(int64_t n, const double* a, const RedDev& red, hipStream_t s);
+// deterministic reductions without atomics: producers write one partial per block
+// (reduction_grid(n) of them); consumers re-sum them in a fixed order
+int reduction_grid(int64_t n);
+hipError_t launch_dot_partials(int64_t n, const double* a, const double* b, double* partials, hipStream_t s);
+hipError_t launch_finish(const double* partials, int g, double* out, int sqrt_out, hipStream_t s);
+// MGS step: h = sum(pin) -> *hout; w -= h vi; partials of (w, vnext) (vnext NULL: (w, w))
+hipError_t launch_mgs_step(int64_t n, double* w, const double* vi, const double* vnext, const double* pin,
+                           double* pout, double* hout, hipStream_t s);
+// nrm = sqrt(sum(pin)) -> *hout; w /= nrm unless nrm == 0
+hipError_t launch_mgs_normalize(int64_t n, double* w, const double* pin, double* hout, hipStream_t s);
 // x += sum_{i<k} y[i] Z_i, Z_i = Z + i*ldz of kind zk
 hipError_t launch_update_x(int64_t n, double* x, const void* Z, int zk, int64_t ldz, const double* y,
                            int k, hipStream_t s);

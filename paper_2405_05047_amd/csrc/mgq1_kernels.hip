@@ -2,20 +2,30 @@
 //
 // Every kernel here streams sparse data and is bound by HBM bandwidth (about 0.1-0.25
 // flop per byte in FP64), so there is no matrix-core work: the design goals are coalesced
-// value / index streams, cached gathers of x, one pass over A per smoothing sweep and
-// deterministic reductions (no floating-point atomics).
+// value / index streams, cached gathers of x, one pass over A per smoothing sweep, short
+// chains of dependent loads on small levels, and deterministic reductions (no atomics).
 //
 //   SELL slice kernels (defect / SpMV, smoothing sweep): one wavefront per slice of
-//   64/B nodes; lane = node*B + component owns one scalar row.  For every block slot the
-//   wave issues B fully coalesced 512-byte value loads and one load of the R column
-//   indices, gathers x[col*B + cc] (L2 / MALL hits: neighbouring slices share columns),
-//   and accumulates in registers.  The smoother exchanges the B residual components of a
-//   node across its lanes with wave shuffles and applies the stored block inverse.
-//   Workgroup ids are remapped so that each XCD (round-robin dispatch over 8 XCDs) walks
-//   a contiguous range of slices and keeps its own L2 warm.
+//   64/B nodes; lane = node*B + component owns one scalar row.  Block slots are consumed
+//   in batches: the column indices of a batch are loaded first, then all value and x
+//   loads of the batch are issued together, then the FMAs run, so a row of 9 (2D) or 27
+//   (3D) blocks costs 2-8 memory round trips instead of one per block.  Each value load of
+//   a wave is one contiguous 512-byte (FP64) stream.  The smoother exchanges the B residual
+//   components of a node across its lanes with wave shuffles and applies the stored block
+//   inverse.  Workgroup ids are remapped so that each XCD (round-robin dispatch over 8
+//   XCDs) walks a contiguous range of slices and keeps its own L2 warm.
 //
-// Paper correspondence: smoother x + omega S (b - A x) and transfers P, R = P^T
-// (Sec. 4.1 "Geometric Multigrid CUDA"); GMRES building blocks (Sec. 4.2).
+//   Reductions: every block writes one partial sum; the consumer (the next kernel in the
+//   chain) re-sums all partials in a fixed order in every block, so the result is
+//   deterministic, identical in all blocks and needs no atomics (same-address atomics
+//   serialise at roughly 30 ns each).
+//
+//   Tail kernel: the levels below a size threshold and the coarse solve run as one
+//   single-workgroup launch with workgroup barriers between the steps of the V-cycle.
+//
+// Paper correspondence: smoother x + omega S (b - A x), transfers P and R = P^T and the
+// coarse solve (Sec. 4.1 "Geometric Multigrid CUDA", Algorithm "Geometric multigrid
+// solver"); GMRES building blocks with modified Gram-Schmidt (Sec. 4.2).
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -25,6 +35,8 @@ namespace mgq1 {
 namespace {
 
 constexpr int kThreads = kWave * kSliceWaves;   // 256
+constexpr int kTailThreads = 1024;
+constexpr int kMaxWaves = 16;
 
 __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   // hardware dispatch sends workgroup w to XCD w % 8; give XCD x a contiguous range
@@ -35,26 +47,22 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
 
 template <int K> struct Val;
 template <> struct Val<VK_F64> {
-  using T = double;
   __device__ __forceinline__ static double get(const void* p, int64_t i, float) {
     return __builtin_nontemporal_load(static_cast<const double*>(p) + i);
   }
 };
 template <> struct Val<VK_F32> {
-  using T = float;
   __device__ __forceinline__ static float get(const void* p, int64_t i, float) {
     return __builtin_nontemporal_load(static_cast<const float*>(p) + i);
   }
 };
 template <> struct Val<VK_F16> {
-  using T = float;
   __device__ __forceinline__ static float get(const void* p, int64_t i, float sc) {
     const unsigned short u = __builtin_nontemporal_load(static_cast<const unsigned short*>(p) + i);
     return sc * __half2float(__ushort_as_half(u));
   }
 };
 template <> struct Val<VK_BF16> {
-  using T = float;
   __device__ __forceinline__ static float get(const void* p, int64_t i, float sc) {
     const unsigned short u = __builtin_nontemporal_load(static_cast<const unsigned short*>(p) + i);
     return sc * __uint_as_float(static_cast<uint32_t>(u) << 16);
@@ -66,22 +74,38 @@ template <int B, int K, class XI, class T>
 __device__ __forceinline__ T sell_dot(const SellDev& A, int slice, int lane, bool valid,
                                       const XI* __restrict__ x) {
   constexpr int R = kWave / B;
+  constexpr int KB = B <= 2 ? 8 : 4;       // block slots per batch
   T acc = T(0);
   if (!valid) return acc;
   float sc = 1.0f;
   if (K == VK_F16 || K == VK_BF16) sc = ldexpf(1.0f, A.rexp[int64_t(slice) * kWave + lane]);
   const int r = lane / B;
   const int k0 = A.sptr[slice], k1 = A.sptr[slice + 1];
-  const int32_t* colp = A.col + int64_t(k0) * R + r;
-  int64_t vb = int64_t(k0) * B * kWave + lane;
-#pragma unroll 2
-  for (int k = k0; k < k1; ++k) {
-    const int j = __builtin_nontemporal_load(colp);
-    colp += R;
-    const XI* xj = x + int64_t(j) * B;
+  for (int k = k0; k < k1; k += KB) {
+    int js[KB];
 #pragma unroll
-    for (int cc = 0; cc < B; ++cc) acc += T(Val<K>::get(A.val, vb + cc * kWave, sc)) * T(xj[cc]);
-    vb += B * kWave;
+    for (int q = 0; q < KB; ++q)
+      js[q] = (k + q < k1) ? __builtin_nontemporal_load(A.col + int64_t(k + q) * R + r) : -1;
+    T av[KB][B], xv[KB][B];
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+      if (js[q] >= 0) {                      // uniform across the wave (slice-wide k range)
+        const XI* xj = x + int64_t(js[q]) * B;
+        const int64_t vb = int64_t(k + q) * B * kWave + lane;
+#pragma unroll
+        for (int cc = 0; cc < B; ++cc) {
+          av[q][cc] = T(Val<K>::get(A.val, vb + cc * kWave, sc));
+          xv[q][cc] = T(xj[cc]);
+        }
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < B; ++cc) { av[q][cc] = T(0); xv[q][cc] = T(0); }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KB; ++q)
+#pragma unroll
+      for (int cc = 0; cc < B; ++cc) acc += av[q][cc] * xv[q][cc];
   }
   return acc;
 }
@@ -93,165 +117,288 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// block sum (256 threads) -> thread 0
-__device__ __forceinline__ double block_sum(double v, double* lds) {
+// sum over the block in a fixed order, returned to every thread
+__device__ __forceinline__ double block_allsum(double v, double* lds) {
   v = wave_sum(v);
   const int w = threadIdx.x / kWave, ln = threadIdx.x % kWave;
+  const int nw = blockDim.x / kWave;
   if (ln == 0) lds[w] = v;
   __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int q = 0; q < int(blockDim.x / kWave); ++q) t += lds[q];
-  __syncthreads();
-  return t;
-}
-
-// store this block's partial; the last block to arrive sums all partials in block order
-__device__ void finish_reduction(double part, const RedDev& red, double* lds) {
-  __shared__ int last;
   if (threadIdx.x == 0) {
-    red.partials[blockIdx.x] = part;
-    __threadfence();
-    const unsigned prev = atomicAdd(red.counter, 1u);
-    last = (prev == gridDim.x - 1);
+    double t = 0.0;
+    for (int q = 0; q < nw; ++q) t += lds[q];
+    lds[kMaxWaves] = t;
   }
   __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double t = 0.0;
-  for (int q = threadIdx.x; q < int(gridDim.x); q += blockDim.x)
-    t += __hip_atomic_load(red.partials + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  t = block_sum(t, lds);
-  if (threadIdx.x == 0) {
-    *red.out = red.sqrt_out ? sqrt(t) : t;
-    *red.counter = 0u;
-  }
+  const double r = lds[kMaxWaves];
+  __syncthreads();
+  return r;
 }
 
-template <int B, int K, class XI, class XO, class T, int MODE, bool NORM>
-__global__ __launch_bounds__(kThreads) void k_spmv(SellDev A, const XO* __restrict__ b,
-                                                   const XI* __restrict__ x, XO* __restrict__ y,
-                                                   const uint8_t* __restrict__ mask, RedDev red) {
+// sum of partials[0..g) in a fixed order (every block computes the same value)
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p, int g, double* lds) {
+  double t = 0.0;
+  for (int q = threadIdx.x; q < g; q += blockDim.x) t += p[q];
+  return block_allsum(t, lds);
+}
+
+// ------------------------------------------------------------------ per-slice bodies
+// geometry of one wave-slice
+struct SliceLane {
+  int slice, lane, node;
+  int64_t dof;
+  bool valid;
+};
+
+template <int B>
+__device__ __forceinline__ SliceLane slice_lane(const SellDev& A, int slice, int lane) {
   constexpr int R = kWave / B;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int slice = bid * kSliceWaves + wave;
-  const int node = slice * R + lane / B;
-  const bool valid = slice < A.nslices && lane < R * B && node < A.n;
-  const T acc = sell_dot<B, K, XI, T>(A, slice, lane, valid, x);
-  const int64_t dof = int64_t(slice) * R * B + lane;
+  SliceLane s;
+  s.slice = slice;
+  s.lane = lane;
+  s.node = slice * R + lane / B;
+  s.dof = int64_t(slice) * R * B + lane;
+  s.valid = slice < A.nslices && lane < R * B && s.node < A.n;
+  return s;
+}
+
+// y = A x (MODE 0), b - A x (MODE 1), M (b - A x) (MODE 2); returns the written value
+template <int B, int K, class XI, class XO, class T, int MODE>
+__device__ __forceinline__ T spmv_slice(const SellDev& A, const XO* __restrict__ b, const XI* __restrict__ x,
+                                        XO* __restrict__ y, const uint8_t* __restrict__ mask, const SliceLane& s) {
+  const T acc = sell_dot<B, K, XI, T>(A, s.slice, s.lane, s.valid, x);
   T out = T(0);
-  if (valid) {
+  if (s.valid) {
     if (MODE == 0) {
       out = acc;
     } else {
-      out = T(b[dof]) - acc;
-      if (MODE == 2 && mask[dof]) out = T(0);
+      out = T(b[s.dof]) - acc;
+      if (MODE == 2 && mask[s.dof]) out = T(0);
     }
-    y[dof] = XO(out);
+    y[s.dof] = XO(out);
   }
-  if (NORM) {
-    __shared__ double lds[kSliceWaves];
-    const double p = block_sum(double(out) * double(out), lds);
-    // keep the partial index in dispatch order: reductions stay deterministic
-    finish_reduction(p, red, lds);
-  }
+  return out;
 }
 
 template <int B, int K, class X, class T>
-__global__ __launch_bounds__(kThreads) void k_sweep(SellDev A, const X* __restrict__ S,
-                                                    const X* __restrict__ b, const X* __restrict__ x,
-                                                    X* __restrict__ xo, T omega) {
-  constexpr int R = kWave / B;
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int slice = bid * kSliceWaves + wave;
-  const int node = slice * R + lane / B;
-  const bool valid = slice < A.nslices && lane < R * B && node < A.n;
-  const T acc = sell_dot<B, K, X, T>(A, slice, lane, valid, x);
-  const int64_t dof = int64_t(slice) * R * B + lane;
-  const T res = valid ? T(b[dof]) - acc : T(0);
-  const int base = (lane / B) * B;
+__device__ __forceinline__ void sweep_slice(const SellDev& A, const X* __restrict__ S, const X* __restrict__ b,
+                                            const X* __restrict__ x, X* __restrict__ xo, T omega,
+                                            const SliceLane& s) {
+  const T acc = sell_dot<B, K, X, T>(A, s.slice, s.lane, s.valid, x);
+  const T res = s.valid ? T(b[s.dof]) - acc : T(0);
+  const int base = (s.lane / B) * B;
   T upd = T(0);
 #pragma unroll
   for (int cc = 0; cc < B; ++cc) {
     const T rc = __shfl(res, (base + cc) & (kWave - 1), kWave);
-    if (valid) upd += T(S[(int64_t(slice) * B + cc) * kWave + lane]) * rc;
+    if (s.valid) upd += T(S[(int64_t(s.slice) * B + cc) * kWave + s.lane]) * rc;
   }
-  if (valid) xo[dof] = X(T(x[dof]) + omega * upd);
+  if (s.valid) xo[s.dof] = X(T(x[s.dof]) + omega * upd);
 }
 
 template <int B, class X, class T>
-__global__ __launch_bounds__(kThreads) void k_sweep0(int n, int nslices, const X* __restrict__ S,
-                                                     const X* __restrict__ b, X* __restrict__ xo,
-                                                     T omega) {
-  constexpr int R = kWave / B;
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int slice = blockIdx.x * kSliceWaves + wave;
-  const int node = slice * R + lane / B;
-  if (!(slice < nslices && lane < R * B && node < n)) return;
-  const int64_t dof = int64_t(slice) * R * B + lane;
+__device__ __forceinline__ void sweep0_slice(const X* __restrict__ S, const X* __restrict__ b, X* __restrict__ xo,
+                                             T omega, const SliceLane& s) {
+  if (!s.valid) return;
   T upd = T(0);
 #pragma unroll
   for (int cc = 0; cc < B; ++cc)
-    upd += T(S[(int64_t(slice) * B + cc) * kWave + lane]) * T(b[int64_t(node) * B + cc]);
-  xo[dof] = X(omega * upd);
+    upd += T(S[(int64_t(s.slice) * B + cc) * kWave + s.lane]) * T(b[int64_t(s.node) * B + cc]);
+  xo[s.dof] = X(omega * upd);
 }
 
-template <int B, class X, class T, class W>
-__global__ __launch_bounds__(kThreads) void k_restrict(int nc, const int32_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ rc,
-                                                       const W* __restrict__ rv,
-                                                       const X* __restrict__ r, X* __restrict__ d,
-                                                       const uint8_t* __restrict__ mask_c,
-                                                       const uint8_t* __restrict__ mask_f) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= int64_t(nc) * B) return;
+__device__ __forceinline__ double weight(const CsrDev& M, int k) {
+  return M.f32 ? double(static_cast<const float*>(M.val)[k]) : static_cast<const double*>(M.val)[k];
+}
+
+// d[t] = M_c sum_k R_jk (M_f r)[k], t = j*B + c
+template <int B, class X, class T>
+__device__ __forceinline__ void restrict_dof(const CsrDev& R, const X* __restrict__ r, X* __restrict__ d,
+                                             const uint8_t* __restrict__ mask_c, const uint8_t* __restrict__ mask_f,
+                                             int64_t t) {
   const int j = int(t / B), c = int(t % B);
   T acc = T(0);
   if (!mask_c[t]) {
-    for (int k = rp[j]; k < rp[j + 1]; ++k) {
-      const int64_t q = int64_t(rc[k]) * B + c;
-      if (mask_f == nullptr || !mask_f[q]) acc += T(rv[k]) * T(r[q]);
+    for (int k = R.rowptr[j]; k < R.rowptr[j + 1]; ++k) {
+      const int64_t q = int64_t(R.col[k]) * B + c;
+      if (mask_f == nullptr || !mask_f[q]) acc += T(weight(R, k)) * T(r[q]);
     }
   }
   d[t] = X(acc);
 }
 
-template <int B, class X, class T, class W>
-__global__ __launch_bounds__(kThreads) void k_prolong(int nf, const int32_t* __restrict__ pp,
-                                                      const int32_t* __restrict__ pc,
-                                                      const W* __restrict__ pv,
-                                                      const X* __restrict__ y, X* __restrict__ x,
-                                                      const uint8_t* __restrict__ mask_f,
-                                                      const uint8_t* __restrict__ mask_c) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= int64_t(nf) * B) return;
+// x[t] += M_f sum_k P_ik (M_c y)[k]
+template <int B, class X, class T>
+__device__ __forceinline__ void prolong_dof(const CsrDev& P, const X* __restrict__ y, X* __restrict__ x,
+                                            const uint8_t* __restrict__ mask_f, const uint8_t* __restrict__ mask_c,
+                                            int64_t t) {
   if (mask_f[t]) return;
   const int i = int(t / B), c = int(t % B);
   T acc = T(0);
-  for (int k = pp[i]; k < pp[i + 1]; ++k) {
-    const int64_t q = int64_t(pc[k]) * B + c;
-    if (!mask_c[q]) acc += T(pv[k]) * T(y[q]);
+  for (int k = P.rowptr[i]; k < P.rowptr[i + 1]; ++k) {
+    const int64_t q = int64_t(P.col[k]) * B + c;
+    if (!mask_c[q]) acc += T(weight(P, k)) * T(y[q]);
   }
   x[t] = X(T(x[t]) + acc);
 }
 
-template <class XI, class XO>
-__global__ __launch_bounds__(kThreads) void k_coarse_gemv(int n, const double* __restrict__ AinvT,
-                                                          const XI* __restrict__ b, XO* __restrict__ x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double acc = 0.0;
-  for (int k = 0; k < n; ++k) acc += AinvT[int64_t(k) * n + i] * double(b[k]);
-  x[i] = XO(acc);
+// ------------------------------------------------------------------ grid kernels
+template <int B, int K, class XI, class XO, class T, int MODE, bool NORM>
+__global__ __launch_bounds__(kThreads) void k_spmv(SellDev A, const XO* __restrict__ b, const XI* __restrict__ x,
+                                                   XO* __restrict__ y, const uint8_t* __restrict__ mask,
+                                                   double* __restrict__ partials) {
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const SliceLane s = slice_lane<B>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
+  const T out = spmv_slice<B, K, XI, XO, T, MODE>(A, b, x, y, mask, s);
+  if (NORM) {
+    __shared__ double lds[kMaxWaves + 1];
+    const double p = block_allsum(double(out) * double(out), lds);
+    if (threadIdx.x == 0) partials[blockIdx.x] = p;
+  }
 }
 
+template <int B, int K, class X, class T>
+__global__ __launch_bounds__(kThreads) void k_sweep(SellDev A, const X* __restrict__ S, const X* __restrict__ b,
+                                                    const X* __restrict__ x, X* __restrict__ xo, T omega) {
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const SliceLane s = slice_lane<B>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
+  sweep_slice<B, K, X, T>(A, S, b, x, xo, omega, s);
+}
+
+template <int B, class X, class T>
+__global__ __launch_bounds__(kThreads) void k_sweep0(SellDev A, const X* __restrict__ S, const X* __restrict__ b,
+                                                     X* __restrict__ xo, T omega) {
+  const SliceLane s = slice_lane<B>(A, blockIdx.x * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
+  sweep0_slice<B, X, T>(S, b, xo, omega, s);
+}
+
+template <int B, class X, class T>
+__global__ __launch_bounds__(kThreads) void k_restrict(CsrDev R, const X* __restrict__ r, X* __restrict__ d,
+                                                       const uint8_t* __restrict__ mask_c,
+                                                       const uint8_t* __restrict__ mask_f) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < int64_t(R.nrows) * B) restrict_dof<B, X, T>(R, r, d, mask_c, mask_f, t);
+}
+
+template <int B, class X, class T>
+__global__ __launch_bounds__(kThreads) void k_prolong(CsrDev P, const X* __restrict__ y, X* __restrict__ x,
+                                                      const uint8_t* __restrict__ mask_f,
+                                                      const uint8_t* __restrict__ mask_c) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < int64_t(P.nrows) * B) prolong_dof<B, X, T>(P, y, x, mask_f, mask_c, t);
+}
+
+// x = Ainv b, one wavefront per row (Ainv row-major, FP64)
+template <class XI, class XO>
+__device__ __forceinline__ void gemv_row(int n, const double* __restrict__ Ainv, const XI* __restrict__ b,
+                                         XO* __restrict__ x, int i, int lane) {
+  double acc = 0.0;
+  for (int k = lane; k < n; k += kWave) acc += Ainv[int64_t(i) * n + k] * double(b[k]);
+  acc = wave_sum(acc);
+  if (lane == 0) x[i] = XO(acc);
+}
+
+template <class XI, class XO>
+__global__ __launch_bounds__(kThreads) void k_coarse_gemv(int n, const double* __restrict__ Ainv,
+                                                          const XI* __restrict__ b, XO* __restrict__ x) {
+  const int i = blockIdx.x * kSliceWaves + threadIdx.x / kWave;
+  if (i < n) gemv_row<XI, XO>(n, Ainv, b, x, i, threadIdx.x % kWave);
+}
+
+// ------------------------------------------------------------------ tail kernel
+template <int B, int K, class X, class T>
+__device__ void tail_sweep(const TailLevel& L, const X* b, const X* x, X* xo, T omega) {
+  const int nw = blockDim.x / kWave, w = threadIdx.x / kWave, ln = threadIdx.x % kWave;
+  for (int sl = w; sl < L.A.nslices; sl += nw)
+    sweep_slice<B, K, X, T>(L.A, static_cast<const X*>(L.S), b, x, xo, omega, slice_lane<B>(L.A, sl, ln));
+  __syncthreads();
+}
+
+// Levels top .. 1 and the coarse solve of one V-cycle in a single workgroup.  Level top
+// reads its right-hand side from lv[top].b and leaves its result in lv[top].x, exactly
+// like the grid-kernel path of the host driver (same ping-pong order).
+template <int B, int K, class X, class T>
+__global__ __launch_bounds__(kTailThreads) void k_tail(const TailLevel* __restrict__ lv, TailParams p) {
+  const int nw = blockDim.x / kWave, w = threadIdx.x / kWave, ln = threadIdx.x % kWave;
+  const T omega = T(p.omega);
+  const int pre_pp = p.nu1 >= 1 ? p.nu1 - 1 : 0;
+  const int pp = pre_pp + p.nu2;
+  // descent
+  for (int l = p.top; l >= 1; --l) {
+    const TailLevel& L = lv[l];
+    X* own = static_cast<X*>(L.x);
+    X* tmp = static_cast<X*>(L.t);
+    X* cur = (pp % 2 == 0) ? own : tmp;
+    X* oth = (pp % 2 == 0) ? tmp : own;
+    const X* b = static_cast<const X*>(L.b);
+    if (p.nu1 >= 1) {
+      for (int sl = w; sl < L.A.nslices; sl += nw)
+        sweep0_slice<B, X, T>(static_cast<const X*>(L.S), b, cur, omega, slice_lane<B>(L.A, sl, ln));
+      __syncthreads();
+      for (int q = 1; q < p.nu1; ++q) {
+        tail_sweep<B, K, X, T>(L, b, cur, oth, omega);
+        X* t = cur; cur = oth; oth = t;
+      }
+    } else {
+      for (int64_t t = threadIdx.x; t < int64_t(L.A.n) * B; t += blockDim.x) cur[t] = X(0);
+      __syncthreads();
+    }
+    for (int sl = w; sl < L.A.nslices; sl += nw)
+      spmv_slice<B, K, X, X, T, 2>(L.A, b, cur, static_cast<X*>(L.r), L.mask, slice_lane<B>(L.A, sl, ln));
+    __syncthreads();
+    const TailLevel& C = lv[l - 1];
+    for (int64_t t = threadIdx.x; t < int64_t(C.A.n) * B; t += blockDim.x)
+      restrict_dof<B, X, T>(L.R, static_cast<const X*>(L.r), static_cast<X*>(C.b), C.mask, nullptr, t);
+    __syncthreads();
+  }
+  // coarse solve on level 0
+  {
+    const TailLevel& C = lv[0];
+    X* x0 = static_cast<X*>(C.x);
+    const X* b0 = static_cast<const X*>(C.b);
+    if (p.coarse_mode == 0) {
+      for (int i = w; i < p.n0; i += nw) gemv_row<X, X>(p.n0, p.Ainv, b0, x0, i, ln);
+      __syncthreads();
+    } else {
+      const int k = p.coarse_sweeps > 1 ? p.coarse_sweeps : 1;
+      X* tmp = static_cast<X*>(C.t);
+      X* cur = ((k - 1) % 2 == 0) ? x0 : tmp;
+      X* oth = ((k - 1) % 2 == 0) ? tmp : x0;
+      for (int sl = w; sl < C.A.nslices; sl += nw)
+        sweep0_slice<B, X, T>(static_cast<const X*>(C.S), b0, cur, omega, slice_lane<B>(C.A, sl, ln));
+      __syncthreads();
+      for (int q = 1; q < k; ++q) {
+        tail_sweep<B, K, X, T>(C, b0, cur, oth, omega);
+        X* t = cur; cur = oth; oth = t;
+      }
+    }
+  }
+  // ascent
+  for (int l = 1; l <= p.top; ++l) {
+    const TailLevel& L = lv[l];
+    const TailLevel& C = lv[l - 1];
+    X* own = static_cast<X*>(L.x);
+    X* tmp = static_cast<X*>(L.t);
+    X* cur = (pp % 2 == 0) ? own : tmp;
+    X* oth = (pp % 2 == 0) ? tmp : own;
+    if (pre_pp % 2 == 1) { X* t = cur; cur = oth; oth = t; }
+    for (int64_t t = threadIdx.x; t < int64_t(L.A.n) * B; t += blockDim.x)
+      prolong_dof<B, X, T>(L.P, static_cast<const X*>(C.x), cur, L.mask, C.mask, t);
+    __syncthreads();
+    for (int q = 0; q < p.nu2; ++q) {
+      tail_sweep<B, K, X, T>(L, static_cast<const X*>(L.b), cur, oth, omega);
+      X* t = cur; cur = oth; oth = t;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ setup kernels
 // Gauss-Jordan step k, part 1 (one workgroup): pivot search in column k, row swap,
 // pivot row scaled to 1 and copied to pivbuf.
 __global__ __launch_bounds__(1024) void k_gj_pivot(int n, int k, double* M, double* pivbuf, int* flag) {
   __shared__ double bv[1024];
   __shared__ int bi[1024];
+  __shared__ double spv;
   const int w = 2 * n;
   double best = -1.0;
   int arg = k;
@@ -273,7 +420,6 @@ __global__ __launch_bounds__(1024) void k_gj_pivot(int n, int k, double* M, doub
     }
     __syncthreads();
   }
-  __shared__ double spv;
   const int p = bi[0];
   if (bv[0] <= 0.0) {
     if (threadIdx.x == 0) *flag = 1;
@@ -292,17 +438,14 @@ __global__ __launch_bounds__(1024) void k_gj_pivot(int n, int k, double* M, doub
 }
 
 // Gauss-Jordan step k, part 2: eliminate column k from every other row
-__global__ __launch_bounds__(256) void k_gj_elim(int n, int k, double* M, const double* pivbuf,
-                                                 const int* flag) {
+__global__ __launch_bounds__(256) void k_gj_elim(int n, int k, double* M, const double* pivbuf, const int* flag) {
   if (*flag) return;
   const int w = 2 * n;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= int64_t(n) * w) return;
   const int i = int(t / w), c = int(t % w);
-  if (i == k) return;
-  const double f = M[int64_t(i) * w + k];
-  if (c == k) return;                   // column k cleared after the row is done
-  M[t] -= f * pivbuf[c];
+  if (i == k || c == k) return;         // column k is cleared by k_gj_clear
+  M[t] -= M[int64_t(i) * w + k] * pivbuf[c];
 }
 
 __global__ __launch_bounds__(256) void k_gj_clear(int n, int k, double* M) {
@@ -310,11 +453,11 @@ __global__ __launch_bounds__(256) void k_gj_clear(int n, int k, double* M) {
   if (i < n && i != k) M[int64_t(i) * 2 * n + k] = 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_gj_extract(int n, const double* M, double* AinvT) {
+__global__ __launch_bounds__(256) void k_gj_extract(int n, const double* M, double* Ainv) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= int64_t(n) * n) return;
-  const int i = int(t / n), j = int(t % n);          // inverse entry (i, j)
-  AinvT[int64_t(j) * n + i] = M[int64_t(i) * 2 * n + n + j];
+  const int i = int(t / n), j = int(t % n);
+  Ainv[t] = M[int64_t(i) * 2 * n + n + j];
 }
 
 template <int B, class ST>
@@ -353,6 +496,7 @@ __global__ __launch_bounds__(256) void k_block_invert(SellDev A, ST* __restrict_
     for (int cc = 0; cc < B; ++cc) S[(int64_t(slice) * B + cc) * kWave + r * B + c] = ST(m[c][B + cc]);
 }
 
+// ------------------------------------------------------------------ vector kernels
 template <class Y>
 __global__ void k_fill(int64_t n, Y* y, double v) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -380,14 +524,56 @@ __global__ void k_scale_div(int64_t n, double* __restrict__ y, const double* __r
   if (t < n) y[t] = x[t] / d;
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_dot(int64_t n, const double* __restrict__ a,
-                                                     const double* __restrict__ b, RedDev red) {
-  __shared__ double lds[kRedThreads / kWave];
+// partial sums of a.b (b == nullptr: a.a), one per block
+__global__ __launch_bounds__(kRedThreads) void k_dot_partials(int64_t n, const double* __restrict__ a,
+                                                              const double* __restrict__ b, double* __restrict__ out) {
+  __shared__ double lds[kMaxWaves + 1];
   double t = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
     t += a[i] * (b ? b[i] : a[i]);
-  const double p = block_sum(t, lds);
-  finish_reduction(p, red, lds);
+  const double s = block_allsum(t, lds);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// out = sum (or sqrt of the sum) of partials, one workgroup
+__global__ __launch_bounds__(1024) void k_finish(const double* __restrict__ p, int g, double* out, int sq) {
+  __shared__ double lds[kMaxWaves + 1];
+  const double s = sum_partials(p, g, lds);
+  if (threadIdx.x == 0) *out = sq ? sqrt(s) : s;
+}
+
+// modified Gram-Schmidt step: h = sum(pin) (= (w, v_i)), stored by block 0;
+// w -= h v_i; partial sums of (w, vnext) or, for vnext == nullptr, of (w, w)
+__global__ __launch_bounds__(kRedThreads) void k_mgs_step(int64_t n, double* __restrict__ w,
+                                                          const double* __restrict__ vi,
+                                                          const double* __restrict__ vnext,
+                                                          const double* __restrict__ pin, int gin,
+                                                          double* __restrict__ pout, double* __restrict__ hout) {
+  __shared__ double lds[kMaxWaves + 1];
+  const double h = sum_partials(pin, gin, lds);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *hout = h;
+  double t = 0.0;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double v = w[i] - h * vi[i];
+    w[i] = v;
+    t += v * (vnext ? vnext[i] : v);
+  }
+  const double s = block_allsum(t, lds);
+  if (threadIdx.x == 0) pout[blockIdx.x] = s;
+}
+
+// nrm = sqrt(sum(pin)), stored by block 0; w /= nrm (unless nrm == 0)
+__global__ __launch_bounds__(kRedThreads) void k_mgs_normalize(int64_t n, double* __restrict__ w,
+                                                               const double* __restrict__ pin, int gin,
+                                                               double* __restrict__ hout) {
+  __shared__ double lds[kMaxWaves + 1];
+  const double nrm = sqrt(sum_partials(pin, gin, lds));
+  if (blockIdx.x == 0 && threadIdx.x == 0) *hout = nrm;
+  if (nrm == 0.0) return;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) w[i] = w[i] / nrm;
 }
 
 template <class Z>
@@ -436,45 +622,46 @@ __global__ void k_init_g(int m, double* g, const double* beta) {
   if (t <= m) g[t] = (t == 0) ? *beta : 0.0;
 }
 
+// ------------------------------------------------------------------ launch helpers
 inline unsigned grid_for(int64_t n, int threads) { return unsigned((n + threads - 1) / threads); }
 inline unsigned slice_grid(int nslices) { return unsigned((nslices + kSliceWaves - 1) / kSliceWaves); }
 
-inline RedDev null_red() { return RedDev{}; }
-
 template <int B, int K, class XI, class XO, class T>
-hipError_t spmv_t(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask,
-                  int mode, const RedDev* red, hipStream_t s) {
+hipError_t spmv_t(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask, int mode,
+                  double* partials, hipStream_t s) {
   const unsigned g = slice_grid(A.nslices);
   if (g == 0) return hipSuccess;
   const XO* bb = static_cast<const XO*>(b);
   const XI* xx = static_cast<const XI*>(x);
   XO* yy = static_cast<XO*>(y);
-  const RedDev rd = red ? *red : null_red();
-  if (red) {
-    if (mode == 0) hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, 0, true>), g, kThreads, 0, s, A, bb, xx, yy, mask, rd);
-    else if (mode == 1) hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, 1, true>), g, kThreads, 0, s, A, bb, xx, yy, mask, rd);
-    else hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, 2, true>), g, kThreads, 0, s, A, bb, xx, yy, mask, rd);
+#define MGQ1_SPMV(MODE, NORM) \
+  hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, MODE, NORM>), g, kThreads, 0, s, A, bb, xx, yy, mask, partials)
+  if (partials) {
+    if (mode == 0) MGQ1_SPMV(0, true);
+    else if (mode == 1) MGQ1_SPMV(1, true);
+    else MGQ1_SPMV(2, true);
   } else {
-    if (mode == 0) hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, 0, false>), g, kThreads, 0, s, A, bb, xx, yy, mask, rd);
-    else if (mode == 1) hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, 1, false>), g, kThreads, 0, s, A, bb, xx, yy, mask, rd);
-    else hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, 2, false>), g, kThreads, 0, s, A, bb, xx, yy, mask, rd);
+    if (mode == 0) MGQ1_SPMV(0, false);
+    else if (mode == 1) MGQ1_SPMV(1, false);
+    else MGQ1_SPMV(2, false);
   }
+#undef MGQ1_SPMV
   return hipGetLastError();
 }
 
 template <int B>
-hipError_t spmv_b(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask, int xk,
-                  int yk, int mode, const RedDev* red, hipStream_t s) {
+hipError_t spmv_b(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask, int xk, int yk,
+                  int mode, double* partials, hipStream_t s) {
   if (A.kind == VK_F64) {
-    if (xk == X_F64 && yk == X_F64) return spmv_t<B, VK_F64, double, double, double>(A, b, x, y, mask, mode, red, s);
-    if (xk == X_F32 && yk == X_F64) return spmv_t<B, VK_F64, float, double, double>(A, b, x, y, mask, mode, red, s);
+    if (xk == X_F64 && yk == X_F64) return spmv_t<B, VK_F64, double, double, double>(A, b, x, y, mask, mode, partials, s);
+    if (xk == X_F32 && yk == X_F64) return spmv_t<B, VK_F64, float, double, double>(A, b, x, y, mask, mode, partials, s);
     return hipErrorInvalidValue;
   }
   if (xk != X_F32 || yk != X_F32) return hipErrorInvalidValue;
   switch (A.kind) {
-    case VK_F32: return spmv_t<B, VK_F32, float, float, float>(A, b, x, y, mask, mode, red, s);
-    case VK_F16: return spmv_t<B, VK_F16, float, float, float>(A, b, x, y, mask, mode, red, s);
-    case VK_BF16: return spmv_t<B, VK_BF16, float, float, float>(A, b, x, y, mask, mode, red, s);
+    case VK_F32: return spmv_t<B, VK_F32, float, float, float>(A, b, x, y, mask, mode, partials, s);
+    case VK_F16: return spmv_t<B, VK_F16, float, float, float>(A, b, x, y, mask, mode, partials, s);
+    case VK_BF16: return spmv_t<B, VK_BF16, float, float, float>(A, b, x, y, mask, mode, partials, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -498,50 +685,66 @@ hipError_t sweep_t(const SellDev& A, const void* S, const void* b, const void* x
   return hipGetLastError();
 }
 
-template <int B, class X, class T, class W>
+template <int B, class X, class T>
 hipError_t transfer_t(bool restrict_op, const CsrDev& M, const void* in, void* out, const uint8_t* m1,
                       const uint8_t* m2, hipStream_t s) {
   const int64_t n = int64_t(M.nrows) * B;
   if (n == 0) return hipSuccess;
   const unsigned g = grid_for(n, kThreads);
-  const W* w = static_cast<const W*>(M.val);
   if (restrict_op)
-    hipLaunchKernelGGL((k_restrict<B, X, T, W>), g, kThreads, 0, s, M.nrows, M.rowptr, M.col, w,
-                       static_cast<const X*>(in), static_cast<X*>(out), m1, m2);
+    hipLaunchKernelGGL((k_restrict<B, X, T>), g, kThreads, 0, s, M, static_cast<const X*>(in), static_cast<X*>(out),
+                       m1, m2);
   else
-    hipLaunchKernelGGL((k_prolong<B, X, T, W>), g, kThreads, 0, s, M.nrows, M.rowptr, M.col, w,
-                       static_cast<const X*>(in), static_cast<X*>(out), m1, m2);
+    hipLaunchKernelGGL((k_prolong<B, X, T>), g, kThreads, 0, s, M, static_cast<const X*>(in), static_cast<X*>(out),
+                       m1, m2);
   return hipGetLastError();
 }
 
 template <int B>
 hipError_t transfer_b(bool restrict_op, const CsrDev& M, const void* in, void* out, const uint8_t* m1,
                       const uint8_t* m2, int xk, hipStream_t s) {
-  if (xk == X_F64)
-    return M.f32 ? transfer_t<B, double, double, float>(restrict_op, M, in, out, m1, m2, s)
-                 : transfer_t<B, double, double, double>(restrict_op, M, in, out, m1, m2, s);
-  return M.f32 ? transfer_t<B, float, float, float>(restrict_op, M, in, out, m1, m2, s)
-               : transfer_t<B, float, float, double>(restrict_op, M, in, out, m1, m2, s);
+  if (xk == X_F64) return transfer_t<B, double, double>(restrict_op, M, in, out, m1, m2, s);
+  return transfer_t<B, float, float>(restrict_op, M, in, out, m1, m2, s);
 }
 
-#define MGQ1_DISPATCH_B(B, CALL)                       \
-  switch (B) {                                         \
-    case 1: return CALL<1>;                            \
-    case 2: return CALL<2>;                            \
-    case 3: return CALL<3>;                            \
-    case 4: return CALL<4>;                            \
-    default: return hipErrorInvalidValue;              \
+template <int B, int K, class X, class T>
+hipError_t tail_t(const TailLevel* lv, const TailParams& p, hipStream_t s) {
+  hipLaunchKernelGGL((k_tail<B, K, X, T>), 1, kTailThreads, 0, s, lv, p);
+  return hipGetLastError();
+}
+
+template <int B>
+hipError_t tail_b(const TailLevel* lv, int kind, int xk, const TailParams& p, hipStream_t s) {
+  if (xk == X_F64) {
+    if (kind != VK_F64) return hipErrorInvalidValue;
+    return tail_t<B, VK_F64, double, double>(lv, p, s);
   }
+  switch (kind) {
+    case VK_F32: return tail_t<B, VK_F32, float, float>(lv, p, s);
+    case VK_F16: return tail_t<B, VK_F16, float, float>(lv, p, s);
+    case VK_BF16: return tail_t<B, VK_BF16, float, float>(lv, p, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+inline unsigned vec_grid(int64_t n) {
+  unsigned g = grid_for(n, kRedThreads);
+  if (g > unsigned(kMaxRedBlocks)) g = kMaxRedBlocks;
+  return g ? g : 1;
+}
 
 }  // namespace
 
-hipError_t launch_spmv(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask, int xk,
-                       int yk, int mode, const RedDev* red, hipStream_t s) {
+int reduction_grid(int64_t n) { return int(vec_grid(n)); }
+int spmv_grid(const SellDev& A) { return int(slice_grid(A.nslices)); }
+
+hipError_t launch_spmv(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask, int xk, int yk,
+                       int mode, double* partials, hipStream_t s) {
   switch (A.B) {
-    case 1: return spmv_b<1>(A, b, x, y, mask, xk, yk, mode, red, s);
-    case 2: return spmv_b<2>(A, b, x, y, mask, xk, yk, mode, red, s);
-    case 3: return spmv_b<3>(A, b, x, y, mask, xk, yk, mode, red, s);
-    case 4: return spmv_b<4>(A, b, x, y, mask, xk, yk, mode, red, s);
+    case 1: return spmv_b<1>(A, b, x, y, mask, xk, yk, mode, partials, s);
+    case 2: return spmv_b<2>(A, b, x, y, mask, xk, yk, mode, partials, s);
+    case 3: return spmv_b<3>(A, b, x, y, mask, xk, yk, mode, partials, s);
+    case 4: return spmv_b<4>(A, b, x, y, mask, xk, yk, mode, partials, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -572,12 +775,11 @@ static hipError_t sweep0_b(const SellDev& A, const void* S, const void* b, void*
   const unsigned g = slice_grid(A.nslices);
   if (g == 0) return hipSuccess;
   if (xk == X_F64)
-    hipLaunchKernelGGL((k_sweep0<B, double, double>), g, kThreads, 0, s, A.n, A.nslices,
-                       static_cast<const double*>(S), static_cast<const double*>(b), static_cast<double*>(xo), omega);
+    hipLaunchKernelGGL((k_sweep0<B, double, double>), g, kThreads, 0, s, A, static_cast<const double*>(S),
+                       static_cast<const double*>(b), static_cast<double*>(xo), omega);
   else
-    hipLaunchKernelGGL((k_sweep0<B, float, float>), g, kThreads, 0, s, A.n, A.nslices,
-                       static_cast<const float*>(S), static_cast<const float*>(b), static_cast<float*>(xo),
-                       float(omega));
+    hipLaunchKernelGGL((k_sweep0<B, float, float>), g, kThreads, 0, s, A, static_cast<const float*>(S),
+                       static_cast<const float*>(b), static_cast<float*>(xo), float(omega));
   return hipGetLastError();
 }
 
@@ -614,26 +816,36 @@ hipError_t launch_prolong(const CsrDev& P, int B, const void* y, void* x, const 
   }
 }
 
-hipError_t launch_coarse_gemv(int n, const double* AinvT, const void* b, void* x, int xk, hipStream_t s) {
+hipError_t launch_tail(const TailLevel* lv, int B, int kind, int xk, const TailParams& p, hipStream_t s) {
+  switch (B) {
+    case 1: return tail_b<1>(lv, kind, xk, p, s);
+    case 2: return tail_b<2>(lv, kind, xk, p, s);
+    case 3: return tail_b<3>(lv, kind, xk, p, s);
+    case 4: return tail_b<4>(lv, kind, xk, p, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_coarse_gemv(int n, const double* Ainv, const void* b, void* x, int xk, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const unsigned g = grid_for(n, kThreads);
+  const unsigned g = grid_for(n, kSliceWaves);
   if (xk == X_F64)
-    hipLaunchKernelGGL((k_coarse_gemv<double, double>), g, kThreads, 0, s, n, AinvT,
-                       static_cast<const double*>(b), static_cast<double*>(x));
+    hipLaunchKernelGGL((k_coarse_gemv<double, double>), g, kThreads, 0, s, n, Ainv, static_cast<const double*>(b),
+                       static_cast<double*>(x));
   else
-    hipLaunchKernelGGL((k_coarse_gemv<float, float>), g, kThreads, 0, s, n, AinvT,
-                       static_cast<const float*>(b), static_cast<float*>(x));
+    hipLaunchKernelGGL((k_coarse_gemv<float, float>), g, kThreads, 0, s, n, Ainv, static_cast<const float*>(b),
+                       static_cast<float*>(x));
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_invert(int n, double* M, double* AinvT, double* pivbuf, int* flag, hipStream_t s) {
+hipError_t launch_coarse_invert(int n, double* M, double* Ainv, double* pivbuf, int* flag, hipStream_t s) {
   const int64_t tot = int64_t(n) * 2 * n;
   for (int k = 0; k < n; ++k) {
     hipLaunchKernelGGL(k_gj_pivot, 1, 1024, 0, s, n, k, M, pivbuf, flag);
     hipLaunchKernelGGL(k_gj_elim, grid_for(tot, 256), 256, 0, s, n, k, M, pivbuf, flag);
     hipLaunchKernelGGL(k_gj_clear, grid_for(n, 256), 256, 0, s, n, k, M);
   }
-  hipLaunchKernelGGL(k_gj_extract, grid_for(int64_t(n) * n, 256), 256, 0, s, n, M, AinvT);
+  hipLaunchKernelGGL(k_gj_extract, grid_for(int64_t(n) * n, 256), 256, 0, s, n, M, Ainv);
   return hipGetLastError();
 }
 
@@ -694,21 +906,26 @@ hipError_t launch_scale_div(int64_t n, double* y, const double* x, const double*
   return hipGetLastError();
 }
 
-static unsigned red_grid(int64_t n) {
-  unsigned g = grid_for(n, kRedThreads);
-  if (g > unsigned(kMaxRedBlocks)) g = kMaxRedBlocks;
-  return g ? g : 1;
-}
-
-hipError_t launch_dot(int64_t n, const double* a, const double* b, const RedDev& red, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot, red_grid(n), kRedThreads, 0, s, n, a, b, red);
+hipError_t launch_dot_partials(int64_t n, const double* a, const double* b, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_partials, vec_grid(n), kRedThreads, 0, s, n, a, b, partials);
   return hipGetLastError();
 }
 
-hipError_t launch_nrm2(int64_t n, const double* a, const RedDev& red, hipStream_t s) {
-  RedDev r = red;
-  r.sqrt_out = 1;
-  hipLaunchKernelGGL(k_dot, red_grid(n), kRedThreads, 0, s, n, a, static_cast<const double*>(nullptr), r);
+hipError_t launch_finish(const double* partials, int g, double* out, int sqrt_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish, 1, 1024, 0, s, partials, g, out, sqrt_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mgs_step(int64_t n, double* w, const double* vi, const double* vnext, const double* pin,
+                           double* pout, double* hout, hipStream_t s) {
+  const unsigned g = vec_grid(n);
+  hipLaunchKernelGGL(k_mgs_step, g, kRedThreads, 0, s, n, w, vi, vnext, pin, int(g), pout, hout);
+  return hipGetLastError();
+}
+
+hipError_t launch_mgs_normalize(int64_t n, double* w, const double* pin, double* hout, hipStream_t s) {
+  const unsigned g = vec_grid(n);
+  hipLaunchKernelGGL(k_mgs_normalize, g, kRedThreads, 0, s, n, w, pin, int(g), hout);
   return hipGetLastError();
 }
 

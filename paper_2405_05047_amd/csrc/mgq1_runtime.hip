@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -270,8 +271,10 @@ struct mg_handle {
   int L = 0;
   int xk = X_F64;         // vector kind inside the cycle
   std::vector<LevelDev> lv;
-  double* AinvT = nullptr;
+  double* Ainv = nullptr; // coarse inverse, row-major
   int n0 = 0;
+  int tail_top = -1;      // levels 0..tail_top run in the single-workgroup tail kernel
+  TailLevel* dtail = nullptr;
   // outer loop
   double* V = nullptr;    // (m+1) x N_L FP64
   void* Z = nullptr;      // m x N_L, cycle precision
@@ -280,12 +283,17 @@ struct mg_handle {
   void* bcyc = nullptr;   // cycle-precision copy of the cycle input (mixed mode)
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
   double* dsc = nullptr;  // device scalars: [0] norm, [1] one, [2..3] givens status
-  double* partials = nullptr;
-  unsigned* counter = nullptr;
+  double* pbig = nullptr; // per-block partials of the outer defect norm
+  double* pv[2] = {nullptr, nullptr};   // per-block partials of the vector reductions
   int* dflag = nullptr;
   double* hs = nullptr;   // pinned host scalars
+  hipStream_t cap = nullptr;             // private stream used only to capture graphs
+  std::vector<hipGraphExec_t> step_graph; // FGMRES step j (V-cycle, SpMV, MGS, Givens)
   std::vector<void*> allocs;
   ~mg_handle() {
+    for (hipGraphExec_t g : step_graph)
+      if (g) (void)hipGraphExecDestroy(g);
+    if (cap) (void)hipStreamDestroy(cap);
     for (void* p : allocs) (void)hipFree(p);
     if (hs) (void)hipHostFree(hs);
   }
@@ -389,14 +397,6 @@ int upload_csr(mg_handle* h, const CsrHost& C, CsrDev& D, hipStream_t s) {
   return MG_OK;
 }
 
-RedDev red_of(mg_handle* h, double* out) {
-  RedDev r;
-  r.partials = h->partials;
-  r.counter = h->counter;
-  r.out = out;
-  return r;
-}
-
 // ---------------------------------------------------------------- V-cycle
 int smooth_level(mg_handle* h, int l, const void* b, void*& cur, void*& other, int sweeps, hipStream_t s) {
   LevelDev& L = h->lv[l];
@@ -407,14 +407,18 @@ int smooth_level(mg_handle* h, int l, const void* b, void*& cur, void*& other, i
   return MG_OK;
 }
 
-// x = GMG(L, 0, b) with b, x in cycle precision; x must not alias b
+// x = GMG(L, 0, b) with b, x in cycle precision; x must not alias b.
+// Levels above tail_top use grid-wide kernels; levels 0..tail_top run in one
+// single-workgroup launch (same steps, same order of ping-pong buffers).
 int vcycle_cycle(mg_handle* h, const void* bL, void* xL, hipStream_t s) {
   const int L = h->L;
   const mg_config& c = h->cfg;
+  const int top = h->tail_top;
   std::vector<const void*> bb(L + 1);
   std::vector<void*> cur(L + 1), oth(L + 1);
   for (int l = 0; l <= L; ++l) bb[l] = h->lv[l].b;
   bb[L] = bL;
+  const int pre_pp = c.nu1 >= 1 ? c.nu1 - 1 : 0;
   // choose the first buffer so that the ping-pong ends in the level's own x (or xL)
   auto first_buffers = [&](int l, int pingpongs) {
     void* own = (l == L) ? xL : h->lv[l].x;
@@ -422,9 +426,8 @@ int vcycle_cycle(mg_handle* h, const void* bL, void* xL, hipStream_t s) {
     if (pingpongs % 2 == 0) { cur[l] = own; oth[l] = tmp; }
     else { cur[l] = tmp; oth[l] = own; }
   };
-  for (int l = L; l >= 1; --l) {
+  for (int l = L; l > top; --l) {
     LevelDev& Lv = h->lv[l];
-    const int pre_pp = c.nu1 >= 1 ? c.nu1 - 1 : 0;
     first_buffers(l, pre_pp + c.nu2);
     if (c.nu1 >= 1) {
       MG_HIP(launch_sweep0(Lv.Ac, Lv.S, bb[l], cur[l], c.omega, h->xk, s));
@@ -436,21 +439,42 @@ int vcycle_cycle(mg_handle* h, const void* bL, void* xL, hipStream_t s) {
     MG_HIP(launch_spmv(Lv.Ac, bb[l], cur[l], Lv.r, Lv.mask, h->xk, h->xk, 2, nullptr, s));
     MG_HIP(launch_restrict(Lv.R, Lv.B, Lv.r, h->lv[l - 1].b, h->lv[l - 1].mask, nullptr, h->xk, s));
   }
-  LevelDev& C0 = h->lv[0];
-  void* x0 = (L == 0) ? xL : C0.x;
-  if (c.coarse_mode == MG_COARSE_EXACT) {
-    MG_HIP(launch_coarse_gemv(h->n0, h->AinvT, bb[0], x0, h->xk, s));
+  if (top == 0) {
+    // coarse solve with grid-wide kernels: one wavefront per row of the dense inverse
+    LevelDev& C0 = h->lv[0];
+    void* x0 = (L == 0) ? xL : C0.x;
+    if (c.coarse_mode == MG_COARSE_EXACT) {
+      MG_HIP(launch_coarse_gemv(h->n0, h->Ainv, bb[0], x0, h->xk, s));
+    } else {
+      const int k = std::max(1, c.coarse_sweeps);
+      void* cu = ((k - 1) % 2 == 0) ? x0 : C0.t;
+      void* ot = ((k - 1) % 2 == 0) ? C0.t : x0;
+      MG_HIP(launch_sweep0(C0.Ac, C0.S, bb[0], cu, c.omega, h->xk, s));
+      int rc = smooth_level(h, 0, bb[0], cu, ot, k - 1, s);
+      if (rc) return rc;
+    }
+    if (L == 0) return MG_OK;
   } else {
-    const int k = std::max(1, c.coarse_sweeps);
-    void* cu = ((k - 1) % 2 == 0) ? x0 : C0.t;
-    void* ot = ((k - 1) % 2 == 0) ? C0.t : x0;
-    MG_HIP(launch_sweep0(C0.Ac, C0.S, bb[0], cu, c.omega, h->xk, s));
-    int rc = smooth_level(h, 0, bb[0], cu, ot, k - 1, s);
-    if (rc) return rc;
+    // the tail reads level top's right-hand side from its own b and leaves x in its own x
+    if (top == L) MG_HIP(launch_convert(h->lv[L].N, bL, h->xk, h->lv[L].b, h->xk, s));
+    TailParams tp;
+    tp.top = top;
+    tp.nu1 = c.nu1;
+    tp.nu2 = c.nu2;
+    tp.omega = c.omega;
+    tp.Ainv = h->Ainv;
+    tp.n0 = h->n0;
+    tp.coarse_mode = c.coarse_mode;
+    tp.coarse_sweeps = c.coarse_sweeps;
+    MG_HIP(launch_tail(h->dtail, h->lv[0].B, h->lv[0].Ac.kind, h->xk, tp, s));
+    if (top == L) {
+      MG_HIP(launch_convert(h->lv[L].N, h->lv[L].x, h->xk, xL, h->xk, s));
+      return MG_OK;
+    }
   }
-  for (int l = 1; l <= L; ++l) {
+  for (int l = top + 1; l <= L; ++l) {
     LevelDev& Lv = h->lv[l];
-    const void* y = (l - 1 == 0) ? x0 : cur[l - 1];
+    const void* y = (l - 1 == top) ? h->lv[top].x : cur[l - 1];
     MG_HIP(launch_prolong(Lv.P, Lv.B, y, cur[l], Lv.mask, h->lv[l - 1].mask, h->xk, s));
     int rc = smooth_level(h, l, bb[l], cur[l], oth[l], c.nu2, s);
     if (rc) return rc;
@@ -474,10 +498,59 @@ int read_scalars(mg_handle* h, const double* d, int k, hipStream_t s) {
 // r = b - A x, h->hs[0] = ||r||
 int outer_defect(mg_handle* h, const double* b, const double* x, hipStream_t s) {
   LevelDev& T = h->lv[h->L];
-  RedDev red = red_of(h, h->dsc + 0);
-  red.sqrt_out = 1;
-  MG_HIP(launch_spmv(T.A64, b, x, h->rout, nullptr, X_F64, X_F64, 1, &red, s));
+  MG_HIP(launch_spmv(T.A64, b, x, h->rout, nullptr, X_F64, X_F64, 1, h->pbig, s));
+  MG_HIP(launch_finish(h->pbig, spmv_grid(T.A64), h->dsc + 0, 1, s));
   return read_scalars(h, h->dsc, 1, s);
+}
+
+// One FGMRES step j on internal buffers: z_j = V(v_j), w = A z_j, modified Gram-Schmidt
+// against v_0..v_j (Sec. 4.2), v_{j+1} = w / ||w||, Givens rotation j.
+int enqueue_fgmres_step(mg_handle* h, int j, hipStream_t s) {
+  const int m = h->cfg.gmres_m;
+  LevelDev& T = h->lv[h->L];
+  const int64_t N = T.N;
+  double* vj = h->V + int64_t(j) * N;
+  double* w = h->V + int64_t(j + 1) * N;
+  void* zj = static_cast<char*>(h->Z) + size_t(j) * N * xsize(h->xk);
+  int rc;
+  if ((rc = precond(h, vj, zj, s))) return rc;
+  MG_HIP(launch_spmv(T.A64, nullptr, zj, w, nullptr, h->xk, X_F64, 0, nullptr, s));
+  double* Hj = h->H + int64_t(j) * (m + 1);
+  // each step subtracts the projection on v_i and forms the partial dot products with
+  // v_{i+1} (or with w itself after the last step)
+  MG_HIP(launch_dot_partials(N, w, h->V, h->pv[0], s));
+  for (int i = 0; i <= j; ++i) {
+    const double* vi = h->V + int64_t(i) * N;
+    const double* vn = (i < j) ? h->V + int64_t(i + 1) * N : nullptr;
+    MG_HIP(launch_mgs_step(N, w, vi, vn, h->pv[i & 1], h->pv[(i + 1) & 1], Hj + i, s));
+  }
+  MG_HIP(launch_mgs_normalize(N, w, h->pv[(j + 1) & 1], Hj + j + 1, s));
+  MG_HIP(launch_givens(j, m, h->H, h->cs, h->sn, h->g, h->dsc + 2, s));
+  return MG_OK;
+}
+
+// enqueue step j on the caller's stream: replay its captured graph (captured on first
+// use on a private stream) or launch the kernels directly
+int fgmres_step(mg_handle* h, int j, hipStream_t s) {
+  if (!h->cfg.use_graph) return enqueue_fgmres_step(h, j, s);
+  if (!h->step_graph[j]) {
+    hipGraph_t g = nullptr;
+    MG_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_fgmres_step(h, j, h->cap);
+    const hipError_t e = hipStreamEndCapture(h->cap, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(MG_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) return fail(MG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+    h->step_graph[j] = ex;
+  }
+  MG_HIP(hipGraphLaunch(h->step_graph[j], s));
+  return MG_OK;
 }
 
 int solve_impl(mg_handle* h, const double* b, double* x, mg_solve_stats* st, void* stream, int fixed) {
@@ -489,11 +562,9 @@ int solve_impl(mg_handle* h, const double* b, double* x, mg_solve_stats* st, voi
   mg_solve_stats S{};
   int rc;
   // ||b||
-  {
-    RedDev red = red_of(h, h->dsc + 0);
-    MG_HIP(launch_nrm2(N, b, red, s));
-    if ((rc = read_scalars(h, h->dsc, 1, s))) return rc;
-  }
+  MG_HIP(launch_dot_partials(N, b, nullptr, h->pv[0], s));
+  MG_HIP(launch_finish(h->pv[0], reduction_grid(N), h->dsc + 0, 1, s));
+  if ((rc = read_scalars(h, h->dsc, 1, s))) return rc;
   const double bn = h->hs[0];
   const double tol = c.rtol * bn;
   const int limit = fixed > 0 ? fixed : c.maxit;
@@ -514,7 +585,6 @@ int solve_impl(mg_handle* h, const double* b, double* x, mg_solve_stats* st, voi
     }
   } else {
     const int m = c.gmres_m;
-    const size_t zs = xsize(h->xk);
     while (true) {
       if (!std::isfinite(beta) || beta > 1e6 * std::max(S.res0, 1e-300)) { status = MG_ENUMERIC; break; }
       if (fixed <= 0 && beta <= tol) { S.converged = 1; break; }
@@ -523,24 +593,8 @@ int solve_impl(mg_handle* h, const double* b, double* x, mg_solve_stats* st, voi
       MG_HIP(launch_init_g(m, h->g, h->dsc + 0, s));
       int k = 0;
       for (int j = 0; j < m; ++j) {
-        double* vj = h->V + int64_t(j) * N;
-        double* w = h->V + int64_t(j + 1) * N;
-        void* zj = static_cast<char*>(h->Z) + size_t(j) * N * zs;
-        if ((rc = precond(h, vj, zj, s))) return rc;
+        if ((rc = fgmres_step(h, j, s))) return rc;
         ++S.iters;
-        MG_HIP(launch_spmv(T.A64, nullptr, zj, w, nullptr, h->xk, X_F64, 0, nullptr, s));
-        double* Hj = h->H + int64_t(j) * (m + 1);
-        for (int i = 0; i <= j; ++i) {           // modified Gram-Schmidt
-          const double* vi = h->V + int64_t(i) * N;
-          MG_HIP(launch_dot(N, w, vi, red_of(h, Hj + i), s));
-          MG_HIP(launch_axpy(N, w, X_F64, vi, X_F64, -1.0, Hj + i, s));
-        }
-        {
-          RedDev red = red_of(h, Hj + j + 1);
-          MG_HIP(launch_nrm2(N, w, red, s));
-        }
-        MG_HIP(launch_scale_div(N, w, w, Hj + j + 1, s));
-        MG_HIP(launch_givens(j, m, h->H, h->cs, h->sn, h->g, h->dsc + 2, s));
         if ((rc = read_scalars(h, h->dsc + 2, 2, s))) return rc;
         k = j + 1;
         const double est = h->hs[0];
@@ -690,8 +744,8 @@ int mg_setup_hierarchy(const mg_level_in* lv, int32_t n_levels, const mg_config*
       if ((rc = upload(h, &dM, M, s))) return bail(rc);
       MG_HIP(hipStreamSynchronize(s));
       if ((rc = dalloc(h, &piv, size_t(2) * n0))) return bail(rc);
-      if ((rc = dalloc(h, &h->AinvT, size_t(n0) * n0))) return bail(rc);
-      MG_HIP(launch_coarse_invert(n0, dM, h->AinvT, piv, flag, s));
+      if ((rc = dalloc(h, &h->Ainv, size_t(n0) * n0))) return bail(rc);
+      MG_HIP(launch_coarse_invert(n0, dM, h->Ainv, piv, flag, s));
     }
     int hflag = 0;
     MG_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -719,12 +773,41 @@ int mg_setup_hierarchy(const mg_level_in* lv, int32_t n_levels, const mg_config*
     if ((rc = dalloc(h, &h->dsc, 8))) return bail(rc);
     MG_HIP(launch_fill(8, h->dsc, X_F64, 0.0, s));
     MG_HIP(launch_fill(1, h->dsc + 1, X_F64, 1.0, s));
-    int64_t maxgrid = kMaxRedBlocks;
-    for (const LevelDev& D : h->lv) maxgrid = std::max<int64_t>(maxgrid, (D.A64.nslices + kSliceWaves - 1) / kSliceWaves);
-    if ((rc = dalloc(h, &h->partials, size_t(maxgrid)))) return bail(rc);
-    if ((rc = dalloc(h, &h->counter, 1))) return bail(rc);
-    MG_HIP(hipMemsetAsync(h->counter, 0, sizeof(unsigned), s));
+    int64_t maxgrid = 1;
+    for (const LevelDev& D : h->lv) maxgrid = std::max<int64_t>(maxgrid, spmv_grid(D.A64));
+    if ((rc = dalloc(h, &h->pbig, size_t(maxgrid)))) return bail(rc);
+    for (int q = 0; q < 2; ++q)
+      if ((rc = dalloc(h, &h->pv[q], size_t(kMaxRedBlocks)))) return bail(rc);
+    // tail: every level up to the largest one with at most tail_dofs unknowns
+    {
+      // default off: on MI355X one workgroup walking several levels was measured slower
+      // (dependent-load latency serialises) than separate grid launches per step
+      int64_t tail_dofs = 0;
+      if (const char* e = std::getenv("MGQ1_TAIL_DOFS")) tail_dofs = std::atoll(e);
+      int top = 0;
+      for (int l = 1; l <= h->L; ++l)
+        if (h->lv[l].N <= tail_dofs) top = l;
+      h->tail_top = top;
+      std::vector<TailLevel> tl(top + 1);
+      for (int l = 0; l <= top; ++l) {
+        const LevelDev& D = h->lv[l];
+        tl[l].A = D.Ac;
+        tl[l].S = D.S;
+        tl[l].mask = D.mask;
+        tl[l].P = D.P;
+        tl[l].R = D.R;
+        tl[l].x = D.x;
+        tl[l].b = D.b;
+        tl[l].r = D.r;
+        tl[l].t = D.t;
+      }
+      if ((rc = dalloc(h, &h->dtail, tl.size()))) return bail(rc);
+      MG_HIP(hipMemcpyAsync(h->dtail, tl.data(), tl.size() * sizeof(TailLevel), hipMemcpyHostToDevice, s));
+      MG_HIP(hipStreamSynchronize(s));
+    }
     MG_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hs), 16 * sizeof(double), hipHostMallocDefault));
+    h->step_graph.assign(size_t(m), nullptr);
+    if (c.use_graph) MG_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     MG_HIP(hipStreamSynchronize(s));
   } catch (const std::bad_alloc&) {
     return bail(fail(MG_ENOMEM, "host allocation failed"));
@@ -812,7 +895,7 @@ int mg_coarse_solve(mg_handle* h, const double* b, double* x, void* stream) {
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (h->cfg.coarse_mode == MG_COARSE_EXACT) {
-    MG_HIP(launch_coarse_gemv(h->n0, h->AinvT, b, x, X_F64, s));
+    MG_HIP(launch_coarse_gemv(h->n0, h->Ainv, b, x, X_F64, s));
     return MG_OK;
   }
   LevelDev& C0 = h->lv[0];

@@ -185,6 +185,10 @@ def build(wl: W.Workload, nrhs: int = 1) -> Problem:
                 hang_weight=_arr(v.hang_weight, 4 * v.n_hanging, np.float64).reshape(-1, 4),
                 lattice=_arr(v.node_lattice, 3 * n, np.int32).reshape(n, 3),
                 max_depth=v.max_depth))
+        # the coarse mesh may be any level of the hierarchy; drop the levels below it
+        levels = levels[min(wl.coarse_level, len(levels) - 1):]
+        levels[0].p_rowptr = levels[0].p_col = levels[0].p_val = None
+        levels[0].p_cols = 0
         top = levels[-1]
         if wl.rhs == W.RHS_NOISE:
             xi = np.ascontiguousarray(W.noise(wl.seed, top.n, nrhs))

@@ -144,7 +144,7 @@ def config_from(wl: W.Workload, precision="fp64", **over) -> Config:
     c.gmres_m = over.get("gmres_m", wl.gmres_m)
     c.maxit = over.get("maxit", wl.maxit)
     c.rtol = over.get("rtol", wl.rtol)
-    c.use_graph = 0
+    c.use_graph = over.get("use_graph", 1)
     return c
 
 

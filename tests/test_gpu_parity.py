@@ -34,6 +34,8 @@ CASES = {
     "oseen17": W.c4_oseen(3),
     "edge4": W.c3_adaptive("edge", 4),
     "oseen_tall": W.c4_oseen(2, tall=True),
+    "td_band_cl3": W.c2_td(band_rounds=3, uniform_rounds=1).with_(coarse_level=3),
+    "elast17_cl2": W.c3_elasticity(3).with_(coarse_level=2),
 }
 
 _cache = {}
@@ -218,3 +220,37 @@ def test_mixed_precision_reaches_fp64_tolerance(name, prec):
     assert st["converged"] == 1
     assert res <= wl.rtol * np.linalg.norm(o.b) * (1 + 1e-9)
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["td_band", "elast17", "oseen17"])
+def test_tail_kernel_parity(name, monkeypatch):
+    """The optional single-workgroup tail (levels below MGQ1_TAIL_DOFS in one launch)
+    computes the same V-cycle."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    monkeypatch.setenv("MGQ1_TAIL_DOFS", "100000")
+    h = mg.Hierarchy(p.levels, mg.config_from(wl))
+    ref = mgo.vcycle(o.b)
+    x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+    h.vcycle(dev(o.b), x)
+    assert np.abs(host(x) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", ["td_band", "oseen17", "td_band_cl3"])
+def test_graph_and_eager_agree(name):
+    """FGMRES with the captured per-step graphs gives the same result bit for bit as the
+    eager launches, also on repeated calls."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    he = mg.Hierarchy(p.levels, mg.config_from(wl, use_graph=0))
+    hg = mg.Hierarchy(p.levels, mg.config_from(wl, use_graph=1))
+    b = dev(o.b)
+    xe = torch.zeros_like(b)
+    st_e = he.solve(b, xe)
+    ge = host(xe)
+    for rep in range(3):
+        xg = torch.zeros_like(b)
+        st_g = hg.solve(b, xg)
+        torch.cuda.synchronize()
+        assert st_g["iters"] == st_e["iters"]
+        assert np.array_equal(host(xg), ge), rep

@@ -72,6 +72,10 @@ class Workload:
     maxit: int = 200
     coarse_mode: int = COARSE_EXACT
     coarse_sweeps: int = 20
+    # index (in the full coarsening hierarchy) of the level solved exactly; the paper allows
+    # the coarse mesh to be the starting mesh or any finer one that balances multigrid work
+    # against the cost of the direct solve (Sec. 2.2)
+    coarse_level: int = 0
 
     @property
     def n_rounds(self) -> int:
@@ -218,9 +222,9 @@ def rand_vec(seed: int, n: int) -> np.ndarray:
 def by_name(name: str) -> Workload:
     table = {
         "c1": c1_poisson(),
-        "c2": c2_td(),
-        "c3": c3_elasticity(),
-        "c4": c4_oseen(),
-        "c4b": c4_oseen(rounds=6, tall=True),
+        "c2": c2_td().with_(coarse_level=3),
+        "c3": c3_elasticity().with_(coarse_level=2),
+        "c4": c4_oseen().with_(coarse_level=2),
+        "c4b": c4_oseen(rounds=6, tall=True).with_(coarse_level=2),
     }
     return table[name]
