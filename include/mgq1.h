@@ -144,6 +144,29 @@ int32_t mg_num_levels(const mg_handle* h);
 int mg_validate_level(const mg_level_in* lv, const mg_level_in* coarser);
 
 void mg_destroy(mg_handle* h);
+
+/* ---- batched form: many independent problems, 1 or 8 right-hand sides each ----------
+ * Every problem brings its own hierarchy (same block size for all).  Vectors of the batch
+ * are the problems' vectors concatenated; inside problem p they are node-major with the
+ * right-hand sides innermost: v[off[p] + (node * b + c) * nrhs + q], off from
+ * mg_batch_offsets (n_problems + 1 entries).  Each step of the V-cycle runs as one launch
+ * over all problems (levels aligned by depth below each problem's finest level); the
+ * n_problems * nrhs FGMRES(m) instances run in lockstep, each with its own Hessenberg
+ * matrix, Givens rotations and stopping test ||b_i - A x_i|| <= rtol ||b_i||; with
+ * use_graph each Krylov step of the whole batch is one captured HIP graph.
+ * Requirements: outer = MG_OUTER_FGMRES, coarse_mode = MG_COARSE_EXACT, nrhs in {1, 8}
+ * (8 for block size 1 only).  Mathematically every instance is the single-problem solve
+ * of mg_solve (Algorithm "Geometric multigrid solver" inside GMRES, Sec. 4.2). */
+typedef struct mg_batch mg_batch;
+int mg_setup_batch(const mg_level_in* const* problems, const int32_t* n_levels, int32_t n_problems,
+                   int32_t nrhs, const mg_config* cfg, int32_t inputs_on_device, void* stream,
+                   mg_batch** out);
+int mg_batch_offsets(const mg_batch* h, int64_t* offsets);
+/* b, x: device FP64 batch vectors; x is the initial guess on entry.  stats: NULL or an
+ * array of n_problems * nrhs entries (instance p * nrhs + q).  Returns MG_OK when every
+ * instance converged, else MG_ENOCONV / MG_ENUMERIC (stats still filled). */
+int mg_solve_batch(mg_batch* h, const double* b, double* x, mg_solve_stats* stats, void* stream);
+void mg_destroy_batch(mg_batch* h);
 const char* mg_status_string(int status);
 const char* mg_last_error(void);
 

@@ -90,7 +90,7 @@ hipError_t launch_coarse_invert(int n, double* M, double* Ainv, double* pivbuf, 
 hipError_t launch_tail(const TailLevel* lv, int B, int kind, int xk, const TailParams& p, hipStream_t s);
 // nodal block inverses of the diagonal blocks of A (FP64 SELL) into S (lane layout,
 // double or float per sk); flag != 0 if a block is singular
-hipError_t launch_block_invert(const SellDev& A, void* S, int sk, int* flag, hipStream_t s);
+hipError_t launch_block_invert(const SellDev& A, void* S, int sk, int* flag, int NR, hipStream_t s);
 
 // vector kernels (n elements)
 hipError_t launch_fill(int64_t n, void* y, int yk, double v, hipStream_t s);
@@ -121,5 +121,85 @@ hipError_t launch_givens(int j, int m, double* H, double* cs, double* sn, double
 hipError_t launch_backsolve(int k, int m, const double* H, const double* g, double* y, hipStream_t s);
 // g = (beta, 0, ..., 0), beta read from the device
 hipError_t launch_init_g(int m, double* g, const double* beta, hipStream_t s);
+
+// ------------------------------------------------------------------ batched form
+// Many independent problems (same block size) with NR right-hand sides each.  Vectors
+// of one problem are stored [node][component][rhs]; the problems' vectors are
+// concatenated.  A batched launch covers one step of the V-cycle (or of the outer loop)
+// for every problem at once: entry e of the launch's table describes one problem and owns
+// blocks [first_e, first_{e+1}).
+enum BKind {
+  BK_SWEEP0 = 0,   // out = omega S in0
+  BK_SWEEP = 1,    // out = in1 + omega S (in0 - A in1)
+  BK_DEFECT = 2,   // out = M (in0 - A in1)
+  BK_RESTRICT = 3, // out = M_c T in0           (T = P~^T)
+  BK_PROLONG = 4,  // out += M T M_c in0         (T = P~)
+  BK_COARSE = 5,   // out = Ainv in0
+  BK_SPMV64 = 6,   // out (FP64) = A64 in1 (cycle precision)
+  BK_DEFECT64 = 7, // out = in0 - A64 in1 (all FP64), partial sums of squares per (block, rhs)
+  BK_FILL0 = 8     // out = 0
+};
+
+struct BEntry {
+  SellDev A;
+  const void* S = nullptr;
+  const uint8_t* mask = nullptr;
+  CsrDev T;
+  const uint8_t* mask_c = nullptr;
+  const void* in0 = nullptr;
+  const void* in1 = nullptr;
+  void* out = nullptr;
+  const double* Ainv = nullptr;
+  int n0 = 0;
+  int prob = 0;
+  int first = 0;
+};
+
+// blocks of an entry for a launch kind
+int batched_blocks(int kind, const SellDev& A, const CsrDev& T, int n0, int NR);
+// one batched step; `active[prob] == 0` skips a problem; `partials` for BK_DEFECT64
+hipError_t launch_batched(int kind, const BEntry* entries, int n_entries, int n_blocks, int B, int NR, int vkind,
+                          int xk, double omega, const int* active, double* partials, hipStream_t s);
+
+// vector segments of the concatenated batch vectors: problem p owns elements
+// [off[p], off[p] + len[p]) and vector blocks [vfirst[p], vfirst[p] + vcount[p])
+struct BSegs {
+  const int64_t* off = nullptr;
+  const int64_t* len = nullptr;
+  const int* vfirst = nullptr;
+  const int* vcount = nullptr;
+  const int* blk_prob = nullptr;   // vector block -> problem
+  int n_blocks = 0;
+  int NR = 1;
+};
+constexpr int kSegBlocksMax = 256;   // vector blocks per problem (partials re-summed per block)
+
+// partial sums per (vector block, rhs) of a.b (b == NULL: a.a)
+hipError_t launch_bdot(const BSegs& g, const double* a, const double* b, double* partials, hipStream_t s);
+// per-instance sum (sqrt) of partials over the instance's blocks: out[p*NR + q]
+// (pfirst / pcount: blocks per problem of the producing launch)
+hipError_t launch_bfinish(const double* partials, const int* pfirst, const int* pcount, int n_inst, int NR,
+                          double* out, int sqrt_out, hipStream_t s);
+// batched modified Gram-Schmidt step / normalisation; per-instance Hessenberg entries are
+// written to H[inst * hstride] (H points at the entry's offset inside each instance block)
+hipError_t launch_bmgs_step(const BSegs& g, double* w, const double* vi, const double* vnext, const double* pin,
+                            double* pout, double* H, int64_t hstride, hipStream_t s);
+hipError_t launch_bmgs_normalize(const BSegs& g, double* w, const double* pin, double* H, int64_t hstride,
+                                 hipStream_t s);
+// y = x / beta[inst] (0 where beta == 0 or the instance is inactive)
+hipError_t launch_bscale(const BSegs& g, double* y, const double* x, const double* beta, const int* iact,
+                         hipStream_t s);
+// x += sum_{i < kk[inst]} yv[inst][i] Z_i   (Z_i = Z + i * ldz of kind zk)
+hipError_t launch_bupdate(const BSegs& g, double* x, const void* Z, int zk, int64_t ldz, const double* yv, int m,
+                          const int* kk, hipStream_t s);
+// per-instance Givens step j, then kk[inst] = j + 1 when |g_{j+1}| <= tol[inst] or breakdown
+hipError_t launch_bgivens(int j, int m, int n_inst, double* H, double* cs, double* sn, double* g, double* st,
+                          const double* tol, int* kk, const int* iact, hipStream_t s);
+hipError_t launch_bbacksolve(int m, int n_inst, const double* H, const double* g, double* yv, const int* kk,
+                             hipStream_t s);
+// g[inst] = (beta, 0, ...), kk = 0
+hipError_t launch_binit(int m, int n_inst, double* g, const double* beta, int* kk, hipStream_t s);
+// kk[inst] = j + 1 where still 0 (end of a lockstep restart cycle of j + 1 steps)
+hipError_t launch_bclose(int j, int n_inst, int* kk, const int* iact, hipStream_t s);
 
 }  // namespace mgq1

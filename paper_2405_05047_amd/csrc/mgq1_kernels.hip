@@ -69,43 +69,49 @@ template <> struct Val<VK_BF16> {
   }
 };
 
-// per-lane row dot product of a slice: sum_k sum_cc a(k, cc) x[col_k * B + cc]
-template <int B, int K, class XI, class T>
+// per-lane row dot product of a slice: sum_k sum_cc a(k, cc) x[(col_k * B + cc) * NR + q].
+// NR right-hand sides share every matrix entry: lane = (r * B + c) * NR + q, the slice
+// holds R = 64 / (B * NR) nodes, and the values of row lane rl = lane / NR sit at
+// val[(k * B + cc) * W + rl] with the padded row-lane stride W = 64 / NR (R * B rounded up,
+// 64 for one right-hand side).  NR = 1 is the single right-hand-side layout.
+template <int B, int NR, int K, class XI, class T>
 __device__ __forceinline__ T sell_dot(const SellDev& A, int slice, int lane, bool valid,
                                       const XI* __restrict__ x) {
-  constexpr int R = kWave / B;
+  constexpr int R = kWave / (B * NR);
+  constexpr int W = kWave / NR;
   constexpr int KB = B <= 2 ? 8 : 4;       // block slots per batch
   T acc = T(0);
   if (!valid) return acc;
+  const int rl = lane / NR, q = lane % NR;
   float sc = 1.0f;
-  if (K == VK_F16 || K == VK_BF16) sc = ldexpf(1.0f, A.rexp[int64_t(slice) * kWave + lane]);
-  const int r = lane / B;
+  if (K == VK_F16 || K == VK_BF16) sc = ldexpf(1.0f, A.rexp[int64_t(slice) * W + rl]);
+  const int r = rl / B;
   const int k0 = A.sptr[slice], k1 = A.sptr[slice + 1];
   for (int k = k0; k < k1; k += KB) {
     int js[KB];
 #pragma unroll
-    for (int q = 0; q < KB; ++q)
-      js[q] = (k + q < k1) ? __builtin_nontemporal_load(A.col + int64_t(k + q) * R + r) : -1;
+    for (int qq = 0; qq < KB; ++qq)
+      js[qq] = (k + qq < k1) ? __builtin_nontemporal_load(A.col + int64_t(k + qq) * R + r) : -1;
     T av[KB][B], xv[KB][B];
 #pragma unroll
-    for (int q = 0; q < KB; ++q) {
-      if (js[q] >= 0) {                      // uniform across the wave (slice-wide k range)
-        const XI* xj = x + int64_t(js[q]) * B;
-        const int64_t vb = int64_t(k + q) * B * kWave + lane;
+    for (int qq = 0; qq < KB; ++qq) {
+      if (js[qq] >= 0) {                     // uniform across the wave (slice-wide k range)
+        const XI* xj = x + int64_t(js[qq]) * B * NR + q;
+        const int64_t vb = int64_t(k + qq) * B * W + rl;
 #pragma unroll
         for (int cc = 0; cc < B; ++cc) {
-          av[q][cc] = T(Val<K>::get(A.val, vb + cc * kWave, sc));
-          xv[q][cc] = T(xj[cc]);
+          av[qq][cc] = T(Val<K>::get(A.val, vb + cc * W, sc));
+          xv[qq][cc] = T(xj[cc * NR]);
         }
       } else {
 #pragma unroll
-        for (int cc = 0; cc < B; ++cc) { av[q][cc] = T(0); xv[q][cc] = T(0); }
+        for (int cc = 0; cc < B; ++cc) { av[qq][cc] = T(0); xv[qq][cc] = T(0); }
       }
     }
 #pragma unroll
-    for (int q = 0; q < KB; ++q)
+    for (int qq = 0; qq < KB; ++qq)
 #pragma unroll
-      for (int cc = 0; cc < B; ++cc) acc += av[q][cc] * xv[q][cc];
+      for (int cc = 0; cc < B; ++cc) acc += av[qq][cc] * xv[qq][cc];
   }
   return acc;
 }
@@ -146,64 +152,68 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
 // geometry of one wave-slice
 struct SliceLane {
   int slice, lane, node;
-  int64_t dof;
+  int64_t dof;            // (node * B + c) * NR + q
   bool valid;
 };
 
-template <int B>
+template <int B, int NR>
 __device__ __forceinline__ SliceLane slice_lane(const SellDev& A, int slice, int lane) {
-  constexpr int R = kWave / B;
+  constexpr int R = kWave / (B * NR);
   SliceLane s;
   s.slice = slice;
   s.lane = lane;
-  s.node = slice * R + lane / B;
-  s.dof = int64_t(slice) * R * B + lane;
-  s.valid = slice < A.nslices && lane < R * B && s.node < A.n;
+  s.node = slice * R + lane / (B * NR);
+  s.dof = int64_t(slice) * R * B * NR + lane;
+  s.valid = slice < A.nslices && lane < R * B * NR && s.node < A.n;
   return s;
 }
 
 // y = A x (MODE 0), b - A x (MODE 1), M (b - A x) (MODE 2); returns the written value
-template <int B, int K, class XI, class XO, class T, int MODE>
+template <int B, int NR, int K, class XI, class XO, class T, int MODE>
 __device__ __forceinline__ T spmv_slice(const SellDev& A, const XO* __restrict__ b, const XI* __restrict__ x,
                                         XO* __restrict__ y, const uint8_t* __restrict__ mask, const SliceLane& s) {
-  const T acc = sell_dot<B, K, XI, T>(A, s.slice, s.lane, s.valid, x);
+  const T acc = sell_dot<B, NR, K, XI, T>(A, s.slice, s.lane, s.valid, x);
   T out = T(0);
   if (s.valid) {
     if (MODE == 0) {
       out = acc;
     } else {
       out = T(b[s.dof]) - acc;
-      if (MODE == 2 && mask[s.dof]) out = T(0);
+      if (MODE == 2 && mask[s.dof / NR]) out = T(0);
     }
     y[s.dof] = XO(out);
   }
   return out;
 }
 
-template <int B, int K, class X, class T>
+template <int B, int NR, int K, class X, class T>
 __device__ __forceinline__ void sweep_slice(const SellDev& A, const X* __restrict__ S, const X* __restrict__ b,
                                             const X* __restrict__ x, X* __restrict__ xo, T omega,
                                             const SliceLane& s) {
-  const T acc = sell_dot<B, K, X, T>(A, s.slice, s.lane, s.valid, x);
+  constexpr int W = kWave / NR;
+  const T acc = sell_dot<B, NR, K, X, T>(A, s.slice, s.lane, s.valid, x);
   const T res = s.valid ? T(b[s.dof]) - acc : T(0);
-  const int base = (s.lane / B) * B;
+  const int rl = s.lane / NR, q = s.lane % NR;
+  const int base = (rl / B) * B;
   T upd = T(0);
 #pragma unroll
   for (int cc = 0; cc < B; ++cc) {
-    const T rc = __shfl(res, (base + cc) & (kWave - 1), kWave);
-    if (s.valid) upd += T(S[(int64_t(s.slice) * B + cc) * kWave + s.lane]) * rc;
+    const T rc = __shfl(res, ((base + cc) * NR + q) & (kWave - 1), kWave);
+    if (s.valid) upd += T(S[(int64_t(s.slice) * B + cc) * W + rl]) * rc;
   }
   if (s.valid) xo[s.dof] = X(T(x[s.dof]) + omega * upd);
 }
 
-template <int B, class X, class T>
+template <int B, int NR, class X, class T>
 __device__ __forceinline__ void sweep0_slice(const X* __restrict__ S, const X* __restrict__ b, X* __restrict__ xo,
                                              T omega, const SliceLane& s) {
+  constexpr int W = kWave / NR;
   if (!s.valid) return;
+  const int rl = s.lane / NR, q = s.lane % NR;
   T upd = T(0);
 #pragma unroll
   for (int cc = 0; cc < B; ++cc)
-    upd += T(S[(int64_t(s.slice) * B + cc) * kWave + s.lane]) * T(b[int64_t(s.node) * B + cc]);
+    upd += T(S[(int64_t(s.slice) * B + cc) * W + rl]) * T(b[(int64_t(s.node) * B + cc) * NR + q]);
   xo[s.dof] = X(omega * upd);
 }
 
@@ -211,33 +221,37 @@ __device__ __forceinline__ double weight(const CsrDev& M, int k) {
   return M.f32 ? double(static_cast<const float*>(M.val)[k]) : static_cast<const double*>(M.val)[k];
 }
 
-// d[t] = M_c sum_k R_jk (M_f r)[k], t = j*B + c
-template <int B, class X, class T>
+// d[t] = M_c sum_k R_jk (M_f r)[k], t = (j*B + c) * NR + q
+template <int B, int NR, class X, class T>
 __device__ __forceinline__ void restrict_dof(const CsrDev& R, const X* __restrict__ r, X* __restrict__ d,
                                              const uint8_t* __restrict__ mask_c, const uint8_t* __restrict__ mask_f,
                                              int64_t t) {
-  const int j = int(t / B), c = int(t % B);
+  const int64_t dof = t / NR;
+  const int q = int(t % NR);
+  const int j = int(dof / B), c = int(dof % B);
   T acc = T(0);
-  if (!mask_c[t]) {
+  if (!mask_c[dof]) {
     for (int k = R.rowptr[j]; k < R.rowptr[j + 1]; ++k) {
-      const int64_t q = int64_t(R.col[k]) * B + c;
-      if (mask_f == nullptr || !mask_f[q]) acc += T(weight(R, k)) * T(r[q]);
+      const int64_t fd = int64_t(R.col[k]) * B + c;
+      if (mask_f == nullptr || !mask_f[fd]) acc += T(weight(R, k)) * T(r[fd * NR + q]);
     }
   }
   d[t] = X(acc);
 }
 
 // x[t] += M_f sum_k P_ik (M_c y)[k]
-template <int B, class X, class T>
+template <int B, int NR, class X, class T>
 __device__ __forceinline__ void prolong_dof(const CsrDev& P, const X* __restrict__ y, X* __restrict__ x,
                                             const uint8_t* __restrict__ mask_f, const uint8_t* __restrict__ mask_c,
                                             int64_t t) {
-  if (mask_f[t]) return;
-  const int i = int(t / B), c = int(t % B);
+  const int64_t dof = t / NR;
+  const int q = int(t % NR);
+  if (mask_f[dof]) return;
+  const int i = int(dof / B), c = int(dof % B);
   T acc = T(0);
   for (int k = P.rowptr[i]; k < P.rowptr[i + 1]; ++k) {
-    const int64_t q = int64_t(P.col[k]) * B + c;
-    if (!mask_c[q]) acc += T(weight(P, k)) * T(y[q]);
+    const int64_t cd = int64_t(P.col[k]) * B + c;
+    if (!mask_c[cd]) acc += T(weight(P, k)) * T(y[cd * NR + q]);
   }
   x[t] = X(T(x[t]) + acc);
 }
@@ -248,8 +262,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(SellDev A, const XO* __restri
                                                    XO* __restrict__ y, const uint8_t* __restrict__ mask,
                                                    double* __restrict__ partials) {
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const SliceLane s = slice_lane<B>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
-  const T out = spmv_slice<B, K, XI, XO, T, MODE>(A, b, x, y, mask, s);
+  const SliceLane s = slice_lane<B, 1>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
+  const T out = spmv_slice<B, 1, K, XI, XO, T, MODE>(A, b, x, y, mask, s);
   if (NORM) {
     __shared__ double lds[kMaxWaves + 1];
     const double p = block_allsum(double(out) * double(out), lds);
@@ -261,15 +275,15 @@ template <int B, int K, class X, class T>
 __global__ __launch_bounds__(kThreads) void k_sweep(SellDev A, const X* __restrict__ S, const X* __restrict__ b,
                                                     const X* __restrict__ x, X* __restrict__ xo, T omega) {
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const SliceLane s = slice_lane<B>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
-  sweep_slice<B, K, X, T>(A, S, b, x, xo, omega, s);
+  const SliceLane s = slice_lane<B, 1>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
+  sweep_slice<B, 1, K, X, T>(A, S, b, x, xo, omega, s);
 }
 
 template <int B, class X, class T>
 __global__ __launch_bounds__(kThreads) void k_sweep0(SellDev A, const X* __restrict__ S, const X* __restrict__ b,
                                                      X* __restrict__ xo, T omega) {
-  const SliceLane s = slice_lane<B>(A, blockIdx.x * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
-  sweep0_slice<B, X, T>(S, b, xo, omega, s);
+  const SliceLane s = slice_lane<B, 1>(A, blockIdx.x * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
+  sweep0_slice<B, 1, X, T>(S, b, xo, omega, s);
 }
 
 template <int B, class X, class T>
@@ -277,7 +291,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict(CsrDev R, const X* __rest
                                                        const uint8_t* __restrict__ mask_c,
                                                        const uint8_t* __restrict__ mask_f) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < int64_t(R.nrows) * B) restrict_dof<B, X, T>(R, r, d, mask_c, mask_f, t);
+  if (t < int64_t(R.nrows) * B) restrict_dof<B, 1, X, T>(R, r, d, mask_c, mask_f, t);
 }
 
 template <int B, class X, class T>
@@ -285,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_prolong(CsrDev P, const X* __restr
                                                       const uint8_t* __restrict__ mask_f,
                                                       const uint8_t* __restrict__ mask_c) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < int64_t(P.nrows) * B) prolong_dof<B, X, T>(P, y, x, mask_f, mask_c, t);
+  if (t < int64_t(P.nrows) * B) prolong_dof<B, 1, X, T>(P, y, x, mask_f, mask_c, t);
 }
 
 // x = Ainv b, one wavefront per row (Ainv row-major, FP64)
@@ -310,7 +324,7 @@ template <int B, int K, class X, class T>
 __device__ void tail_sweep(const TailLevel& L, const X* b, const X* x, X* xo, T omega) {
   const int nw = blockDim.x / kWave, w = threadIdx.x / kWave, ln = threadIdx.x % kWave;
   for (int sl = w; sl < L.A.nslices; sl += nw)
-    sweep_slice<B, K, X, T>(L.A, static_cast<const X*>(L.S), b, x, xo, omega, slice_lane<B>(L.A, sl, ln));
+    sweep_slice<B, 1, K, X, T>(L.A, static_cast<const X*>(L.S), b, x, xo, omega, slice_lane<B, 1>(L.A, sl, ln));
   __syncthreads();
 }
 
@@ -333,7 +347,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailLevel* __restri
     const X* b = static_cast<const X*>(L.b);
     if (p.nu1 >= 1) {
       for (int sl = w; sl < L.A.nslices; sl += nw)
-        sweep0_slice<B, X, T>(static_cast<const X*>(L.S), b, cur, omega, slice_lane<B>(L.A, sl, ln));
+        sweep0_slice<B, 1, X, T>(static_cast<const X*>(L.S), b, cur, omega, slice_lane<B, 1>(L.A, sl, ln));
       __syncthreads();
       for (int q = 1; q < p.nu1; ++q) {
         tail_sweep<B, K, X, T>(L, b, cur, oth, omega);
@@ -344,11 +358,11 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailLevel* __restri
       __syncthreads();
     }
     for (int sl = w; sl < L.A.nslices; sl += nw)
-      spmv_slice<B, K, X, X, T, 2>(L.A, b, cur, static_cast<X*>(L.r), L.mask, slice_lane<B>(L.A, sl, ln));
+      spmv_slice<B, 1, K, X, X, T, 2>(L.A, b, cur, static_cast<X*>(L.r), L.mask, slice_lane<B, 1>(L.A, sl, ln));
     __syncthreads();
     const TailLevel& C = lv[l - 1];
     for (int64_t t = threadIdx.x; t < int64_t(C.A.n) * B; t += blockDim.x)
-      restrict_dof<B, X, T>(L.R, static_cast<const X*>(L.r), static_cast<X*>(C.b), C.mask, nullptr, t);
+      restrict_dof<B, 1, X, T>(L.R, static_cast<const X*>(L.r), static_cast<X*>(C.b), C.mask, nullptr, t);
     __syncthreads();
   }
   // coarse solve on level 0
@@ -365,7 +379,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailLevel* __restri
       X* cur = ((k - 1) % 2 == 0) ? x0 : tmp;
       X* oth = ((k - 1) % 2 == 0) ? tmp : x0;
       for (int sl = w; sl < C.A.nslices; sl += nw)
-        sweep0_slice<B, X, T>(static_cast<const X*>(C.S), b0, cur, omega, slice_lane<B>(C.A, sl, ln));
+        sweep0_slice<B, 1, X, T>(static_cast<const X*>(C.S), b0, cur, omega, slice_lane<B, 1>(C.A, sl, ln));
       __syncthreads();
       for (int q = 1; q < k; ++q) {
         tail_sweep<B, K, X, T>(C, b0, cur, oth, omega);
@@ -383,7 +397,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(const TailLevel* __restri
     X* oth = (pp % 2 == 0) ? tmp : own;
     if (pre_pp % 2 == 1) { X* t = cur; cur = oth; oth = t; }
     for (int64_t t = threadIdx.x; t < int64_t(L.A.n) * B; t += blockDim.x)
-      prolong_dof<B, X, T>(L.P, static_cast<const X*>(C.x), cur, L.mask, C.mask, t);
+      prolong_dof<B, 1, X, T>(L.P, static_cast<const X*>(C.x), cur, L.mask, C.mask, t);
     __syncthreads();
     for (int q = 0; q < p.nu2; ++q) {
       tail_sweep<B, K, X, T>(L, static_cast<const X*>(L.b), cur, oth, omega);
@@ -460,9 +474,10 @@ __global__ __launch_bounds__(256) void k_gj_extract(int n, const double* M, doub
   Ainv[t] = M[int64_t(i) * 2 * n + n + j];
 }
 
-template <int B, class ST>
+template <int B, int NR, class ST>
 __global__ __launch_bounds__(256) void k_block_invert(SellDev A, ST* __restrict__ S, int* flag) {
-  constexpr int R = kWave / B;
+  constexpr int R = kWave / (B * NR);
+  constexpr int W = kWave / NR;
   const int node = blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= A.n) return;
   const int slice = node / R, r = node % R;
@@ -474,7 +489,7 @@ __global__ __launch_bounds__(256) void k_block_invert(SellDev A, ST* __restrict_
   double m[B][2 * B];
   for (int c = 0; c < B; ++c)
     for (int cc = 0; cc < B; ++cc) {
-      m[c][cc] = val[(int64_t(kd) * B + cc) * kWave + r * B + c];
+      m[c][cc] = val[(int64_t(kd) * B + cc) * W + r * B + c];
       m[c][B + cc] = (c == cc) ? 1.0 : 0.0;
     }
   for (int k = 0; k < B; ++k) {
@@ -493,7 +508,7 @@ __global__ __launch_bounds__(256) void k_block_invert(SellDev A, ST* __restrict_
     }
   }
   for (int c = 0; c < B; ++c)
-    for (int cc = 0; cc < B; ++cc) S[(int64_t(slice) * B + cc) * kWave + r * B + c] = ST(m[c][B + cc]);
+    for (int cc = 0; cc < B; ++cc) S[(int64_t(slice) * B + cc) * W + r * B + c] = ST(m[c][B + cc]);
 }
 
 // ------------------------------------------------------------------ vector kernels
@@ -849,17 +864,22 @@ hipError_t launch_coarse_invert(int n, double* M, double* Ainv, double* pivbuf, 
   return hipGetLastError();
 }
 
-hipError_t launch_block_invert(const SellDev& A, void* S, int sk, int* flag, hipStream_t s) {
+hipError_t launch_block_invert(const SellDev& A, void* S, int sk, int* flag, int NR, hipStream_t s) {
   const unsigned g = grid_for(A.n, 256);
   if (g == 0) return hipSuccess;
-#define MGQ1_BI(BB)                                                                                          \
-  if (sk == X_F64) hipLaunchKernelGGL((k_block_invert<BB, double>), g, 256, 0, s, A, static_cast<double*>(S), flag); \
-  else hipLaunchKernelGGL((k_block_invert<BB, float>), g, 256, 0, s, A, static_cast<float*>(S), flag);
+#define MGQ1_BI(BB, NN)                                                                                           \
+  if (sk == X_F64) hipLaunchKernelGGL((k_block_invert<BB, NN, double>), g, 256, 0, s, A, static_cast<double*>(S), flag); \
+  else hipLaunchKernelGGL((k_block_invert<BB, NN, float>), g, 256, 0, s, A, static_cast<float*>(S), flag);
+  if (NR == 8) {
+    if (A.B != 1) return hipErrorInvalidValue;
+    MGQ1_BI(1, 8)
+    return hipGetLastError();
+  }
   switch (A.B) {
-    case 1: MGQ1_BI(1) break;
-    case 2: MGQ1_BI(2) break;
-    case 3: MGQ1_BI(3) break;
-    case 4: MGQ1_BI(4) break;
+    case 1: MGQ1_BI(1, 1) break;
+    case 2: MGQ1_BI(2, 1) break;
+    case 3: MGQ1_BI(3, 1) break;
+    case 4: MGQ1_BI(4, 1) break;
     default: return hipErrorInvalidValue;
   }
 #undef MGQ1_BI
@@ -952,6 +972,433 @@ hipError_t launch_backsolve(int k, int m, const double* H, const double* g, doub
 
 hipError_t launch_init_g(int m, double* g, const double* beta, hipStream_t s) {
   hipLaunchKernelGGL(k_init_g, 1, 128, 0, s, m, g, beta);
+  return hipGetLastError();
+}
+
+// ======================================================================== batched form
+namespace {
+
+__device__ __forceinline__ int find_entry(const BEntry* __restrict__ E, int n, int blk) {
+  int lo = 0, hi = n - 1;                 // largest e with E[e].first <= blk
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (E[mid].first <= blk) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// V-cycle steps on slices (sweep0, sweep, masked defect) for every problem of the batch
+template <int B, int NR, int K, class X, class T, int KIND>
+__global__ __launch_bounds__(kThreads) void k_bsell(const BEntry* __restrict__ E, int ne, T omega,
+                                                    const int* __restrict__ active) {
+  __shared__ int se;
+  if (threadIdx.x == 0) se = find_entry(E, ne, blockIdx.x);
+  __syncthreads();
+  const BEntry& e = E[se];
+  if (active && !active[e.prob]) return;
+  const SliceLane s = slice_lane<B, NR>(e.A, (blockIdx.x - e.first) * kSliceWaves + threadIdx.x / kWave,
+                                        threadIdx.x % kWave);
+  if (KIND == BK_SWEEP0)
+    sweep0_slice<B, NR, X, T>(static_cast<const X*>(e.S), static_cast<const X*>(e.in0), static_cast<X*>(e.out),
+                              omega, s);
+  else if (KIND == BK_SWEEP)
+    sweep_slice<B, NR, K, X, T>(e.A, static_cast<const X*>(e.S), static_cast<const X*>(e.in0),
+                                static_cast<const X*>(e.in1), static_cast<X*>(e.out), omega, s);
+  else
+    spmv_slice<B, NR, K, X, X, T, 2>(e.A, static_cast<const X*>(e.in0), static_cast<const X*>(e.in1),
+                                     static_cast<X*>(e.out), e.mask, s);
+}
+
+// outer-loop products with the FP64 operator: w = A z (KIND SPMV64) or r = b - A x with
+// partial sums of squares per (block, rhs) (KIND DEFECT64)
+template <int B, int NR, class XI, int KIND>
+__global__ __launch_bounds__(kThreads) void k_bsell64(const BEntry* __restrict__ E, int ne,
+                                                      const int* __restrict__ active, double* __restrict__ partials) {
+  __shared__ int se;
+  __shared__ double lds[kThreads];
+  if (threadIdx.x == 0) se = find_entry(E, ne, blockIdx.x);
+  __syncthreads();
+  const BEntry& e = E[se];
+  const bool on = !(active && !active[e.prob]);
+  double out = 0.0;
+  if (on) {
+    const SliceLane s = slice_lane<B, NR>(e.A, (blockIdx.x - e.first) * kSliceWaves + threadIdx.x / kWave,
+                                          threadIdx.x % kWave);
+    if (KIND == BK_SPMV64)
+      out = spmv_slice<B, NR, VK_F64, XI, double, double, 0>(e.A, nullptr, static_cast<const XI*>(e.in1),
+                                                             static_cast<double*>(e.out), nullptr, s);
+    else
+      out = spmv_slice<B, NR, VK_F64, double, double, double, 1>(e.A, static_cast<const double*>(e.in0),
+                                                                 static_cast<const double*>(e.in1),
+                                                                 static_cast<double*>(e.out), nullptr, s);
+  }
+  if (KIND == BK_DEFECT64) {
+    lds[threadIdx.x] = out * out;         // lane % NR is the right-hand side
+    __syncthreads();
+    if (threadIdx.x < NR) {
+      double t = 0.0;
+      for (int i = threadIdx.x; i < kThreads; i += NR) t += lds[i];
+      partials[int64_t(blockIdx.x) * NR + threadIdx.x] = t;
+    }
+  }
+}
+
+template <int B, int NR, class X, class T, int KIND>
+__global__ __launch_bounds__(kThreads) void k_belem(const BEntry* __restrict__ E, int ne,
+                                                    const int* __restrict__ active) {
+  __shared__ int se;
+  if (threadIdx.x == 0) se = find_entry(E, ne, blockIdx.x);
+  __syncthreads();
+  const BEntry& e = E[se];
+  if (active && !active[e.prob]) return;
+  const int64_t t = int64_t(blockIdx.x - e.first) * kThreads + threadIdx.x;
+  if (KIND == BK_RESTRICT) {
+    if (t < int64_t(e.T.nrows) * B * NR)
+      restrict_dof<B, NR, X, T>(e.T, static_cast<const X*>(e.in0), static_cast<X*>(e.out), e.mask_c, nullptr, t);
+  } else if (KIND == BK_PROLONG) {
+    if (t < int64_t(e.T.nrows) * B * NR)
+      prolong_dof<B, NR, X, T>(e.T, static_cast<const X*>(e.in0), static_cast<X*>(e.out), e.mask, e.mask_c, t);
+  } else {                                 // BK_FILL0
+    if (t < int64_t(e.A.n) * B * NR) static_cast<X*>(e.out)[t] = X(0);
+  }
+}
+
+// coarse solve x = Ainv b for NR right-hand sides, one wavefront per row
+template <int NR, class X>
+__global__ __launch_bounds__(kThreads) void k_bcoarse(const BEntry* __restrict__ E, int ne,
+                                                      const int* __restrict__ active) {
+  __shared__ int se;
+  if (threadIdx.x == 0) se = find_entry(E, ne, blockIdx.x);
+  __syncthreads();
+  const BEntry& e = E[se];
+  if (active && !active[e.prob]) return;
+  const int i = (blockIdx.x - e.first) * kSliceWaves + threadIdx.x / kWave;
+  if (i >= e.n0) return;
+  const int lane = threadIdx.x % kWave, q = lane % NR;
+  const X* b = static_cast<const X*>(e.in0);
+  double acc = 0.0;
+  for (int k = lane / NR; k < e.n0; k += kWave / NR) acc += e.Ainv[int64_t(i) * e.n0 + k] * double(b[int64_t(k) * NR + q]);
+#pragma unroll
+  for (int o = kWave / 2; o >= NR; o >>= 1) acc += __shfl_down(acc, o, kWave);
+  if (lane < NR) static_cast<X*>(e.out)[int64_t(i) * NR + lane] = X(acc);
+}
+
+// ---- segmented vector kernels: block -> problem segment, thread keeps rhs q = tid % NR
+struct SegPos {
+  int p, lb, nb, first;
+  int64_t off, len;
+};
+
+__device__ __forceinline__ SegPos seg_pos(const BSegs& g) {
+  SegPos s;
+  s.p = g.blk_prob[blockIdx.x];
+  s.first = g.vfirst[s.p];
+  s.lb = blockIdx.x - s.first;
+  s.nb = g.vcount[s.p];
+  s.off = g.off[s.p];
+  s.len = g.len[s.p];
+  return s;
+}
+
+// fixed-order sum over the block of values that belong to rhs q = tid % NR; thread q of
+// the result gets the sum for q
+__device__ __forceinline__ double block_sum_rhs(double v, int NR, double* lds) {
+  lds[threadIdx.x] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (int(threadIdx.x) < NR)
+    for (int i = threadIdx.x; i < int(blockDim.x); i += NR) t += lds[i];
+  __syncthreads();
+  return t;
+}
+
+// every block of problem p computes the per-rhs sums of the problem's partials
+__device__ __forceinline__ void seg_sums(const double* __restrict__ pin, const SegPos& sp, int NR, double* lds,
+                                         double* out) {
+  double t = 0.0;
+  const int q = threadIdx.x % NR;
+  for (int b = threadIdx.x / NR; b < sp.nb; b += blockDim.x / NR) t += pin[int64_t(sp.first + b) * NR + q];
+  const double r = block_sum_rhs(t, NR, lds);
+  if (int(threadIdx.x) < NR) out[threadIdx.x] = r;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) void k_bdot(BSegs g, const double* __restrict__ a,
+                                                   const double* __restrict__ b, double* __restrict__ out) {
+  __shared__ double lds[kThreads];
+  const SegPos sp = seg_pos(g);
+  double t = 0.0;
+  const int64_t stride = int64_t(sp.nb) * blockDim.x;
+  for (int64_t i = int64_t(sp.lb) * blockDim.x + threadIdx.x; i < sp.len; i += stride) {
+    const double av = a[sp.off + i];
+    t += av * (b ? b[sp.off + i] : av);
+  }
+  const double r = block_sum_rhs(t, g.NR, lds);
+  if (int(threadIdx.x) < g.NR) out[int64_t(blockIdx.x) * g.NR + threadIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bmgs_step(BSegs g, double* __restrict__ w, const double* __restrict__ vi,
+                                                        const double* __restrict__ vnext, const double* __restrict__ pin,
+                                                        double* __restrict__ pout, double* __restrict__ H,
+                                                        int64_t hstride) {
+  __shared__ double lds[kThreads];
+  __shared__ double hq[64];
+  const SegPos sp = seg_pos(g);
+  seg_sums(pin, sp, g.NR, lds, hq);
+  if (sp.lb == 0 && int(threadIdx.x) < g.NR) H[int64_t(sp.p * g.NR + threadIdx.x) * hstride] = hq[threadIdx.x];
+  const double h = hq[threadIdx.x % g.NR];
+  double t = 0.0;
+  const int64_t stride = int64_t(sp.nb) * blockDim.x;
+  for (int64_t i = int64_t(sp.lb) * blockDim.x + threadIdx.x; i < sp.len; i += stride) {
+    const int64_t k = sp.off + i;
+    const double v = w[k] - h * vi[k];
+    w[k] = v;
+    t += v * (vnext ? vnext[k] : v);
+  }
+  const double r = block_sum_rhs(t, g.NR, lds);
+  if (int(threadIdx.x) < g.NR) pout[int64_t(blockIdx.x) * g.NR + threadIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bmgs_normalize(BSegs g, double* __restrict__ w,
+                                                             const double* __restrict__ pin, double* __restrict__ H,
+                                                             int64_t hstride) {
+  __shared__ double lds[kThreads];
+  __shared__ double hq[64];
+  const SegPos sp = seg_pos(g);
+  seg_sums(pin, sp, g.NR, lds, hq);
+  if (int(threadIdx.x) < g.NR) hq[threadIdx.x] = sqrt(hq[threadIdx.x]);
+  __syncthreads();
+  if (sp.lb == 0 && int(threadIdx.x) < g.NR) H[int64_t(sp.p * g.NR + threadIdx.x) * hstride] = hq[threadIdx.x];
+  const double nrm = hq[threadIdx.x % g.NR];
+  if (nrm == 0.0) return;
+  const int64_t stride = int64_t(sp.nb) * blockDim.x;
+  for (int64_t i = int64_t(sp.lb) * blockDim.x + threadIdx.x; i < sp.len; i += stride) w[sp.off + i] /= nrm;
+}
+
+__global__ __launch_bounds__(kThreads) void k_bscale(BSegs g, double* __restrict__ y, const double* __restrict__ x,
+                                                     const double* __restrict__ beta, const int* __restrict__ iact) {
+  const SegPos sp = seg_pos(g);
+  const int inst = sp.p * g.NR + threadIdx.x % g.NR;
+  const double bt = beta[inst];
+  const bool on = iact[inst] && bt != 0.0;
+  const int64_t stride = int64_t(sp.nb) * blockDim.x;
+  for (int64_t i = int64_t(sp.lb) * blockDim.x + threadIdx.x; i < sp.len; i += stride)
+    y[sp.off + i] = on ? x[sp.off + i] / bt : 0.0;
+}
+
+template <class Z>
+__global__ __launch_bounds__(kThreads) void k_bupdate(BSegs g, double* __restrict__ x, const Z* __restrict__ Zm,
+                                                      int64_t ldz, const double* __restrict__ yv, int m,
+                                                      const int* __restrict__ kk) {
+  const SegPos sp = seg_pos(g);
+  const int inst = sp.p * g.NR + threadIdx.x % g.NR;
+  const int k = kk[inst];
+  if (k == 0) return;
+  const double* y = yv + int64_t(inst) * m;
+  const int64_t stride = int64_t(sp.nb) * blockDim.x;
+  for (int64_t i = int64_t(sp.lb) * blockDim.x + threadIdx.x; i < sp.len; i += stride) {
+    const int64_t e = sp.off + i;
+    double acc = x[e];
+    for (int c = 0; c < k; ++c) acc += y[c] * double(Zm[int64_t(c) * ldz + e]);
+    x[e] = acc;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_bfinish(const double* __restrict__ p, const int* __restrict__ pfirst,
+                                                      const int* __restrict__ pcount, int NR, double* out, int sq) {
+  __shared__ double lds[kMaxWaves + 1];
+  const int inst = blockIdx.x, pr = inst / NR, q = inst % NR;
+  double t = 0.0;
+  for (int b = threadIdx.x; b < pcount[pr]; b += blockDim.x) t += p[int64_t(pfirst[pr] + b) * NR + q];
+  const double s = block_allsum(t, lds);
+  if (threadIdx.x == 0) out[inst] = sq ? sqrt(s) : s;
+}
+
+__global__ void k_bgivens(int j, int m, int n_inst, double* H, double* cs, double* sn, double* g, double* st,
+                          const double* __restrict__ tol, int* kk, const int* __restrict__ iact) {
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst >= n_inst || !iact[inst]) return;
+  const int ld = m + 1;
+  double* h = H + int64_t(inst) * ld * m + int64_t(j) * ld;
+  double* c = cs + int64_t(inst) * m;
+  double* s = sn + int64_t(inst) * m;
+  double* gg = g + int64_t(inst) * ld;
+  const bool breakdown = h[j + 1] == 0.0;
+  for (int i = 0; i < j; ++i) {
+    const double t = c[i] * h[i] + s[i] * h[i + 1];
+    h[i + 1] = -s[i] * h[i] + c[i] * h[i + 1];
+    h[i] = t;
+  }
+  const double den = hypot(h[j], h[j + 1]);
+  c[j] = h[j] / den;
+  s[j] = h[j + 1] / den;
+  h[j] = den;
+  h[j + 1] = 0.0;
+  gg[j + 1] = -s[j] * gg[j];
+  gg[j] = c[j] * gg[j];
+  st[2 * inst] = fabs(gg[j + 1]);
+  st[2 * inst + 1] = breakdown ? 1.0 : 0.0;
+  // closes on breakdown, on the tolerance, or on a non-finite estimate (!(x > tol))
+  if (kk[inst] == 0 && (breakdown || !(fabs(gg[j + 1]) > tol[inst]))) kk[inst] = j + 1;
+}
+
+__global__ void k_bbacksolve(int m, int n_inst, const double* H, const double* g, double* yv, const int* kk) {
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst >= n_inst) return;
+  const int k = kk[inst];
+  const int ld = m + 1;
+  const double* Hh = H + int64_t(inst) * ld * m;
+  const double* gg = g + int64_t(inst) * ld;
+  double* y = yv + int64_t(inst) * m;
+  for (int i = k - 1; i >= 0; --i) {
+    double t = gg[i];
+    for (int c = i + 1; c < k; ++c) t -= Hh[int64_t(c) * ld + i] * y[c];
+    y[i] = t / Hh[int64_t(i) * ld + i];
+  }
+}
+
+__global__ void k_binit(int m, int n_inst, double* g, const double* beta, int* kk) {
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst >= n_inst) return;
+  double* gg = g + int64_t(inst) * (m + 1);
+  gg[0] = beta[inst];
+  for (int i = 1; i <= m; ++i) gg[i] = 0.0;
+  kk[inst] = 0;
+}
+
+__global__ void k_bclose(int j, int n_inst, int* kk, const int* iact) {
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst < n_inst && iact[inst] && kk[inst] == 0) kk[inst] = j + 1;
+}
+
+template <int B, int NR, int K, class X, class T>
+hipError_t batched_t(int kind, const BEntry* E, int ne, int nb, double omega, const int* active, double* partials,
+                     hipStream_t s) {
+  switch (kind) {
+    case BK_SWEEP0: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_SWEEP0>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
+    case BK_SWEEP: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_SWEEP>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
+    case BK_DEFECT: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_DEFECT>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
+    case BK_RESTRICT: hipLaunchKernelGGL((k_belem<B, NR, X, T, BK_RESTRICT>), nb, kThreads, 0, s, E, ne, active); break;
+    case BK_PROLONG: hipLaunchKernelGGL((k_belem<B, NR, X, T, BK_PROLONG>), nb, kThreads, 0, s, E, ne, active); break;
+    case BK_FILL0: hipLaunchKernelGGL((k_belem<B, NR, X, T, BK_FILL0>), nb, kThreads, 0, s, E, ne, active); break;
+    case BK_COARSE: hipLaunchKernelGGL((k_bcoarse<NR, X>), nb, kThreads, 0, s, E, ne, active); break;
+    case BK_SPMV64: hipLaunchKernelGGL((k_bsell64<B, NR, X, BK_SPMV64>), nb, kThreads, 0, s, E, ne, active, partials); break;
+    case BK_DEFECT64: hipLaunchKernelGGL((k_bsell64<B, NR, double, BK_DEFECT64>), nb, kThreads, 0, s, E, ne, active, partials); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int B, int NR>
+hipError_t batched_bn(int kind, const BEntry* E, int ne, int nb, int vkind, int xk, double omega, const int* active,
+                      double* partials, hipStream_t s) {
+  if (xk == X_F64) {
+    if (vkind != VK_F64) return hipErrorInvalidValue;
+    return batched_t<B, NR, VK_F64, double, double>(kind, E, ne, nb, omega, active, partials, s);
+  }
+  switch (vkind) {
+    case VK_F32: return batched_t<B, NR, VK_F32, float, float>(kind, E, ne, nb, omega, active, partials, s);
+    case VK_F16: return batched_t<B, NR, VK_F16, float, float>(kind, E, ne, nb, omega, active, partials, s);
+    case VK_BF16: return batched_t<B, NR, VK_BF16, float, float>(kind, E, ne, nb, omega, active, partials, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+int batched_blocks(int kind, const SellDev& A, const CsrDev& T, int n0, int NR) {
+  switch (kind) {
+    case BK_SWEEP0: case BK_SWEEP: case BK_DEFECT: case BK_SPMV64: case BK_DEFECT64:
+      return int(slice_grid(A.nslices));
+    case BK_RESTRICT: case BK_PROLONG:
+      return int(grid_for(int64_t(T.nrows) * A.B * NR, kThreads));
+    case BK_FILL0:
+      return int(grid_for(int64_t(A.n) * A.B * NR, kThreads));
+    case BK_COARSE:
+      return int(grid_for(n0, kSliceWaves));
+    default:
+      return 0;
+  }
+}
+
+hipError_t launch_batched(int kind, const BEntry* E, int ne, int nb, int B, int NR, int vkind, int xk, double omega,
+                          const int* active, double* partials, hipStream_t s) {
+  if (nb == 0 || ne == 0) return hipSuccess;
+  if (NR == 1) {
+    switch (B) {
+      case 1: return batched_bn<1, 1>(kind, E, ne, nb, vkind, xk, omega, active, partials, s);
+      case 3: return batched_bn<3, 1>(kind, E, ne, nb, vkind, xk, omega, active, partials, s);
+      case 4: return batched_bn<4, 1>(kind, E, ne, nb, vkind, xk, omega, active, partials, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (NR == 8) {
+    switch (B) {
+      case 1: return batched_bn<1, 8>(kind, E, ne, nb, vkind, xk, omega, active, partials, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_bdot(const BSegs& g, const double* a, const double* b, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_bdot, g.n_blocks, kThreads, 0, s, g, a, b, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_bfinish(const double* partials, const int* pfirst, const int* pcount, int n_inst, int NR,
+                          double* out, int sqrt_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_bfinish, n_inst, kThreads, 0, s, partials, pfirst, pcount, NR, out, sqrt_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_bmgs_step(const BSegs& g, double* w, const double* vi, const double* vnext, const double* pin,
+                            double* pout, double* H, int64_t hstride, hipStream_t s) {
+  hipLaunchKernelGGL(k_bmgs_step, g.n_blocks, kThreads, 0, s, g, w, vi, vnext, pin, pout, H, hstride);
+  return hipGetLastError();
+}
+
+hipError_t launch_bmgs_normalize(const BSegs& g, double* w, const double* pin, double* H, int64_t hstride,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_bmgs_normalize, g.n_blocks, kThreads, 0, s, g, w, pin, H, hstride);
+  return hipGetLastError();
+}
+
+hipError_t launch_bscale(const BSegs& g, double* y, const double* x, const double* beta, const int* iact,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_bscale, g.n_blocks, kThreads, 0, s, g, y, x, beta, iact);
+  return hipGetLastError();
+}
+
+hipError_t launch_bupdate(const BSegs& g, double* x, const void* Z, int zk, int64_t ldz, const double* yv, int m,
+                          const int* kk, hipStream_t s) {
+  if (zk == X_F64)
+    hipLaunchKernelGGL(k_bupdate<double>, g.n_blocks, kThreads, 0, s, g, x, static_cast<const double*>(Z), ldz, yv, m, kk);
+  else
+    hipLaunchKernelGGL(k_bupdate<float>, g.n_blocks, kThreads, 0, s, g, x, static_cast<const float*>(Z), ldz, yv, m, kk);
+  return hipGetLastError();
+}
+
+hipError_t launch_bgivens(int j, int m, int n_inst, double* H, double* cs, double* sn, double* g, double* st,
+                          const double* tol, int* kk, const int* iact, hipStream_t s) {
+  hipLaunchKernelGGL(k_bgivens, grid_for(n_inst, 64), 64, 0, s, j, m, n_inst, H, cs, sn, g, st, tol, kk, iact);
+  return hipGetLastError();
+}
+
+hipError_t launch_bbacksolve(int m, int n_inst, const double* H, const double* g, double* yv, const int* kk,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_bbacksolve, grid_for(n_inst, 64), 64, 0, s, m, n_inst, H, g, yv, kk);
+  return hipGetLastError();
+}
+
+hipError_t launch_binit(int m, int n_inst, double* g, const double* beta, int* kk, hipStream_t s) {
+  hipLaunchKernelGGL(k_binit, grid_for(n_inst, 64), 64, 0, s, m, n_inst, g, beta, kk);
+  return hipGetLastError();
+}
+
+hipError_t launch_bclose(int j, int n_inst, int* kk, const int* iact, hipStream_t s) {
+  hipLaunchKernelGGL(k_bclose, grid_for(n_inst, 64), 64, 0, s, j, n_inst, kk, iact);
   return hipGetLastError();
 }
 

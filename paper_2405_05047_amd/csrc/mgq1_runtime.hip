@@ -171,18 +171,20 @@ uint16_t to_bf16_bits(double v) {
 }
 
 struct HostSell {
-  int32_t n = 0, B = 1, R = 64, nslices = 0;
+  int32_t n = 0, B = 1, R = 64, W = 64, nslices = 0;
   int64_t slots = 0;
   std::vector<int32_t> sptr, col;
-  std::vector<double> val;                          // slots * B * 64
-  std::vector<int8_t> rexp;                         // nslices * 64
+  std::vector<double> val;                          // slots * B * W
+  std::vector<int8_t> rexp;                         // nslices * W
 };
 
-HostSell build_sell(const HostLevel& L) {
+// sliced ELL with slices of R = 64 / (B * NR) nodes and padded row-lane stride W = 64 / NR
+HostSell build_sell(const HostLevel& L, int NR = 1) {
   HostSell S;
   S.n = L.n;
   S.B = L.B;
-  S.R = kWave / L.B;
+  S.R = kWave / (L.B * NR);
+  S.W = kWave / NR;
   S.nslices = (L.n + S.R - 1) / S.R;
   S.sptr.assign(size_t(S.nslices) + 1, 0);
   for (int32_t s = 0; s < S.nslices; ++s) {
@@ -194,10 +196,10 @@ HostSell build_sell(const HostLevel& L) {
     S.sptr[s + 1] = S.sptr[s] + w;
   }
   S.slots = S.sptr[S.nslices];
-  const int B = L.B;
+  const int B = L.B, W = S.W;
   S.col.assign(size_t(S.slots) * S.R, 0);
-  S.val.assign(size_t(S.slots) * B * kWave, 0.0);
-  S.rexp.assign(size_t(S.nslices) * kWave, 0);
+  S.val.assign(size_t(S.slots) * B * W, 0.0);
+  S.rexp.assign(size_t(S.nslices) * W, 0);
   for (int32_t s = 0; s < S.nslices; ++s) {
     const int32_t w = S.sptr[s + 1] - S.sptr[s];
     for (int r = 0; r < S.R; ++r) {
@@ -213,14 +215,14 @@ HostSell build_sell(const HostLevel& L) {
           for (int c = 0; c < B; ++c)
             for (int cc = 0; cc < B; ++cc) {
               const double v = L.val[size_t(src) * B * B + c * B + cc];
-              S.val[(slot * B + cc) * kWave + r * B + c] = v;
+              S.val[(slot * B + cc) * W + r * B + c] = v;
               mx[c] = std::max(mx[c], std::fabs(v));
             }
         } else {
           S.col[slot * S.R + r] = int32_t(i);
         }
       }
-      for (int c = 0; c < B; ++c) S.rexp[size_t(s) * kWave + r * B + c] = int8_t(row_exponent(mx[c]));
+      for (int c = 0; c < B; ++c) S.rexp[size_t(s) * W + r * B + c] = int8_t(row_exponent(mx[c]));
     }
   }
   return S;
@@ -255,6 +257,17 @@ CsrHost transpose(int32_t nrows, int32_t ncols, const std::vector<int32_t>& rp, 
 }  // namespace
 
 // ---------------------------------------------------------------- handle
+// owner of device allocations (freed on destruction)
+struct DevOwner {
+  std::vector<void*> allocs;
+  DevOwner() = default;
+  DevOwner(const DevOwner&) = delete;
+  DevOwner& operator=(const DevOwner&) = delete;
+  ~DevOwner() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
 struct LevelDev {
   int32_t n = 0, B = 1;
   int64_t N = 0, nnzb = 0;
@@ -266,7 +279,7 @@ struct LevelDev {
   void *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;   // cycle vectors
 };
 
-struct mg_handle {
+struct mg_handle : DevOwner {
   mg_config cfg{};
   int L = 0;
   int xk = X_F64;         // vector kind inside the cycle
@@ -289,12 +302,10 @@ struct mg_handle {
   double* hs = nullptr;   // pinned host scalars
   hipStream_t cap = nullptr;             // private stream used only to capture graphs
   std::vector<hipGraphExec_t> step_graph; // FGMRES step j (V-cycle, SpMV, MGS, Givens)
-  std::vector<void*> allocs;
   ~mg_handle() {
     for (hipGraphExec_t g : step_graph)
       if (g) (void)hipGraphExecDestroy(g);
     if (cap) (void)hipStreamDestroy(cap);
-    for (void* p : allocs) (void)hipFree(p);
     if (hs) (void)hipHostFree(hs);
   }
 };
@@ -302,7 +313,7 @@ struct mg_handle {
 namespace {
 
 template <class T>
-int dalloc(mg_handle* h, T** p, size_t count) {
+int dalloc(DevOwner* h, T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
   void* q = nullptr;
@@ -314,7 +325,7 @@ int dalloc(mg_handle* h, T** p, size_t count) {
 }
 
 template <class T>
-int upload(mg_handle* h, T** p, const std::vector<T>& src, hipStream_t s) {
+int upload(DevOwner* h, T** p, const std::vector<T>& src, hipStream_t s) {
   int rc = dalloc(h, p, src.size());
   if (rc) return rc;
   if (!src.empty()) MG_HIP(hipMemcpyAsync(*p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
@@ -323,7 +334,7 @@ int upload(mg_handle* h, T** p, const std::vector<T>& src, hipStream_t s) {
 
 size_t xsize(int xk) { return xk == X_F64 ? 8 : 4; }
 
-int upload_sell(mg_handle* h, const HostSell& S, int kind, SellDev& D, hipStream_t s) {
+int upload_sell(DevOwner* h, const HostSell& S, int kind, SellDev& D, hipStream_t s) {
   D.n = S.n;
   D.B = S.B;
   D.R = S.R;
@@ -354,9 +365,9 @@ int upload_sell(mg_handle* h, const HostSell& S, int kind, SellDev& D, hipStream
     for (int32_t sl = 0; sl < S.nslices; ++sl)
       for (int32_t k = S.sptr[sl]; k < S.sptr[sl + 1]; ++k)
         for (int cc = 0; cc < S.B; ++cc)
-          for (int ln = 0; ln < kWave; ++ln) {
-            const size_t idx = (size_t(k) * S.B + cc) * kWave + ln;
-            const double sc = std::ldexp(S.val[idx], -int(S.rexp[size_t(sl) * kWave + ln]));
+          for (int ln = 0; ln < S.W; ++ln) {
+            const size_t idx = (size_t(k) * S.B + cc) * S.W + ln;
+            const double sc = std::ldexp(S.val[idx], -int(S.rexp[size_t(sl) * S.W + ln]));
             q[idx] = kind == VK_F16 ? to_f16_bits(sc) : to_bf16_bits(sc);
           }
     uint16_t* v;
@@ -370,7 +381,7 @@ int upload_sell(mg_handle* h, const HostSell& S, int kind, SellDev& D, hipStream
   return MG_OK;
 }
 
-int upload_csr(mg_handle* h, const CsrHost& C, CsrDev& D, hipStream_t s) {
+int upload_csr(DevOwner* h, const CsrHost& C, CsrDev& D, hipStream_t s) {
   D.nrows = C.nrows;
   D.ncols = C.ncols;
   D.nnz = int64_t(C.col.size());
@@ -633,6 +644,703 @@ int check_level(const mg_handle* h, int level) {
 
 }  // namespace
 
+namespace {
+
+int value_kind(int precision) {
+  return precision == MG_PREC_FP64 ? VK_F64
+         : precision == MG_PREC_FP32 ? VK_F32
+         : precision == MG_PREC_FP32_F16VAL ? VK_F16 : VK_BF16;
+}
+
+int check_config(const mg_config& c) {
+  if (!(c.omega > 0.0) || c.nu1 < 0 || c.nu2 < 0 || c.nu1 + c.nu2 < 1 || c.gmres_m < 1 || c.gmres_m > 64 ||
+      c.maxit < 0 || !(c.rtol >= 0.0) || c.precision < MG_PREC_FP64 || c.precision > MG_PREC_FP32_BF16VAL ||
+      (c.outer != MG_OUTER_IR && c.outer != MG_OUTER_FGMRES) ||
+      (c.coarse_mode != MG_COARSE_EXACT && c.coarse_mode != MG_COARSE_SMOOTH))
+    return fail(MG_EINVAL, "invalid configuration");
+  return MG_OK;
+}
+
+int load_hierarchy(const mg_level_in* lv, int n_levels, bool on_dev, std::vector<HostLevel>& H) {
+  H.resize(n_levels);
+  try {
+    for (int l = 0; l < n_levels; ++l) {
+      int rc = load_level(lv[l], on_dev, l > 0, H[l]);
+      if (rc) return rc;
+      rc = validate_host(H[l], l > 0 ? &H[l - 1] : nullptr, l);
+      if (rc) return rc;
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(MG_ENOMEM, "host allocation failed");
+  }
+  if (H[0].B > 4) return fail(MG_EUNSUPPORTED, "block sizes above 4 are not implemented");
+  if (int64_t(H[0].n) * H[0].B > 4096) return fail(MG_EUNSUPPORTED, "coarse problem above 4096 DoFs");
+  return MG_OK;
+}
+
+// one level on the device: FP64 and cycle operators (sliced ELL for NR right-hand sides),
+// smoother blocks, mask, P~ and R = P~^T; with vectors = true also x, b, r, t
+int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, int xk, bool vectors, int* flag,
+                hipStream_t s, LevelDev& D) {
+  int rc;
+  D.n = L.n;
+  D.B = L.B;
+  D.N = int64_t(L.n) * L.B;
+  D.nnzb = L.nnzb;
+  HostSell S = build_sell(L, NR);
+  if ((rc = upload_sell(h, S, VK_F64, D.A64, s))) return rc;
+  if (vkind == VK_F64) D.Ac = D.A64;
+  else if ((rc = upload_sell(h, S, vkind, D.Ac, s))) return rc;
+  const size_t sblk = size_t(S.nslices) * L.B * S.W;
+  if ((rc = dalloc(h, reinterpret_cast<char**>(&D.S), sblk * xsize(xk)))) return rc;
+  MG_HIP(launch_fill(int64_t(sblk), D.S, xk, 0.0, s));
+  MG_HIP(launch_block_invert(D.A64, D.S, xk, flag, NR, s));
+  if ((rc = upload(h, &D.mask, L.mask, s))) return rc;
+  if (has_p) {
+    CsrHost P;
+    P.nrows = L.n;
+    P.ncols = L.pc;
+    P.rowptr = L.prow;
+    P.col = L.pcol;
+    P.val = L.pval;
+    if ((rc = upload_csr(h, P, D.P, s))) return rc;
+    CsrHost R = transpose(L.n, L.pc, L.prow, L.pcol, L.pval);
+    if ((rc = upload_csr(h, R, D.R, s))) return rc;
+  }
+  if (vectors) {
+    const size_t vb = size_t(D.N) * NR * xsize(xk);
+    char* p;
+    for (void** v : {&D.x, &D.b, &D.r, &D.t}) {
+      if ((rc = dalloc(h, &p, vb))) return rc;
+      *v = p;
+    }
+  }
+  MG_HIP(hipStreamSynchronize(s));
+  return MG_OK;
+}
+
+// dense inverse of the coarse operator (GPU Gauss-Jordan), row-major FP64
+int setup_coarse_inverse(DevOwner* h, const HostLevel& C0, int* flag, hipStream_t s, double** Ainv, int* n0out) {
+  const int B = C0.B;
+  const int n0 = C0.n * B;
+  *n0out = n0;
+  std::vector<double> M(size_t(n0) * 2 * n0, 0.0);
+  for (int32_t i = 0; i < C0.n; ++i)
+    for (int32_t k = C0.rowptr[i]; k < C0.rowptr[i + 1]; ++k)
+      for (int c1 = 0; c1 < B; ++c1)
+        for (int c2 = 0; c2 < B; ++c2)
+          M[size_t(i * B + c1) * 2 * n0 + size_t(C0.col[k]) * B + c2] = C0.val[size_t(k) * B * B + c1 * B + c2];
+  for (int i = 0; i < n0; ++i) M[size_t(i) * 2 * n0 + n0 + i] = 1.0;
+  double *dM, *piv;
+  int rc;
+  if ((rc = upload(h, &dM, M, s))) return rc;
+  MG_HIP(hipStreamSynchronize(s));
+  if ((rc = dalloc(h, &piv, size_t(2) * n0))) return rc;
+  if ((rc = dalloc(h, Ainv, size_t(n0) * n0))) return rc;
+  MG_HIP(launch_coarse_invert(n0, dM, *Ainv, piv, flag, s));
+  return MG_OK;
+}
+
+int check_flag(int* flag, hipStream_t s) {
+  int hflag = 0;
+  MG_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  if (hflag) return fail(MG_ESINGULAR, "singular nodal diagonal block or coarse matrix");
+  return MG_OK;
+}
+
+int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
+  const mg_config& c = h->cfg;
+  const int n_levels = int(H.size());
+  int rc;
+  int* flag;
+  if ((rc = dalloc(h, &flag, 1))) return rc;
+  h->dflag = flag;
+  MG_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+  const int vkind = value_kind(c.precision);
+  for (int l = 0; l < n_levels; ++l)
+    if ((rc = setup_level(h, H[l], l > 0, 1, vkind, h->xk, true, flag, s, h->lv[l]))) return rc;
+  if ((rc = setup_coarse_inverse(h, H[0], flag, s, &h->Ainv, &h->n0))) return rc;
+  if ((rc = check_flag(flag, s))) return rc;
+  // outer-loop storage
+  const int64_t N = h->lv[h->L].N;
+  const int m = c.gmres_m;
+  if ((rc = dalloc(h, &h->rout, size_t(N)))) return rc;
+  char* p;
+  if ((rc = dalloc(h, &p, size_t(N) * xsize(h->xk)))) return rc;
+  h->e = p;
+  if ((rc = dalloc(h, &p, size_t(N) * xsize(h->xk)))) return rc;
+  h->bcyc = p;
+  if (c.outer == MG_OUTER_FGMRES) {
+    if ((rc = dalloc(h, &h->V, size_t(m + 1) * N))) return rc;
+    if ((rc = dalloc(h, &p, size_t(m) * N * xsize(h->xk)))) return rc;
+    h->Z = p;
+  }
+  if ((rc = dalloc(h, &h->H, size_t(m + 1) * m))) return rc;
+  if ((rc = dalloc(h, &h->cs, size_t(m)))) return rc;
+  if ((rc = dalloc(h, &h->sn, size_t(m)))) return rc;
+  if ((rc = dalloc(h, &h->g, size_t(m) + 1))) return rc;
+  if ((rc = dalloc(h, &h->y, size_t(m)))) return rc;
+  if ((rc = dalloc(h, &h->dsc, 8))) return rc;
+  MG_HIP(launch_fill(8, h->dsc, X_F64, 0.0, s));
+  MG_HIP(launch_fill(1, h->dsc + 1, X_F64, 1.0, s));
+  int64_t maxgrid = 1;
+  for (const LevelDev& D : h->lv) maxgrid = std::max<int64_t>(maxgrid, spmv_grid(D.A64));
+  if ((rc = dalloc(h, &h->pbig, size_t(maxgrid)))) return rc;
+  for (int q = 0; q < 2; ++q)
+    if ((rc = dalloc(h, &h->pv[q], size_t(kMaxRedBlocks)))) return rc;
+  // tail: every level up to the largest one with at most tail_dofs unknowns.  Default off:
+  // on MI355X one workgroup walking several levels was measured slower (dependent-load
+  // latency serialises) than separate grid launches per step.
+  int64_t tail_dofs = 0;
+  if (const char* e = std::getenv("MGQ1_TAIL_DOFS")) tail_dofs = std::atoll(e);
+  int top = 0;
+  for (int l = 1; l <= h->L; ++l)
+    if (h->lv[l].N <= tail_dofs) top = l;
+  h->tail_top = top;
+  std::vector<TailLevel> tl(top + 1);
+  for (int l = 0; l <= top; ++l) {
+    const LevelDev& D = h->lv[l];
+    tl[l].A = D.Ac;
+    tl[l].S = D.S;
+    tl[l].mask = D.mask;
+    tl[l].P = D.P;
+    tl[l].R = D.R;
+    tl[l].x = D.x;
+    tl[l].b = D.b;
+    tl[l].r = D.r;
+    tl[l].t = D.t;
+  }
+  if ((rc = dalloc(h, &h->dtail, tl.size()))) return rc;
+  MG_HIP(hipMemcpyAsync(h->dtail, tl.data(), tl.size() * sizeof(TailLevel), hipMemcpyHostToDevice, s));
+  MG_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hs), 16 * sizeof(double), hipHostMallocDefault));
+  h->step_graph.assign(size_t(m), nullptr);
+  if (c.use_graph) MG_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  MG_HIP(hipStreamSynchronize(s));
+  return MG_OK;
+}
+
+}  // namespace
+
+
+// ---------------------------------------------------------------- batched handle
+struct BLaunch {
+  int kind = 0;
+  size_t e0 = 0;     // first entry in the batch's entry table
+  int ne = 0, nb = 0;
+};
+
+struct mg_batch : DevOwner {
+  mg_config cfg{};
+  int NR = 1, P = 0, B = 1, xk = X_F64, vkind = VK_F64, n_inst = 0, Dmax = 0;
+  struct Prob {
+    int L = 0;
+    std::vector<LevelDev> lv;
+    double* Ainv = nullptr;
+    int n0 = 0;
+  };
+  std::vector<Prob> pr;
+  std::vector<int64_t> off;           // P + 1 element offsets in the concatenated vectors
+  int64_t Ntot = 0;
+  void *btop = nullptr, *ttop = nullptr, *rtop = nullptr;   // top-level cycle vectors
+  double *V = nullptr, *rout = nullptr;
+  void* Z = nullptr;
+  double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *yv = nullptr, *st = nullptr;
+  double *beta = nullptr, *bnorm = nullptr, *tolv = nullptr;
+  int *kk = nullptr, *iact = nullptr, *pact = nullptr;
+  double* pvec[2] = {nullptr, nullptr};
+  double* pbig = nullptr;
+  BSegs segs;
+  int *bigfirst = nullptr, *bigcount = nullptr;
+  std::vector<BEntry> hE;             // entry tables of every planned launch
+  BEntry* dE = nullptr;
+  BEntry* dEdef = nullptr;            // outer-defect entries (rebuilt per solve for b, x)
+  std::vector<std::vector<BLaunch>> plan;   // per Krylov index: V-cycle launches
+  std::vector<BLaunch> spmv64;        // per Krylov index: w = A z_j
+  int nbig = 0;                       // blocks of the outer FP64 products
+  hipStream_t cap = nullptr;
+  std::vector<hipGraphExec_t> graphs;
+  int* hkk = nullptr;                 // pinned host copy of kk (read after every step)
+  ~mg_batch() {
+    for (hipGraphExec_t gx : graphs)
+      if (gx) (void)hipGraphExecDestroy(gx);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (hkk) (void)hipHostFree(hkk);
+  }
+};
+
+namespace {
+
+// append one launch (entries already filled except `first`) to the batch plan
+BLaunch add_launch(mg_batch* h, int kind, std::vector<BEntry>& es) {
+  BLaunch L;
+  L.kind = kind;
+  L.e0 = h->hE.size();
+  int first = 0;
+  for (BEntry& e : es) {
+    e.first = first;
+    first += batched_blocks(kind, e.A, e.T, e.n0, h->NR);
+    h->hE.push_back(e);
+  }
+  L.ne = int(es.size());
+  L.nb = first;
+  return L;
+}
+
+// static launch plan of one V-cycle of every problem for Krylov index j: the top level of
+// problem p reads its right-hand side from the cycle copy of v_j and writes z_j
+void build_plan(mg_batch* h, int j, std::vector<BLaunch>& out) {
+  const mg_config& c = h->cfg;
+  const int pre_pp = c.nu1 >= 1 ? c.nu1 - 1 : 0;
+  const int pp = pre_pp + c.nu2;
+  const size_t xs = xsize(h->xk);
+  auto top_x = [&](int p) { return static_cast<char*>(h->Z) + (size_t(j) * h->Ntot + h->off[p]) * xs; };
+  auto top_b = [&](int p) -> void* {
+    if (h->xk == X_F64) return reinterpret_cast<char*>(h->V + int64_t(j) * h->Ntot + h->off[p]);
+    return static_cast<char*>(h->btop) + size_t(h->off[p]) * xs;
+  };
+  const int P = h->P;
+  std::vector<std::vector<void*>> own(P), tmp(P), bb(P), rr(P), cur(P), oth(P);
+  for (int p = 0; p < P; ++p) {
+    const int L = h->pr[p].L;
+    own[p].resize(L + 1);
+    tmp[p].resize(L + 1);
+    bb[p].resize(L + 1);
+    rr[p].resize(L + 1);
+    cur[p].resize(L + 1);
+    oth[p].resize(L + 1);
+    for (int l = 0; l <= L; ++l) {
+      const LevelDev& D = h->pr[p].lv[l];
+      own[p][l] = (l == L) ? static_cast<void*>(top_x(p)) : D.x;
+      tmp[p][l] = (l == L) ? static_cast<char*>(h->ttop) + size_t(h->off[p]) * xs : static_cast<char*>(D.t);
+      bb[p][l] = (l == L) ? top_b(p) : D.b;
+      rr[p][l] = (l == L) ? static_cast<char*>(h->rtop) + size_t(h->off[p]) * xs : static_cast<char*>(D.r);
+      cur[p][l] = (pp % 2 == 0) ? own[p][l] : tmp[p][l];
+      oth[p][l] = (pp % 2 == 0) ? tmp[p][l] : own[p][l];
+    }
+  }
+  auto level_entry = [&](int p, int l) {
+    const LevelDev& D = h->pr[p].lv[l];
+    BEntry e;
+    e.A = D.Ac;
+    e.S = D.S;
+    e.mask = D.mask;
+    e.prob = p;
+    return e;
+  };
+  // descent, aligned by depth below each problem's finest level
+  for (int d = 0; d < h->Dmax; ++d) {
+    std::vector<int> ps;
+    for (int p = 0; p < P; ++p)
+      if (h->pr[p].L - d >= 1) ps.push_back(p);
+    if (ps.empty()) continue;
+    std::vector<BEntry> es;
+    if (c.nu1 >= 1) {
+      es.clear();
+      for (int p : ps) {
+        const int l = h->pr[p].L - d;
+        BEntry e = level_entry(p, l);
+        e.in0 = bb[p][l];
+        e.out = cur[p][l];
+        es.push_back(e);
+      }
+      out.push_back(add_launch(h, BK_SWEEP0, es));
+      for (int q = 1; q < c.nu1; ++q) {
+        es.clear();
+        for (int p : ps) {
+          const int l = h->pr[p].L - d;
+          BEntry e = level_entry(p, l);
+          e.in0 = bb[p][l];
+          e.in1 = cur[p][l];
+          e.out = oth[p][l];
+          es.push_back(e);
+          std::swap(cur[p][l], oth[p][l]);
+        }
+        out.push_back(add_launch(h, BK_SWEEP, es));
+      }
+    } else {
+      es.clear();
+      for (int p : ps) {
+        const int l = h->pr[p].L - d;
+        BEntry e = level_entry(p, l);
+        e.out = cur[p][l];
+        es.push_back(e);
+      }
+      out.push_back(add_launch(h, BK_FILL0, es));
+    }
+    es.clear();
+    for (int p : ps) {
+      const int l = h->pr[p].L - d;
+      BEntry e = level_entry(p, l);
+      e.in0 = bb[p][l];
+      e.in1 = cur[p][l];
+      e.out = rr[p][l];
+      es.push_back(e);
+    }
+    out.push_back(add_launch(h, BK_DEFECT, es));
+    es.clear();
+    for (int p : ps) {
+      const int l = h->pr[p].L - d;
+      BEntry e = level_entry(p, l);
+      e.T = h->pr[p].lv[l].R;
+      e.mask_c = h->pr[p].lv[l - 1].mask;
+      e.in0 = rr[p][l];
+      e.out = bb[p][l - 1];
+      es.push_back(e);
+    }
+    out.push_back(add_launch(h, BK_RESTRICT, es));
+  }
+  // coarse solves of all problems
+  {
+    std::vector<BEntry> es;
+    for (int p = 0; p < P; ++p) {
+      BEntry e = level_entry(p, 0);
+      e.Ainv = h->pr[p].Ainv;
+      e.n0 = h->pr[p].n0;
+      e.in0 = bb[p][0];
+      e.out = own[p][0];
+      es.push_back(e);
+    }
+    out.push_back(add_launch(h, BK_COARSE, es));
+  }
+  // ascent
+  for (int d = h->Dmax - 1; d >= 0; --d) {
+    std::vector<int> ps;
+    for (int p = 0; p < P; ++p)
+      if (h->pr[p].L - d >= 1) ps.push_back(p);
+    if (ps.empty()) continue;
+    // the descent left cur at the pre-smoothed iterate; the coarser level's correction
+    // sits in its own x (its post-smoothing ends there)
+    std::vector<BEntry> es;
+    for (int p : ps) {
+      const int l = h->pr[p].L - d;
+      BEntry e = level_entry(p, l);
+      e.T = h->pr[p].lv[l].P;
+      e.mask_c = h->pr[p].lv[l - 1].mask;
+      e.in0 = own[p][l - 1];
+      e.out = cur[p][l];
+      es.push_back(e);
+    }
+    out.push_back(add_launch(h, BK_PROLONG, es));
+    for (int q = 0; q < c.nu2; ++q) {
+      es.clear();
+      for (int p : ps) {
+        const int l = h->pr[p].L - d;
+        BEntry e = level_entry(p, l);
+        e.in0 = bb[p][l];
+        e.in1 = cur[p][l];
+        e.out = oth[p][l];
+        es.push_back(e);
+        std::swap(cur[p][l], oth[p][l]);
+      }
+      out.push_back(add_launch(h, BK_SWEEP, es));
+    }
+  }
+}
+
+int run_launch(mg_batch* h, const BLaunch& L, const BEntry* table, const int* active, double* partials, hipStream_t s) {
+  MG_HIP(launch_batched(L.kind, table + L.e0, L.ne, L.nb, h->B, h->NR, h->vkind, h->xk, h->cfg.omega, active,
+                        partials, s));
+  return MG_OK;
+}
+
+// one lockstep FGMRES step j for every instance
+int enqueue_batch_step(mg_batch* h, int j, hipStream_t s) {
+  const int m = h->cfg.gmres_m;
+  const int64_t N = h->Ntot;
+  int rc;
+  if (h->xk != X_F64) MG_HIP(launch_convert(N, h->V + int64_t(j) * N, X_F64, h->btop, h->xk, s));
+  for (const BLaunch& L : h->plan[j])
+    if ((rc = run_launch(h, L, h->dE, h->pact, nullptr, s))) return rc;
+  if ((rc = run_launch(h, h->spmv64[j], h->dE, h->pact, nullptr, s))) return rc;
+  double* w = h->V + int64_t(j + 1) * N;
+  const int64_t hs = int64_t(m + 1) * m;
+  double* Hj = h->H + int64_t(j) * (m + 1);
+  MG_HIP(launch_bdot(h->segs, w, h->V, h->pvec[0], s));
+  for (int i = 0; i <= j; ++i) {
+    const double* vi = h->V + int64_t(i) * N;
+    const double* vn = (i < j) ? h->V + int64_t(i + 1) * N : nullptr;
+    MG_HIP(launch_bmgs_step(h->segs, w, vi, vn, h->pvec[i & 1], h->pvec[(i + 1) & 1], Hj + i, hs, s));
+  }
+  MG_HIP(launch_bmgs_normalize(h->segs, w, h->pvec[(j + 1) & 1], Hj + j + 1, hs, s));
+  MG_HIP(launch_bgivens(j, m, h->n_inst, h->H, h->cs, h->sn, h->g, h->st, h->tolv, h->kk, h->iact, s));
+  return MG_OK;
+}
+
+int batch_step(mg_batch* h, int j, hipStream_t s) {
+  if (!h->cfg.use_graph) return enqueue_batch_step(h, j, s);
+  if (!h->graphs[j]) {
+    hipGraph_t gr = nullptr;
+    MG_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_batch_step(h, j, h->cap);
+    const hipError_t e = hipStreamEndCapture(h->cap, &gr);
+    if (rc) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(MG_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e2 != hipSuccess) return fail(MG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+    h->graphs[j] = ex;
+  }
+  MG_HIP(hipGraphLaunch(h->graphs[j], s));
+  return MG_OK;
+}
+
+// beta = ||b - A x|| per instance of the active problems (r stored in rout)
+int batch_defect(mg_batch* h, hipStream_t s) {
+  BLaunch L;
+  L.kind = BK_DEFECT64;
+  L.e0 = 0;
+  L.ne = h->P;
+  L.nb = h->nbig;
+  int rc;
+  if ((rc = run_launch(h, L, h->dEdef, h->pact, h->pbig, s))) return rc;
+  MG_HIP(launch_bfinish(h->pbig, h->bigfirst, h->bigcount, h->n_inst, h->NR, h->beta, 1, s));
+  return MG_OK;
+}
+
+int setup_batch(mg_batch* h, const std::vector<std::vector<HostLevel>>& HH, hipStream_t s) {
+  const mg_config& c = h->cfg;
+  const int P = h->P, NR = h->NR;
+  int rc;
+  int* flag;
+  if ((rc = dalloc(h, &flag, 1))) return rc;
+  MG_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+  h->pr.resize(P);
+  h->off.assign(size_t(P) + 1, 0);
+  for (int p = 0; p < P; ++p) {
+    const auto& H = HH[p];
+    auto& pr = h->pr[p];
+    pr.L = int(H.size()) - 1;
+    h->Dmax = std::max(h->Dmax, pr.L);
+    pr.lv.resize(H.size());
+    for (int l = 0; l <= pr.L; ++l)
+      if ((rc = setup_level(h, H[l], l > 0, NR, h->vkind, h->xk, l < pr.L, flag, s, pr.lv[l]))) return rc;
+    if ((rc = setup_coarse_inverse(h, H[0], flag, s, &pr.Ainv, &pr.n0))) return rc;
+    h->off[p + 1] = h->off[p] + pr.lv[pr.L].N * NR;
+  }
+  if ((rc = check_flag(flag, s))) return rc;
+  const int64_t N = h->Ntot = h->off[P];
+  const int m = c.gmres_m;
+  const size_t xs = xsize(h->xk);
+  char* p8;
+  for (void** v : {&h->btop, &h->ttop, &h->rtop}) {
+    if ((rc = dalloc(h, &p8, size_t(N) * xs))) return rc;
+    *v = p8;
+  }
+  if ((rc = dalloc(h, &h->V, size_t(m + 1) * N))) return rc;
+  if ((rc = dalloc(h, &h->rout, size_t(N)))) return rc;
+  if ((rc = dalloc(h, &p8, size_t(m) * N * xs))) return rc;
+  h->Z = p8;
+  const int ni = h->n_inst = P * NR;
+  if ((rc = dalloc(h, &h->H, size_t(ni) * (m + 1) * m))) return rc;
+  if ((rc = dalloc(h, &h->cs, size_t(ni) * m))) return rc;
+  if ((rc = dalloc(h, &h->sn, size_t(ni) * m))) return rc;
+  if ((rc = dalloc(h, &h->g, size_t(ni) * (m + 1)))) return rc;
+  if ((rc = dalloc(h, &h->yv, size_t(ni) * m))) return rc;
+  if ((rc = dalloc(h, &h->st, size_t(ni) * 2))) return rc;
+  if ((rc = dalloc(h, &h->beta, size_t(ni)))) return rc;
+  if ((rc = dalloc(h, &h->bnorm, size_t(ni)))) return rc;
+  if ((rc = dalloc(h, &h->tolv, size_t(ni)))) return rc;
+  if ((rc = dalloc(h, &h->kk, size_t(ni)))) return rc;
+  if ((rc = dalloc(h, &h->iact, size_t(ni)))) return rc;
+  if ((rc = dalloc(h, &h->pact, size_t(P)))) return rc;
+  // vector segments: up to kSegBlocksMax blocks per problem
+  std::vector<int64_t> len(P);
+  std::vector<int> vfirst(P), vcount(P), blk;
+  for (int p = 0; p < P; ++p) {
+    len[p] = h->off[p + 1] - h->off[p];
+    vfirst[p] = int(blk.size());
+    vcount[p] = int(std::min<int64_t>(kSegBlocksMax, std::max<int64_t>(1, (len[p] + 255) / 256)));
+    for (int b = 0; b < vcount[p]; ++b) blk.push_back(p);
+  }
+  int64_t *doff, *dlen;
+  int *dvf, *dvc, *dblk;
+  std::vector<int64_t> offv(h->off.begin(), h->off.end() - 1);
+  if ((rc = upload(h, &doff, offv, s))) return rc;
+  if ((rc = upload(h, &dlen, len, s))) return rc;
+  if ((rc = upload(h, &dvf, vfirst, s))) return rc;
+  if ((rc = upload(h, &dvc, vcount, s))) return rc;
+  if ((rc = upload(h, &dblk, blk, s))) return rc;
+  h->segs.off = doff;
+  h->segs.len = dlen;
+  h->segs.vfirst = dvf;
+  h->segs.vcount = dvc;
+  h->segs.blk_prob = dblk;
+  h->segs.n_blocks = int(blk.size());
+  h->segs.NR = NR;
+  for (int q = 0; q < 2; ++q)
+    if ((rc = dalloc(h, &h->pvec[q], blk.size() * NR))) return rc;
+  // outer FP64 products: blocks per problem
+  std::vector<int> bf(P), bc(P);
+  int nbig = 0;
+  for (int p = 0; p < P; ++p) {
+    bf[p] = nbig;
+    bc[p] = spmv_grid(h->pr[p].lv[h->pr[p].L].A64);
+    nbig += bc[p];
+  }
+  h->nbig = nbig;
+  if ((rc = upload(h, &h->bigfirst, bf, s))) return rc;
+  if ((rc = upload(h, &h->bigcount, bc, s))) return rc;
+  if ((rc = dalloc(h, &h->pbig, size_t(nbig) * NR))) return rc;
+  if ((rc = dalloc(h, &h->dEdef, size_t(P)))) return rc;
+  // launch plans
+  h->plan.assign(size_t(m), {});
+  h->spmv64.assign(size_t(m), BLaunch());
+  for (int j = 0; j < m; ++j) {
+    build_plan(h, j, h->plan[j]);
+    std::vector<BEntry> es;
+    for (int p = 0; p < P; ++p) {
+      const LevelDev& D = h->pr[p].lv[h->pr[p].L];
+      BEntry e;
+      e.A = D.A64;
+      e.prob = p;
+      e.in1 = static_cast<char*>(h->Z) + (size_t(j) * N + h->off[p]) * xs;
+      e.out = h->V + int64_t(j + 1) * N + h->off[p];
+      es.push_back(e);
+    }
+    h->spmv64[j] = add_launch(h, BK_SPMV64, es);
+  }
+  if ((rc = upload(h, &h->dE, h->hE, s))) return rc;
+  MG_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hkk), sizeof(int) * ni, hipHostMallocDefault));
+  h->graphs.assign(size_t(m), nullptr);
+  if (c.use_graph) MG_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  MG_HIP(hipStreamSynchronize(s));
+  return MG_OK;
+}
+
+template <class T>
+int to_host(T* dst, const T* src, size_t n, hipStream_t s) {
+  MG_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  MG_HIP(hipStreamSynchronize(s));
+  return MG_OK;
+}
+
+template <class T>
+int to_dev(T* dst, const T* src, size_t n, hipStream_t s) {
+  MG_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+  MG_HIP(hipStreamSynchronize(s));
+  return MG_OK;
+}
+
+int solve_batch_impl(mg_batch* h, const double* b, double* x, mg_solve_stats* st, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const mg_config& c = h->cfg;
+  const int P = h->P, NR = h->NR, ni = h->n_inst, m = c.gmres_m;
+  const int64_t N = h->Ntot;
+  int rc;
+  // outer-defect entries for this call's b and x
+  std::vector<BEntry> es(P);
+  int first = 0;
+  for (int p = 0; p < P; ++p) {
+    const LevelDev& D = h->pr[p].lv[h->pr[p].L];
+    es[p].A = D.A64;
+    es[p].prob = p;
+    es[p].in0 = b + h->off[p];
+    es[p].in1 = x + h->off[p];
+    es[p].out = h->rout + h->off[p];
+    es[p].first = first;
+    first += spmv_grid(D.A64);
+  }
+  if ((rc = to_dev(h->dEdef, es.data(), es.size(), s))) return rc;
+  // per-instance ||b|| and tolerances
+  MG_HIP(launch_bdot(h->segs, b, nullptr, h->pvec[0], s));
+  MG_HIP(launch_bfinish(h->pvec[0], h->segs.vfirst, h->segs.vcount, ni, NR, h->bnorm, 1, s));
+  std::vector<double> bn(ni), tol(ni), beta(ni), res0(ni), resf(ni);
+  if ((rc = to_host(bn.data(), h->bnorm, ni, s))) return rc;
+  for (int i = 0; i < ni; ++i) tol[i] = c.rtol * bn[i];
+  if ((rc = to_dev(h->tolv, tol.data(), ni, s))) return rc;
+  std::vector<int> iact(ni, 1), pact(P, 1), iters(ni, 0), restarts(ni, 0), conv(ni, 0), status(ni, MG_OK), kk(ni);
+  if ((rc = to_dev(h->pact, pact.data(), P, s))) return rc;
+  if ((rc = batch_defect(h, s))) return rc;
+  if ((rc = to_host(beta.data(), h->beta, ni, s))) return rc;
+  for (int i = 0; i < ni; ++i) {
+    res0[i] = resf[i] = beta[i];
+    if (!std::isfinite(beta[i])) { status[i] = MG_ENUMERIC; iact[i] = 0; }
+    else if (beta[i] <= tol[i]) { conv[i] = 1; iact[i] = 0; }
+  }
+  for (int i = 0; i < ni; ++i)
+    if (iact[i] && c.maxit <= 0) iact[i] = 0;
+  while (true) {
+    bool any = false;
+    for (int p = 0; p < P; ++p) {
+      pact[p] = 0;
+      for (int q = 0; q < NR; ++q) pact[p] |= iact[p * NR + q];
+      any = any || pact[p];
+    }
+    if (!any) break;
+    if ((rc = to_dev(h->iact, iact.data(), ni, s))) return rc;
+    if ((rc = to_dev(h->pact, pact.data(), P, s))) return rc;
+    MG_HIP(launch_bscale(h->segs, h->V, h->rout, h->beta, h->iact, s));
+    MG_HIP(launch_binit(m, ni, h->g, h->beta, h->kk, s));
+    int jl = 0;
+    for (int j = 0; j < m; ++j) {
+      if ((rc = batch_step(h, j, s))) return rc;
+      jl = j;
+      if ((rc = to_host(h->hkk, h->kk, ni, s))) return rc;
+      // an instance whose V-cycle budget ends here closes its cycle like the single solve
+      bool open = false, dirty = false;
+      for (int i = 0; i < ni; ++i) {
+        if (!iact[i] || h->hkk[i] != 0) continue;
+        if (iters[i] + j + 1 >= c.maxit) {
+          h->hkk[i] = j + 1;
+          dirty = true;
+        } else {
+          open = true;
+        }
+      }
+      if (dirty && (rc = to_dev(h->kk, h->hkk, ni, s))) return rc;
+      if (!open) break;
+    }
+    MG_HIP(launch_bclose(jl, ni, h->kk, h->iact, s));
+    MG_HIP(launch_bbacksolve(m, ni, h->H, h->g, h->yv, h->kk, s));
+    MG_HIP(launch_bupdate(h->segs, x, h->Z, h->xk, N, h->yv, m, h->kk, s));
+    if ((rc = to_host(kk.data(), h->kk, ni, s))) return rc;
+    if ((rc = batch_defect(h, s))) return rc;
+    if ((rc = to_host(beta.data(), h->beta, ni, s))) return rc;
+    for (int i = 0; i < ni; ++i) {
+      if (!iact[i]) continue;
+      iters[i] += kk[i];
+      restarts[i] += 1;
+      resf[i] = beta[i];
+      if (!std::isfinite(beta[i]) || beta[i] > 1e6 * std::max(res0[i], 1e-300)) {
+        status[i] = MG_ENUMERIC;
+        iact[i] = 0;
+      } else if (beta[i] <= tol[i]) {
+        conv[i] = 1;
+        iact[i] = 0;
+      } else if (iters[i] >= c.maxit) {
+        iact[i] = 0;
+      }
+    }
+  }
+  MG_HIP(hipStreamSynchronize(s));
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  int worst = MG_OK;
+  for (int i = 0; i < ni; ++i) {
+    if (status[i] == MG_OK && !conv[i]) status[i] = MG_ENOCONV;
+    if (status[i] == MG_ENUMERIC) worst = MG_ENUMERIC;
+    else if (status[i] == MG_ENOCONV && worst == MG_OK) worst = MG_ENOCONV;
+    if (st) {
+      st[i].iters = iters[i];
+      st[i].restarts = restarts[i];
+      st[i].status = status[i];
+      st[i].converged = conv[i];
+      st[i].res0 = res0[i];
+      st[i].res_final = resf[i];
+      st[i].t_solve_ms = ms;
+    }
+  }
+  if (worst == MG_ENUMERIC) return fail(MG_ENUMERIC, "non-finite or diverging residual in a batch instance");
+  if (worst == MG_ENOCONV) return fail(MG_ENOCONV, "maxit reached before rtol in a batch instance");
+  return MG_OK;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------- C ABI
 extern "C" {
 
@@ -652,165 +1360,25 @@ int mg_setup_hierarchy(const mg_level_in* lv, int32_t n_levels, const mg_config*
                        void* stream, mg_handle** out) {
   if (!lv || !cfg || !out || n_levels < 1) return fail(MG_EINVAL, "null argument or no levels");
   *out = nullptr;
-  const mg_config& c = *cfg;
-  if (!(c.omega > 0.0) || c.nu1 < 0 || c.nu2 < 0 || c.nu1 + c.nu2 < 1 || c.gmres_m < 1 || c.gmres_m > 64 ||
-      c.maxit < 0 || !(c.rtol >= 0.0) || c.precision < MG_PREC_FP64 || c.precision > MG_PREC_FP32_BF16VAL ||
-      (c.outer != MG_OUTER_IR && c.outer != MG_OUTER_FGMRES) ||
-      (c.coarse_mode != MG_COARSE_EXACT && c.coarse_mode != MG_COARSE_SMOOTH))
-    return fail(MG_EINVAL, "invalid configuration");
+  int rc = check_config(*cfg);
+  if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  std::vector<HostLevel> H(n_levels);
-  try {
-    for (int l = 0; l < n_levels; ++l) {
-      int rc = load_level(lv[l], inputs_on_device != 0, l > 0, H[l]);
-      if (rc) return rc;
-      rc = validate_host(H[l], l > 0 ? &H[l - 1] : nullptr, l);
-      if (rc) return rc;
-    }
-  } catch (const std::bad_alloc&) {
-    return fail(MG_ENOMEM, "host allocation failed");
-  }
-  const int B = H[0].B;
-  if (B > 4) return fail(MG_EUNSUPPORTED, "block sizes above 4 are not implemented");
-  if (int64_t(H[0].n) * B > 4096) return fail(MG_EUNSUPPORTED, "coarse problem above 4096 DoFs");
+  std::vector<HostLevel> H;
+  if ((rc = load_hierarchy(lv, n_levels, inputs_on_device != 0, H))) return rc;
   mg_handle* h = new (std::nothrow) mg_handle();
   if (!h) return fail(MG_ENOMEM, "host allocation failed");
-  h->cfg = c;
+  h->cfg = *cfg;
   h->L = n_levels - 1;
-  h->xk = c.precision == MG_PREC_FP64 ? X_F64 : X_F32;
+  h->xk = cfg->precision == MG_PREC_FP64 ? X_F64 : X_F32;
   h->lv.resize(n_levels);
-  auto bail = [&](int rc) {
+  try {
+    rc = setup_handle(h, H, s);
+  } catch (const std::bad_alloc&) {
+    rc = fail(MG_ENOMEM, "host allocation failed");
+  }
+  if (rc) {
     delete h;
     return rc;
-  };
-  int rc;
-  int* flag;
-  if ((rc = dalloc(h, &flag, 1))) return bail(rc);
-  h->dflag = flag;
-  MG_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
-  try {
-    for (int l = 0; l < n_levels; ++l) {
-      LevelDev& D = h->lv[l];
-      const HostLevel& L = H[l];
-      D.n = L.n;
-      D.B = L.B;
-      D.N = int64_t(L.n) * L.B;
-      D.nnzb = L.nnzb;
-      HostSell S = build_sell(L);
-      if ((rc = upload_sell(h, S, VK_F64, D.A64, s))) return bail(rc);
-      const int kind = c.precision == MG_PREC_FP64 ? VK_F64
-                       : c.precision == MG_PREC_FP32 ? VK_F32
-                       : c.precision == MG_PREC_FP32_F16VAL ? VK_F16 : VK_BF16;
-      if (kind == VK_F64) D.Ac = D.A64;
-      else if ((rc = upload_sell(h, S, kind, D.Ac, s))) return bail(rc);
-      const size_t sblk = size_t(S.nslices) * B * kWave;
-      if ((rc = dalloc(h, reinterpret_cast<char**>(&D.S), sblk * xsize(h->xk)))) return bail(rc);
-      MG_HIP(launch_fill(int64_t(sblk), D.S, h->xk, 0.0, s));
-      MG_HIP(launch_block_invert(D.A64, D.S, h->xk, flag, s));
-      if ((rc = upload(h, &D.mask, L.mask, s))) return bail(rc);
-      if (l > 0) {
-        CsrHost P;
-        P.nrows = L.n;
-        P.ncols = L.pc;
-        P.rowptr = L.prow;
-        P.col = L.pcol;
-        P.val = L.pval;
-        if ((rc = upload_csr(h, P, D.P, s))) return bail(rc);
-        CsrHost R = transpose(L.n, L.pc, L.prow, L.pcol, L.pval);
-        if ((rc = upload_csr(h, R, D.R, s))) return bail(rc);
-      }
-      const size_t vb = size_t(D.N) * xsize(h->xk);
-      char* p;
-      for (void** v : {&D.x, &D.b, &D.r, &D.t}) {
-        if ((rc = dalloc(h, &p, vb))) return bail(rc);
-        *v = p;
-      }
-      // mixed mode: the FP64 operator is only needed on the finest level
-      MG_HIP(hipStreamSynchronize(s));
-    }
-    // coarse inverse
-    {
-      const HostLevel& C0 = H[0];
-      const int n0 = C0.n * B;
-      h->n0 = n0;
-      std::vector<double> M(size_t(n0) * 2 * n0, 0.0);
-      for (int32_t i = 0; i < C0.n; ++i)
-        for (int32_t k = C0.rowptr[i]; k < C0.rowptr[i + 1]; ++k)
-          for (int c1 = 0; c1 < B; ++c1)
-            for (int c2 = 0; c2 < B; ++c2)
-              M[size_t(i * B + c1) * 2 * n0 + size_t(C0.col[k]) * B + c2] = C0.val[size_t(k) * B * B + c1 * B + c2];
-      for (int i = 0; i < n0; ++i) M[size_t(i) * 2 * n0 + n0 + i] = 1.0;
-      double *dM, *piv;
-      if ((rc = upload(h, &dM, M, s))) return bail(rc);
-      MG_HIP(hipStreamSynchronize(s));
-      if ((rc = dalloc(h, &piv, size_t(2) * n0))) return bail(rc);
-      if ((rc = dalloc(h, &h->Ainv, size_t(n0) * n0))) return bail(rc);
-      MG_HIP(launch_coarse_invert(n0, dM, h->Ainv, piv, flag, s));
-    }
-    int hflag = 0;
-    MG_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    MG_HIP(hipStreamSynchronize(s));
-    if (hflag) return bail(fail(MG_ESINGULAR, "singular nodal diagonal block or coarse matrix"));
-    // outer-loop storage
-    const int64_t N = h->lv[h->L].N;
-    const int m = c.gmres_m;
-    if ((rc = dalloc(h, &h->rout, size_t(N)))) return bail(rc);
-    char* p;
-    if ((rc = dalloc(h, &p, size_t(N) * xsize(h->xk)))) return bail(rc);
-    h->e = p;
-    if ((rc = dalloc(h, &p, size_t(N) * xsize(h->xk)))) return bail(rc);
-    h->bcyc = p;
-    if (c.outer == MG_OUTER_FGMRES) {
-      if ((rc = dalloc(h, &h->V, size_t(m + 1) * N))) return bail(rc);
-      if ((rc = dalloc(h, &p, size_t(m) * N * xsize(h->xk)))) return bail(rc);
-      h->Z = p;
-    }
-    if ((rc = dalloc(h, &h->H, size_t(m + 1) * m))) return bail(rc);
-    if ((rc = dalloc(h, &h->cs, size_t(m)))) return bail(rc);
-    if ((rc = dalloc(h, &h->sn, size_t(m)))) return bail(rc);
-    if ((rc = dalloc(h, &h->g, size_t(m) + 1))) return bail(rc);
-    if ((rc = dalloc(h, &h->y, size_t(m)))) return bail(rc);
-    if ((rc = dalloc(h, &h->dsc, 8))) return bail(rc);
-    MG_HIP(launch_fill(8, h->dsc, X_F64, 0.0, s));
-    MG_HIP(launch_fill(1, h->dsc + 1, X_F64, 1.0, s));
-    int64_t maxgrid = 1;
-    for (const LevelDev& D : h->lv) maxgrid = std::max<int64_t>(maxgrid, spmv_grid(D.A64));
-    if ((rc = dalloc(h, &h->pbig, size_t(maxgrid)))) return bail(rc);
-    for (int q = 0; q < 2; ++q)
-      if ((rc = dalloc(h, &h->pv[q], size_t(kMaxRedBlocks)))) return bail(rc);
-    // tail: every level up to the largest one with at most tail_dofs unknowns
-    {
-      // default off: on MI355X one workgroup walking several levels was measured slower
-      // (dependent-load latency serialises) than separate grid launches per step
-      int64_t tail_dofs = 0;
-      if (const char* e = std::getenv("MGQ1_TAIL_DOFS")) tail_dofs = std::atoll(e);
-      int top = 0;
-      for (int l = 1; l <= h->L; ++l)
-        if (h->lv[l].N <= tail_dofs) top = l;
-      h->tail_top = top;
-      std::vector<TailLevel> tl(top + 1);
-      for (int l = 0; l <= top; ++l) {
-        const LevelDev& D = h->lv[l];
-        tl[l].A = D.Ac;
-        tl[l].S = D.S;
-        tl[l].mask = D.mask;
-        tl[l].P = D.P;
-        tl[l].R = D.R;
-        tl[l].x = D.x;
-        tl[l].b = D.b;
-        tl[l].r = D.r;
-        tl[l].t = D.t;
-      }
-      if ((rc = dalloc(h, &h->dtail, tl.size()))) return bail(rc);
-      MG_HIP(hipMemcpyAsync(h->dtail, tl.data(), tl.size() * sizeof(TailLevel), hipMemcpyHostToDevice, s));
-      MG_HIP(hipStreamSynchronize(s));
-    }
-    MG_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hs), 16 * sizeof(double), hipHostMallocDefault));
-    h->step_graph.assign(size_t(m), nullptr);
-    if (c.use_graph) MG_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-    MG_HIP(hipStreamSynchronize(s));
-  } catch (const std::bad_alloc&) {
-    return bail(fail(MG_ENOMEM, "host allocation failed"));
   }
   *out = h;
   return MG_OK;
@@ -934,5 +1502,63 @@ const char* mg_status_string(int status) {
 }
 
 const char* mg_last_error(void) { return g_err.c_str(); }
+
+int mg_setup_batch(const mg_level_in* const* problems, const int32_t* n_levels, int32_t n_problems, int32_t nrhs,
+                   const mg_config* cfg, int32_t inputs_on_device, void* stream, mg_batch** out) {
+  if (!problems || !n_levels || !cfg || !out || n_problems < 1) return fail(MG_EINVAL, "null argument or no problems");
+  *out = nullptr;
+  if (nrhs != 1 && nrhs != 8) return fail(MG_EUNSUPPORTED, "batched solves support 1 or 8 right-hand sides");
+  int rc = check_config(*cfg);
+  if (rc) return rc;
+  if (cfg->outer != MG_OUTER_FGMRES) return fail(MG_EUNSUPPORTED, "batched solves use the FGMRES outer loop");
+  if (cfg->coarse_mode != MG_COARSE_EXACT) return fail(MG_EUNSUPPORTED, "batched solves use the exact coarse solve");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<std::vector<HostLevel>> HH(n_problems);
+  for (int p = 0; p < n_problems; ++p) {
+    if (n_levels[p] < 1 || !problems[p]) return fail(MG_EINVAL, "problem without levels");
+    if ((rc = load_hierarchy(problems[p], n_levels[p], inputs_on_device != 0, HH[p]))) return rc;
+    if (HH[p][0].B != HH[0][0].B) return fail(MG_EINVAL, "all problems of a batch need the same block size");
+  }
+  const int B = HH[0][0].B;
+  if (nrhs == 8 && B != 1) return fail(MG_EUNSUPPORTED, "8 right-hand sides are implemented for block size 1");
+  if (B == 2) return fail(MG_EUNSUPPORTED, "batched solves support block sizes 1, 3 and 4");
+  mg_batch* h = new (std::nothrow) mg_batch();
+  if (!h) return fail(MG_ENOMEM, "host allocation failed");
+  h->cfg = *cfg;
+  h->NR = nrhs;
+  h->P = n_problems;
+  h->B = B;
+  h->xk = cfg->precision == MG_PREC_FP64 ? X_F64 : X_F32;
+  h->vkind = value_kind(cfg->precision);
+  try {
+    rc = setup_batch(h, HH, s);
+  } catch (const std::bad_alloc&) {
+    rc = fail(MG_ENOMEM, "host allocation failed");
+  }
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return MG_OK;
+}
+
+int mg_batch_offsets(const mg_batch* h, int64_t* offsets) {
+  if (!h || !offsets) return fail(MG_EINVAL, "null argument");
+  for (size_t p = 0; p < h->off.size(); ++p) offsets[p] = h->off[p];
+  return MG_OK;
+}
+
+int mg_solve_batch(mg_batch* h, const double* b, double* x, mg_solve_stats* stats, void* stream) {
+  if (!h || !b || !x) return fail(MG_EINVAL, "null argument");
+  try {
+    return solve_batch_impl(h, b, x, stats, static_cast<hipStream_t>(stream));
+  } catch (const std::bad_alloc&) {
+    return fail(MG_ENOMEM, "host allocation failed");
+  }
+}
+
+void mg_destroy_batch(mg_batch* h) { delete h; }
+
 
 }  // extern "C"

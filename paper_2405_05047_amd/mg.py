@@ -47,7 +47,8 @@ class Stats(C.Structure):
 SYMBOLS = ["mg_setup_hierarchy", "mg_vcycle", "mg_solve", "mg_solve_fixed", "mg_level_defect",
            "mg_level_spmv", "mg_level_sweep", "mg_level_sweep0", "mg_level_restrict",
            "mg_level_prolong", "mg_coarse_solve", "mg_level_info", "mg_num_levels",
-           "mg_validate_level", "mg_destroy", "mg_status_string", "mg_last_error"]
+           "mg_validate_level", "mg_destroy", "mg_status_string", "mg_last_error",
+           "mg_setup_batch", "mg_batch_offsets", "mg_solve_batch", "mg_destroy_batch"]
 
 
 def lib():
@@ -76,8 +77,15 @@ def lib():
         L.mg_status_string.restype = C.c_char_p
         L.mg_last_error.argtypes = []
         L.mg_last_error.restype = C.c_char_p
+        L.mg_setup_batch.argtypes = [C.POINTER(C.POINTER(LevelIn)), C.POINTER(i32), i32, i32,
+                                     C.POINTER(Config), i32, vp, C.POINTER(vp)]
+        L.mg_batch_offsets.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.mg_solve_batch.argtypes = [vp, vp, vp, C.POINTER(Stats), vp]
+        L.mg_destroy_batch.argtypes = [vp]
+        L.mg_destroy_batch.restype = None
         for name in SYMBOLS:
-            if name not in ("mg_destroy", "mg_status_string", "mg_last_error", "mg_num_levels"):
+            if name not in ("mg_destroy", "mg_status_string", "mg_last_error", "mg_num_levels",
+                            "mg_destroy_batch"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -216,6 +224,54 @@ class Hierarchy:
 
     def coarse_solve(self, b, x, stream=None):
         _check(lib().mg_coarse_solve(self.h, _ptr(b), _ptr(x), _stream(stream)))
+
+
+class Batch:
+    """Many independent hierarchies (same block size) solved together with `nrhs`
+    right-hand sides each; batch vectors are the problems' (node, component, rhs)-ordered
+    vectors concatenated, problem p at offsets[p]:offsets[p + 1]."""
+
+    def __init__(self, problems, cfg: Config, nrhs=1, stream=None):
+        L = lib()
+        P = len(problems)
+        keep, ptrs = [], (C.POINTER(LevelIn) * P)()
+        nl = (C.c_int32 * P)()
+        for p, levels in enumerate(problems):
+            arr, k = level_structs(levels)
+            keep += [arr, k]
+            ptrs[p] = C.cast(arr, C.POINTER(LevelIn))
+            nl[p] = len(levels)
+        h = C.c_void_p()
+        self.cfg, self.nrhs, self.n_problems = cfg, nrhs, P
+        _check(L.mg_setup_batch(ptrs, nl, P, nrhs, C.byref(cfg), 0, _stream(stream), C.byref(h)))
+        self.h = h
+        off = (C.c_int64 * (P + 1))()
+        _check(L.mg_batch_offsets(h, off))
+        self.offsets = np.array(off[:], dtype=np.int64)
+
+    @property
+    def size(self):
+        return int(self.offsets[-1])
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mg_destroy_batch(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, b, x, stream=None):
+        """Returns (status, list of per-instance stats dicts, instance p * nrhs + q)."""
+        n = self.n_problems * self.nrhs
+        st = (Stats * n)()
+        rc = lib().mg_solve_batch(self.h, _ptr(b), _ptr(x), st, _stream(stream))
+        if rc not in (0, -5):
+            _check(rc)
+        return rc, [st[i].as_dict() for i in range(n)]
 
 
 def validate_level(level, coarser=None) -> int:

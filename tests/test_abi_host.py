@@ -78,3 +78,25 @@ def test_malformed_rejected(levels, breakage):
         lv.p_cols = co.n + 1
     assert mg.validate_level(lv, co) == -1
     assert mg.last_error()
+
+
+@pytest.mark.parametrize("bad", ["nrhs3", "outer_ir", "coarse_smooth", "nrhs8_block3", "block_mismatch"])
+def test_batch_setup_rejects_unsupported_requests(levels, bad):
+    """mg_setup_batch refuses requests it does not implement before touching a device."""
+    import ctypes as C
+    wl = W.c2_td(band_rounds=2, uniform_rounds=1)
+    cfg = mg.config_from(wl)
+    problems, nrhs, want = [levels, levels], 1, -7
+    if bad == "nrhs3":
+        nrhs = 3
+    elif bad == "outer_ir":
+        cfg.outer = 0
+    elif bad == "coarse_smooth":
+        cfg.coarse_mode = 1
+    elif bad == "nrhs8_block3":
+        problems, nrhs = [gen.build(W.c3_elasticity(1)).levels], 8
+    else:
+        problems, want = [levels, gen.build(W.c3_elasticity(1)).levels], -1
+    with pytest.raises(mg.MGError) as e:
+        mg.Batch(problems, cfg, nrhs=nrhs, stream=C.c_void_p(0))
+    assert e.value.code == want
