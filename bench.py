@@ -7,8 +7,10 @@ inputs are resident in HBM before the timed region.  The default workload is the
 adaptive 2D transport-diffusion problem (~1.0e6 DoFs, 9 levels).
 
 Printed: one JSON line with the FP64 solve throughput as `value`, the mixed-precision
-variants, the roofline of the dominant kernel (finest-level smoothing sweep) and the
-oracle timed on the host.
+variants, the roofline of the dominant kernel (finest-level smoothing sweep), the oracle
+timed on the host and the batched form (64 uneven transport-diffusion problems x 8
+right-hand sides solved together, against the same 512 solves done one at a time).
+Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -90,6 +92,96 @@ def kernel_time(torch, h, level, n_dof, launches=50):
     return e0.elapsed_time(e1) / launches * 1e-3
 
 
+def _progress(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def batched(torch, gen, mg, n_problems, nrhs, steps, precisions=("fp64", "fp32", "fp16")):
+    """The batched form: `n_problems` seeded transport-diffusion problems of uneven size
+    (4-9 levels), `nrhs` seeded right-hand sides each, all solved in one lockstep FGMRES
+    whose V-cycle steps are single launches over the whole batch; compared with the same
+    solves done one problem and one right-hand side at a time (FP64 single-problem path)."""
+    import scipy.sparse as sp
+    wls = W.batch_problems(n_problems=n_problems)
+    t = time.perf_counter()
+    probs = []
+    for k, wl in enumerate(wls):
+        probs.append(gen.build(wl, nrhs))
+        if k % 16 == 15:
+            _progress(f"batch: generated {k + 1}/{len(wls)} problems")
+    t_gen = time.perf_counter() - t
+    sizes = [p.finest.n for p in probs]
+    n_inst = n_problems * nrhs
+    dofs = sum(sizes) * nrhs
+    b = np.concatenate([np.asarray(p.b, np.float64).reshape(-1) for p in probs])
+    bd = torch.from_numpy(b).cuda()
+    x = torch.zeros_like(bd)
+    res = {}
+    for prec in precisions:
+        t = time.perf_counter()
+        bt = mg.Batch([p.levels for p in probs], mg.config_from(wls[0], precision=prec), nrhs=nrhs)
+        t_setup = time.perf_counter() - t
+        x.zero_()
+        bt.solve(bd, x)                     # warm-up (captures the step graphs)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            x.zero_()
+            rc, st = bt.solve(bd, x)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / steps
+        xs = x.cpu().numpy()
+        worst = 0.0
+        for p, pr in enumerate(probs):
+            top = pr.finest
+            A = sp.bsr_matrix((top.val, top.col, top.rowptr), shape=(top.n, top.n)).tocsr()
+            seg = slice(int(bt.offsets[p]), int(bt.offsets[p + 1]))
+            X, B = xs[seg].reshape(top.n, nrhs), b[seg].reshape(top.n, nrhs)
+            r = np.linalg.norm(B - A @ X, axis=0) / np.linalg.norm(B, axis=0)
+            worst = max(worst, float(r.max()))
+        its = [s["iters"] for s in st]
+        res[prec + "_batch"] = {"dof_per_s": dofs / sec, "ms_per_solve": sec * 1e3, "status": rc,
+                                "converged": int(sum(s["converged"] for s in st)), "instances": n_inst,
+                                "cycles_min": min(its), "cycles_max": max(its),
+                                "max_rel_residual": worst, "setup_s": round(t_setup, 2)}
+        _progress(f"batch {prec}: {sec * 1e3:.1f} ms for {n_inst} solves")
+        del bt
+    # the same solves one at a time with the single-problem FP64 path
+    hs = [mg.Hierarchy(p.levels, mg.config_from(wl)) for p, wl in zip(probs, wls)]
+    cols = []
+    for p in probs:
+        B = np.asarray(p.b, np.float64).reshape(p.finest.n, nrhs)
+        cols.append([torch.from_numpy(np.ascontiguousarray(B[:, q])).cuda() for q in range(nrhs)])
+    xq = torch.zeros(max(sizes), dtype=torch.float64, device="cuda")
+    for h, c, n in zip(hs, cols, sizes):     # warm-up (graphs)
+        xv = xq[:n]
+        xv.zero_()
+        h.solve(c[0], xv)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    iters = []
+    for h, c, n in zip(hs, cols, sizes):
+        xv = xq[:n]
+        for q in range(nrhs):
+            xv.zero_()
+            iters.append(h.solve(c[q], xv)["iters"])
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t
+    res["fp64_sequential"] = {"dof_per_s": dofs / sec, "ms_per_solve": sec * 1e3, "instances": n_inst,
+                              "cycles_min": min(iters), "cycles_max": max(iters)}
+    _progress(f"sequential fp64: {sec * 1e3:.1f} ms for {n_inst} solves")
+    base = res["fp64_sequential"]["dof_per_s"]
+    for k, v in res.items():
+        v["speedup_vs_fp64_sequential"] = v["dof_per_s"] / base
+    return {"workload": f"{n_problems} seeded 2D transport-diffusion problems (eps log-uniform in "
+                        f"[1e-4,1e-1], random unit b, 4-9 levels, annulus-refined), {nrhs} seeded "
+                        f"right-hand sides each, FGMRES(10) + V(2,2) w=0.6 to rtol 1e-8 per instance",
+            "problems": n_problems, "nrhs": nrhs, "nodes_total": int(sum(sizes)), "dofs_total": int(dofs),
+            "nodes_min": int(min(sizes)), "nodes_max": int(max(sizes)), "generator_s": round(t_gen, 1),
+            "results": {k: {kk: (float(f"{vv:.6g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                        for k, v in res.items()}}
+
+
 def cpu_baseline(wl, budget_s=30.0):
     """The oracle (NumPy/SciPy, FP64) timed on the host on the same workload."""
     from threadpoolctl import threadpool_limits
@@ -122,6 +214,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--precisions", default="fp64,fp32,fp16,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-problems", type=int, default=64,
+                    help="problems of the batched section (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -157,6 +252,7 @@ def main():
                          "converged": all(s["converged"] for s in stats), "rel_residual": rel,
                          "setup_s": round(t_setup, 3)}
         handles[prec] = h
+        _progress(f"{wl.name} {prec}: {sec * 1e3:.2f} ms per solve, {stats[-1]['iters']} cycles")
     base = results["fp64"]
     for prec, r in results.items():
         r["speedup_vs_fp64"] = r["dof_per_s"] / base["dof_per_s"]
@@ -190,7 +286,12 @@ def main():
            "roofline": roof,
            "variants": {k: {kk: (float(f"{vv:.6g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
                         for k, v in results.items()}}
+    del handles, h64, h
+    if args.batch_problems > 0:
+        _progress("batched section")
+        out["batched"] = batched(torch, gen, mg, args.batch_problems, 8, args.batch_steps)
     if not args.no_cpu_baseline:
+        _progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
 

@@ -169,6 +169,7 @@ struct BSegs {
   const int* vfirst = nullptr;
   const int* vcount = nullptr;
   const int* blk_prob = nullptr;   // vector block -> problem
+  const int* on = nullptr;         // per-problem flags (NULL: all problems take part)
   int n_blocks = 0;
   int NR = 1;
 };

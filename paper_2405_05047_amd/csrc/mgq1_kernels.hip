@@ -1088,6 +1088,7 @@ __global__ __launch_bounds__(kThreads) void k_bcoarse(const BEntry* __restrict__
 struct SegPos {
   int p, lb, nb, first;
   int64_t off, len;
+  bool on;                                 // the problem takes part in this launch
 };
 
 __device__ __forceinline__ SegPos seg_pos(const BSegs& g) {
@@ -1098,6 +1099,7 @@ __device__ __forceinline__ SegPos seg_pos(const BSegs& g) {
   s.nb = g.vcount[s.p];
   s.off = g.off[s.p];
   s.len = g.len[s.p];
+  s.on = !g.on || g.on[s.p];
   return s;
 }
 
@@ -1128,6 +1130,7 @@ __global__ __launch_bounds__(kThreads) void k_bdot(BSegs g, const double* __rest
                                                    const double* __restrict__ b, double* __restrict__ out) {
   __shared__ double lds[kThreads];
   const SegPos sp = seg_pos(g);
+  if (!sp.on) return;                      // uniform over the block
   double t = 0.0;
   const int64_t stride = int64_t(sp.nb) * blockDim.x;
   for (int64_t i = int64_t(sp.lb) * blockDim.x + threadIdx.x; i < sp.len; i += stride) {
@@ -1145,6 +1148,7 @@ __global__ __launch_bounds__(kThreads) void k_bmgs_step(BSegs g, double* __restr
   __shared__ double lds[kThreads];
   __shared__ double hq[64];
   const SegPos sp = seg_pos(g);
+  if (!sp.on) return;                      // uniform over the block
   seg_sums(pin, sp, g.NR, lds, hq);
   if (sp.lb == 0 && int(threadIdx.x) < g.NR) H[int64_t(sp.p * g.NR + threadIdx.x) * hstride] = hq[threadIdx.x];
   const double h = hq[threadIdx.x % g.NR];
@@ -1166,6 +1170,7 @@ __global__ __launch_bounds__(kThreads) void k_bmgs_normalize(BSegs g, double* __
   __shared__ double lds[kThreads];
   __shared__ double hq[64];
   const SegPos sp = seg_pos(g);
+  if (!sp.on) return;                      // uniform over the block
   seg_sums(pin, sp, g.NR, lds, hq);
   if (int(threadIdx.x) < g.NR) hq[threadIdx.x] = sqrt(hq[threadIdx.x]);
   __syncthreads();
@@ -1179,6 +1184,7 @@ __global__ __launch_bounds__(kThreads) void k_bmgs_normalize(BSegs g, double* __
 __global__ __launch_bounds__(kThreads) void k_bscale(BSegs g, double* __restrict__ y, const double* __restrict__ x,
                                                      const double* __restrict__ beta, const int* __restrict__ iact) {
   const SegPos sp = seg_pos(g);
+  if (!sp.on) return;                      // uniform over the block
   const int inst = sp.p * g.NR + threadIdx.x % g.NR;
   const double bt = beta[inst];
   const bool on = iact[inst] && bt != 0.0;
@@ -1192,6 +1198,7 @@ __global__ __launch_bounds__(kThreads) void k_bupdate(BSegs g, double* __restric
                                                       int64_t ldz, const double* __restrict__ yv, int m,
                                                       const int* __restrict__ kk) {
   const SegPos sp = seg_pos(g);
+  if (!sp.on) return;                      // uniform over the block
   const int inst = sp.p * g.NR + threadIdx.x % g.NR;
   const int k = kk[inst];
   if (k == 0) return;
@@ -1218,7 +1225,8 @@ __global__ __launch_bounds__(kThreads) void k_bfinish(const double* __restrict__
 __global__ void k_bgivens(int j, int m, int n_inst, double* H, double* cs, double* sn, double* g, double* st,
                           const double* __restrict__ tol, int* kk, const int* __restrict__ iact) {
   const int inst = blockIdx.x * blockDim.x + threadIdx.x;
-  if (inst >= n_inst || !iact[inst]) return;
+  // rotations after the instance's cycle has closed are never used
+  if (inst >= n_inst || !iact[inst] || kk[inst] != 0) return;
   const int ld = m + 1;
   double* h = H + int64_t(inst) * ld * m + int64_t(j) * ld;
   double* c = cs + int64_t(inst) * m;

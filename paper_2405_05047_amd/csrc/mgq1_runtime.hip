@@ -847,10 +847,12 @@ struct mg_batch : DevOwner {
   void* Z = nullptr;
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *yv = nullptr, *st = nullptr;
   double *beta = nullptr, *bnorm = nullptr, *tolv = nullptr;
-  int *kk = nullptr, *iact = nullptr, *pact = nullptr;
+  int *kk = nullptr, *iact = nullptr;
+  int* pact = nullptr;                // problem has an unconverged instance
+  int* pstep = nullptr;               // problem has an instance whose Krylov cycle is still open
   double* pvec[2] = {nullptr, nullptr};
   double* pbig = nullptr;
-  BSegs segs;
+  BSegs segs, segs_act, segs_step;   // vector segments: all problems / pact / pstep
   int *bigfirst = nullptr, *bigcount = nullptr;
   std::vector<BEntry> hE;             // entry tables of every planned launch
   BEntry* dE = nullptr;
@@ -1051,18 +1053,19 @@ int enqueue_batch_step(mg_batch* h, int j, hipStream_t s) {
   int rc;
   if (h->xk != X_F64) MG_HIP(launch_convert(N, h->V + int64_t(j) * N, X_F64, h->btop, h->xk, s));
   for (const BLaunch& L : h->plan[j])
-    if ((rc = run_launch(h, L, h->dE, h->pact, nullptr, s))) return rc;
-  if ((rc = run_launch(h, h->spmv64[j], h->dE, h->pact, nullptr, s))) return rc;
+    if ((rc = run_launch(h, L, h->dE, h->pstep, nullptr, s))) return rc;
+  if ((rc = run_launch(h, h->spmv64[j], h->dE, h->pstep, nullptr, s))) return rc;
   double* w = h->V + int64_t(j + 1) * N;
   const int64_t hs = int64_t(m + 1) * m;
   double* Hj = h->H + int64_t(j) * (m + 1);
-  MG_HIP(launch_bdot(h->segs, w, h->V, h->pvec[0], s));
+  const BSegs& sg = h->segs_step;
+  MG_HIP(launch_bdot(sg, w, h->V, h->pvec[0], s));
   for (int i = 0; i <= j; ++i) {
     const double* vi = h->V + int64_t(i) * N;
     const double* vn = (i < j) ? h->V + int64_t(i + 1) * N : nullptr;
-    MG_HIP(launch_bmgs_step(h->segs, w, vi, vn, h->pvec[i & 1], h->pvec[(i + 1) & 1], Hj + i, hs, s));
+    MG_HIP(launch_bmgs_step(sg, w, vi, vn, h->pvec[i & 1], h->pvec[(i + 1) & 1], Hj + i, hs, s));
   }
-  MG_HIP(launch_bmgs_normalize(h->segs, w, h->pvec[(j + 1) & 1], Hj + j + 1, hs, s));
+  MG_HIP(launch_bmgs_normalize(sg, w, h->pvec[(j + 1) & 1], Hj + j + 1, hs, s));
   MG_HIP(launch_bgivens(j, m, h->n_inst, h->H, h->cs, h->sn, h->g, h->st, h->tolv, h->kk, h->iact, s));
   return MG_OK;
 }
@@ -1148,6 +1151,7 @@ int setup_batch(mg_batch* h, const std::vector<std::vector<HostLevel>>& HH, hipS
   if ((rc = dalloc(h, &h->kk, size_t(ni)))) return rc;
   if ((rc = dalloc(h, &h->iact, size_t(ni)))) return rc;
   if ((rc = dalloc(h, &h->pact, size_t(P)))) return rc;
+  if ((rc = dalloc(h, &h->pstep, size_t(P)))) return rc;
   // vector segments: up to kSegBlocksMax blocks per problem
   std::vector<int64_t> len(P);
   std::vector<int> vfirst(P), vcount(P), blk;
@@ -1172,6 +1176,10 @@ int setup_batch(mg_batch* h, const std::vector<std::vector<HostLevel>>& HH, hipS
   h->segs.blk_prob = dblk;
   h->segs.n_blocks = int(blk.size());
   h->segs.NR = NR;
+  h->segs_act = h->segs;
+  h->segs_act.on = h->pact;
+  h->segs_step = h->segs;
+  h->segs_step.on = h->pstep;
   for (int q = 0; q < 2; ++q)
     if ((rc = dalloc(h, &h->pvec[q], blk.size() * NR))) return rc;
   // outer FP64 products: blocks per problem
@@ -1274,7 +1282,9 @@ int solve_batch_impl(mg_batch* h, const double* b, double* x, mg_solve_stats* st
     if (!any) break;
     if ((rc = to_dev(h->iact, iact.data(), ni, s))) return rc;
     if ((rc = to_dev(h->pact, pact.data(), P, s))) return rc;
-    MG_HIP(launch_bscale(h->segs, h->V, h->rout, h->beta, h->iact, s));
+    std::vector<int> pstep(pact);
+    if ((rc = to_dev(h->pstep, pstep.data(), P, s))) return rc;
+    MG_HIP(launch_bscale(h->segs_act, h->V, h->rout, h->beta, h->iact, s));
     MG_HIP(launch_binit(m, ni, h->g, h->beta, h->kk, s));
     int jl = 0;
     for (int j = 0; j < m; ++j) {
@@ -1282,22 +1292,28 @@ int solve_batch_impl(mg_batch* h, const double* b, double* x, mg_solve_stats* st
       jl = j;
       if ((rc = to_host(h->hkk, h->kk, ni, s))) return rc;
       // an instance whose V-cycle budget ends here closes its cycle like the single solve
-      bool open = false, dirty = false;
-      for (int i = 0; i < ni; ++i) {
-        if (!iact[i] || h->hkk[i] != 0) continue;
-        if (iters[i] + j + 1 >= c.maxit) {
+      bool dirty = false;
+      for (int i = 0; i < ni; ++i)
+        if (iact[i] && h->hkk[i] == 0 && iters[i] + j + 1 >= c.maxit) {
           h->hkk[i] = j + 1;
           dirty = true;
-        } else {
-          open = true;
         }
-      }
       if (dirty && (rc = to_dev(h->kk, h->hkk, ni, s))) return rc;
+      // problems whose instances have all closed their cycles wait for the restart
+      bool open = false, changed = false;
+      for (int p = 0; p < P; ++p) {
+        int o = 0;
+        for (int q = 0; q < NR; ++q) o |= iact[p * NR + q] && h->hkk[p * NR + q] == 0;
+        changed = changed || (o != pstep[p]);
+        pstep[p] = o;
+        open = open || o;
+      }
       if (!open) break;
+      if (changed && (rc = to_dev(h->pstep, pstep.data(), P, s))) return rc;
     }
     MG_HIP(launch_bclose(jl, ni, h->kk, h->iact, s));
     MG_HIP(launch_bbacksolve(m, ni, h->H, h->g, h->yv, h->kk, s));
-    MG_HIP(launch_bupdate(h->segs, x, h->Z, h->xk, N, h->yv, m, h->kk, s));
+    MG_HIP(launch_bupdate(h->segs_act, x, h->Z, h->xk, N, h->yv, m, h->kk, s));
     if ((rc = to_host(kk.data(), h->kk, ni, s))) return rc;
     if ((rc = batch_defect(h, s))) return rc;
     if ((rc = to_host(beta.data(), h->beta, ni, s))) return rc;

@@ -187,7 +187,11 @@ def batch_problems(n_problems: int = 64, base_seed: int = 1000, max_levels: int 
     Problem k uses numpy.random.default_rng(base_seed + k): eps = 10^U[-4,-1],
     b = (cos t, sin t) with t ~ U[0, 2pi), L ~ U{min..max} levels, u ~ U{1..L-1}
     uniform rounds, the remaining L-1-u rounds refine an annulus with centre
-    ~ U[0.3,0.7]^2, radius ~ U[0.15,0.35] and half-width ~ U[0.02,0.1]."""
+    ~ U[0.3,0.7]^2, radius ~ U[0.15,0.35] and half-width ~ U[0.02,0.1].
+
+    Jacobi damping 0.6: with 0.8 the V-cycle of the most convection-dominated members
+    (Peclet numbers in the hundreds on the coarse levels) amplifies some error modes and
+    FGMRES(10) stalls on 6 of the 64 default problems; 0.6 converges on all of them."""
     out = []
     for k in range(n_problems):
         rng = np.random.default_rng(base_seed + k)
@@ -202,7 +206,7 @@ def batch_problems(n_problems: int = 64, base_seed: int = 1000, max_levels: int 
         out.append(Workload(name=f"batch{k}", dim=2, coarse=(8, 8), h0=0.125, rounds=rounds,
                             pde=PDE_TD, block=1, eps=float(eps),
                             bvec=(math.cos(t), math.sin(t)), dir_faces=ALL_FACES_2D,
-                            dir_comps=1, rhs=RHS_NOISE, seed=base_seed + k, omega=0.8,
+                            dir_comps=1, rhs=RHS_NOISE, seed=base_seed + k, omega=0.6,
                             outer=OUTER_FGMRES, gmres_m=10, rtol=1e-8))
     return out
 
