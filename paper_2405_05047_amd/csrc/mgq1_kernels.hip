@@ -45,74 +45,108 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   return x * q + (x < r ? x : r) + k;
 }
 
+// stored matrix values: load() fetches the raw stored word (nontemporal: A is streamed
+// once per sweep), dec() widens it to FP32/FP64.  FP16/BF16 values are a_ij / s_i with the
+// power-of-two row scale s_i applied once to the finished row sum (exact: scaling by 2^e
+// commutes with rounding away from overflow and underflow).
 template <int K> struct Val;
 template <> struct Val<VK_F64> {
-  __device__ __forceinline__ static double get(const void* p, int64_t i, float) {
+  using raw = double;
+  __device__ __forceinline__ static raw load(const void* p, int64_t i) {
     return __builtin_nontemporal_load(static_cast<const double*>(p) + i);
   }
+  __device__ __forceinline__ static double dec(raw u) { return u; }
 };
 template <> struct Val<VK_F32> {
-  __device__ __forceinline__ static float get(const void* p, int64_t i, float) {
+  using raw = float;
+  __device__ __forceinline__ static raw load(const void* p, int64_t i) {
     return __builtin_nontemporal_load(static_cast<const float*>(p) + i);
   }
+  __device__ __forceinline__ static float dec(raw u) { return u; }
 };
 template <> struct Val<VK_F16> {
-  __device__ __forceinline__ static float get(const void* p, int64_t i, float sc) {
-    const unsigned short u = __builtin_nontemporal_load(static_cast<const unsigned short*>(p) + i);
-    return sc * __half2float(__ushort_as_half(u));
+  using raw = unsigned short;
+  __device__ __forceinline__ static raw load(const void* p, int64_t i) {
+    return __builtin_nontemporal_load(static_cast<const unsigned short*>(p) + i);
   }
+  __device__ __forceinline__ static float dec(raw u) { return __half2float(__ushort_as_half(u)); }
 };
 template <> struct Val<VK_BF16> {
-  __device__ __forceinline__ static float get(const void* p, int64_t i, float sc) {
-    const unsigned short u = __builtin_nontemporal_load(static_cast<const unsigned short*>(p) + i);
-    return sc * __uint_as_float(static_cast<uint32_t>(u) << 16);
+  using raw = unsigned short;
+  __device__ __forceinline__ static raw load(const void* p, int64_t i) {
+    return __builtin_nontemporal_load(static_cast<const unsigned short*>(p) + i);
   }
+  __device__ __forceinline__ static float dec(raw u) { return __uint_as_float(static_cast<uint32_t>(u) << 16); }
 };
+
+// NB block slots k .. k+NB-1 of a slice: the column indices first, then every value and
+// x load of the batch, then the FMAs, so the batch costs two memory round trips.  NB is a
+// compile-time constant, so no load sits in a conditional block (a conditional load whose
+// result is widened inside the block would force a wait per slot).
+template <int NB, int B, int NR, int K, class XI, class T>
+__device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int rl, int q,
+                                           const XI* __restrict__ x, T& acc) {
+  constexpr int R = kWave / (B * NR);
+  constexpr int W = kWave / NR;
+  using VR = typename Val<K>::raw;
+  // phase 1: column indices and values (independent of each other); phase 2: the x
+  // gathers; phase 3: the FMAs.  Scheduling barriers keep the phases apart, otherwise the
+  // scheduler interleaves the FMA chain with the loads and adds round trips.
+  unsigned js[NB];                         // unsigned: widening needs no sign extension
+  VR av[NB][B];
+  XI xv[NB][B];
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq)
+    js[qq] = unsigned(__builtin_nontemporal_load(A.col + int64_t(k + qq) * R + r));
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) {
+    const int64_t vb = int64_t(k + qq) * B * W + rl;
+#pragma unroll
+    for (int cc = 0; cc < B; ++cc) av[qq][cc] = Val<K>::load(A.val, vb + cc * W);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) {
+    const XI* xj = x + uint64_t(js[qq]) * (B * NR) + q;
+#pragma unroll
+    for (int cc = 0; cc < B; ++cc) xv[qq][cc] = xj[cc * NR];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq)
+#pragma unroll
+    for (int cc = 0; cc < B; ++cc) acc += T(Val<K>::dec(av[qq][cc])) * T(xv[qq][cc]);
+}
 
 // per-lane row dot product of a slice: sum_k sum_cc a(k, cc) x[(col_k * B + cc) * NR + q].
 // NR right-hand sides share every matrix entry: lane = (r * B + c) * NR + q, the slice
 // holds R = 64 / (B * NR) nodes, and the values of row lane rl = lane / NR sit at
 // val[(k * B + cc) * W + rl] with the padded row-lane stride W = 64 / NR (R * B rounded up,
-// 64 for one right-hand side).  NR = 1 is the single right-hand-side layout.
+// 64 for one right-hand side).  NR = 1 is the single right-hand-side layout.  Slots are
+// consumed in batches of KB, the remainder in one shorter batch (slice-uniform branch).
 template <int B, int NR, int K, class XI, class T>
 __device__ __forceinline__ T sell_dot(const SellDev& A, int slice, int lane, bool valid,
                                       const XI* __restrict__ x) {
-  constexpr int R = kWave / (B * NR);
   constexpr int W = kWave / NR;
   constexpr int KB = B <= 2 ? 8 : 4;       // block slots per batch
   T acc = T(0);
   if (!valid) return acc;
   const int rl = lane / NR, q = lane % NR;
-  float sc = 1.0f;
-  if (K == VK_F16 || K == VK_BF16) sc = ldexpf(1.0f, A.rexp[int64_t(slice) * W + rl]);
   const int r = rl / B;
-  const int k0 = A.sptr[slice], k1 = A.sptr[slice + 1];
-  for (int k = k0; k < k1; k += KB) {
-    int js[KB];
-#pragma unroll
-    for (int qq = 0; qq < KB; ++qq)
-      js[qq] = (k + qq < k1) ? __builtin_nontemporal_load(A.col + int64_t(k + qq) * R + r) : -1;
-    T av[KB][B], xv[KB][B];
-#pragma unroll
-    for (int qq = 0; qq < KB; ++qq) {
-      if (js[qq] >= 0) {                     // uniform across the wave (slice-wide k range)
-        const XI* xj = x + int64_t(js[qq]) * B * NR + q;
-        const int64_t vb = int64_t(k + qq) * B * W + rl;
-#pragma unroll
-        for (int cc = 0; cc < B; ++cc) {
-          av[qq][cc] = T(Val<K>::get(A.val, vb + cc * W, sc));
-          xv[qq][cc] = T(xj[cc * NR]);
-        }
-      } else {
-#pragma unroll
-        for (int cc = 0; cc < B; ++cc) { av[qq][cc] = T(0); xv[qq][cc] = T(0); }
-      }
-    }
-#pragma unroll
-    for (int qq = 0; qq < KB; ++qq)
-#pragma unroll
-      for (int cc = 0; cc < B; ++cc) acc += av[qq][cc] * xv[qq][cc];
+  const int k1 = A.sptr[slice + 1];
+  int k = A.sptr[slice];
+  for (; k + KB <= k1; k += KB) sell_batch<KB, B, NR, K>(A, k, r, rl, q, x, acc);
+  switch (k1 - k) {
+    case 1: sell_batch<1, B, NR, K>(A, k, r, rl, q, x, acc); break;
+    case 2: sell_batch<2, B, NR, K>(A, k, r, rl, q, x, acc); break;
+    case 3: sell_batch<3, B, NR, K>(A, k, r, rl, q, x, acc); break;
+    case 4: if (KB > 4) sell_batch<(KB > 4 ? 4 : 1), B, NR, K>(A, k, r, rl, q, x, acc); break;
+    case 5: if (KB > 5) sell_batch<(KB > 5 ? 5 : 1), B, NR, K>(A, k, r, rl, q, x, acc); break;
+    case 6: if (KB > 6) sell_batch<(KB > 6 ? 6 : 1), B, NR, K>(A, k, r, rl, q, x, acc); break;
+    case 7: if (KB > 7) sell_batch<(KB > 7 ? 7 : 1), B, NR, K>(A, k, r, rl, q, x, acc); break;
+    default: break;
   }
+  if (K == VK_F16 || K == VK_BF16) acc *= T(ldexpf(1.0f, A.rexp[int64_t(slice) * W + rl]));
   return acc;
 }
 
