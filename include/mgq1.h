@@ -80,6 +80,10 @@ typedef struct {
   int32_t use_graph;          /* 1: mg_solve replays one captured HIP graph per Krylov step
                                  (V-cycle, SpMV, Gram-Schmidt, Givens) instead of launching
                                  every kernel; 0: plain launches.  Results are identical. */
+  int32_t slot_batch;         /* block slots whose loads the slice kernels issue together:
+                                 0 = autotune (setup times both built sizes on every level's
+                                 sweep and keeps the faster), or a fixed size: 8 or 16 for
+                                 block sizes 1-2, 4 or 8 for 3-4.  Results are identical. */
 } mg_config;
 
 typedef struct {
@@ -138,6 +142,11 @@ int mg_coarse_solve(mg_handle* h, const double* b, double* x, void* stream);
 int mg_level_info(const mg_handle* h, int32_t level, int32_t* n_nodes, int32_t* block,
                   int64_t* nnzb);
 int32_t mg_num_levels(const mg_handle* h);
+
+/* Slot batch used on level `level` and the sweep times (microseconds per launch) that the
+ * setup measured for the default and the other size (0 when slot_batch was fixed). */
+int mg_level_tuning(const mg_handle* h, int32_t level, int32_t* slot_batch, double* us_default,
+                    double* us_other);
 
 /* Host-only structural validation of one level (and its coarser neighbour for P~);
  * no device is touched.  Returns MG_OK or MG_EINVAL with a message. */

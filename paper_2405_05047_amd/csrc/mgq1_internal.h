@@ -30,7 +30,11 @@ struct SellDev {
   const void* val = nullptr;        // slots * B * 64 values of `kind`
   const int8_t* rexp = nullptr;     // nslices * 64 power-of-two row exponents (F16 / BF16)
   int kind = VK_F64;
+  int kb = 0;                       // block slots per load batch (0: the default for B)
 };
+
+// the two slot-batch sizes the slice kernels are built for (default, alternative)
+void slot_batch_choices(int B, int* kb_def, int* kb_other);
 
 // scalar CSR (transfer matrices); weights stored as float when every weight is exact in
 // FP32 (dyadic), else as double

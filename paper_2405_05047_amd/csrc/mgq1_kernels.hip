@@ -124,11 +124,30 @@ __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int r
 // val[(k * B + cc) * W + rl] with the padded row-lane stride W = 64 / NR (R * B rounded up,
 // 64 for one right-hand side).  NR = 1 is the single right-hand-side layout.  Slots are
 // consumed in batches of KB, the remainder in one shorter batch (slice-uniform branch).
-template <int B, int NR, int K, class XI, class T>
+// the remaining rem < KB slots of a slice as one batch of exactly rem slots
+template <int N, int B, int NR, int K, class XI, class T>
+__device__ __forceinline__ void sell_rest(int rem, const SellDev& A, int k, int r, int rl, int q,
+                                          const XI* __restrict__ x, T& acc) {
+  if constexpr (N >= 1) {
+    if (rem == N) sell_batch<N, B, NR, K>(A, k, r, rl, q, x, acc);
+    else sell_rest<N - 1, B, NR, K>(rem, A, k, r, rl, q, x, acc);
+  }
+}
+
+template <int B> constexpr int kb_default() { return B <= 2 ? 8 : 4; }
+template <int B> constexpr int kb_alt() { return B <= 2 ? 16 : 8; }
+
+// per-lane row dot product of a slice: sum_k sum_cc a(k, cc) x[(col_k * B + cc) * NR + q].
+// NR right-hand sides share every matrix entry: lane = (r * B + c) * NR + q, the slice
+// holds R = 64 / (B * NR) nodes, and the values of row lane rl = lane / NR sit at
+// val[(k * B + cc) * W + rl] with the padded row-lane stride W = 64 / NR (R * B rounded up,
+// 64 for one right-hand side).  NR = 1 is the single right-hand-side layout.  Slots are
+// consumed in batches of KB, the remainder in one shorter batch (slice-uniform branch);
+// the FMAs run in slot order whatever KB is, so every KB gives the same bits.
+template <int B, int NR, int K, class XI, class T, int KB = kb_default<B>()>
 __device__ __forceinline__ T sell_dot(const SellDev& A, int slice, int lane, bool valid,
                                       const XI* __restrict__ x) {
   constexpr int W = kWave / NR;
-  constexpr int KB = B <= 2 ? 8 : 4;       // block slots per batch
   T acc = T(0);
   if (!valid) return acc;
   const int rl = lane / NR, q = lane % NR;
@@ -136,16 +155,7 @@ __device__ __forceinline__ T sell_dot(const SellDev& A, int slice, int lane, boo
   const int k1 = A.sptr[slice + 1];
   int k = A.sptr[slice];
   for (; k + KB <= k1; k += KB) sell_batch<KB, B, NR, K>(A, k, r, rl, q, x, acc);
-  switch (k1 - k) {
-    case 1: sell_batch<1, B, NR, K>(A, k, r, rl, q, x, acc); break;
-    case 2: sell_batch<2, B, NR, K>(A, k, r, rl, q, x, acc); break;
-    case 3: sell_batch<3, B, NR, K>(A, k, r, rl, q, x, acc); break;
-    case 4: if (KB > 4) sell_batch<(KB > 4 ? 4 : 1), B, NR, K>(A, k, r, rl, q, x, acc); break;
-    case 5: if (KB > 5) sell_batch<(KB > 5 ? 5 : 1), B, NR, K>(A, k, r, rl, q, x, acc); break;
-    case 6: if (KB > 6) sell_batch<(KB > 6 ? 6 : 1), B, NR, K>(A, k, r, rl, q, x, acc); break;
-    case 7: if (KB > 7) sell_batch<(KB > 7 ? 7 : 1), B, NR, K>(A, k, r, rl, q, x, acc); break;
-    default: break;
-  }
+  sell_rest<KB - 1, B, NR, K>(k1 - k, A, k, r, rl, q, x, acc);
   if (K == VK_F16 || K == VK_BF16) acc *= T(ldexpf(1.0f, A.rexp[int64_t(slice) * W + rl]));
   return acc;
 }
@@ -203,10 +213,10 @@ __device__ __forceinline__ SliceLane slice_lane(const SellDev& A, int slice, int
 }
 
 // y = A x (MODE 0), b - A x (MODE 1), M (b - A x) (MODE 2); returns the written value
-template <int B, int NR, int K, class XI, class XO, class T, int MODE>
+template <int B, int NR, int K, class XI, class XO, class T, int MODE, int KB = kb_default<B>()>
 __device__ __forceinline__ T spmv_slice(const SellDev& A, const XO* __restrict__ b, const XI* __restrict__ x,
                                         XO* __restrict__ y, const uint8_t* __restrict__ mask, const SliceLane& s) {
-  const T acc = sell_dot<B, NR, K, XI, T>(A, s.slice, s.lane, s.valid, x);
+  const T acc = sell_dot<B, NR, K, XI, T, KB>(A, s.slice, s.lane, s.valid, x);
   T out = T(0);
   if (s.valid) {
     if (MODE == 0) {
@@ -220,12 +230,12 @@ __device__ __forceinline__ T spmv_slice(const SellDev& A, const XO* __restrict__
   return out;
 }
 
-template <int B, int NR, int K, class X, class T>
+template <int B, int NR, int K, class X, class T, int KB = kb_default<B>()>
 __device__ __forceinline__ void sweep_slice(const SellDev& A, const X* __restrict__ S, const X* __restrict__ b,
                                             const X* __restrict__ x, X* __restrict__ xo, T omega,
                                             const SliceLane& s) {
   constexpr int W = kWave / NR;
-  const T acc = sell_dot<B, NR, K, X, T>(A, s.slice, s.lane, s.valid, x);
+  const T acc = sell_dot<B, NR, K, X, T, KB>(A, s.slice, s.lane, s.valid, x);
   const T res = s.valid ? T(b[s.dof]) - acc : T(0);
   const int rl = s.lane / NR, q = s.lane % NR;
   const int base = (rl / B) * B;
@@ -291,13 +301,13 @@ __device__ __forceinline__ void prolong_dof(const CsrDev& P, const X* __restrict
 }
 
 // ------------------------------------------------------------------ grid kernels
-template <int B, int K, class XI, class XO, class T, int MODE, bool NORM>
+template <int B, int K, class XI, class XO, class T, int MODE, bool NORM, int KB>
 __global__ __launch_bounds__(kThreads) void k_spmv(SellDev A, const XO* __restrict__ b, const XI* __restrict__ x,
                                                    XO* __restrict__ y, const uint8_t* __restrict__ mask,
                                                    double* __restrict__ partials) {
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const SliceLane s = slice_lane<B, 1>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
-  const T out = spmv_slice<B, 1, K, XI, XO, T, MODE>(A, b, x, y, mask, s);
+  const T out = spmv_slice<B, 1, K, XI, XO, T, MODE, KB>(A, b, x, y, mask, s);
   if (NORM) {
     __shared__ double lds[kMaxWaves + 1];
     const double p = block_allsum(double(out) * double(out), lds);
@@ -305,12 +315,12 @@ __global__ __launch_bounds__(kThreads) void k_spmv(SellDev A, const XO* __restri
   }
 }
 
-template <int B, int K, class X, class T>
+template <int B, int K, class X, class T, int KB>
 __global__ __launch_bounds__(kThreads) void k_sweep(SellDev A, const X* __restrict__ S, const X* __restrict__ b,
                                                     const X* __restrict__ x, X* __restrict__ xo, T omega) {
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const SliceLane s = slice_lane<B, 1>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
-  sweep_slice<B, 1, K, X, T>(A, S, b, x, xo, omega, s);
+  sweep_slice<B, 1, K, X, T, KB>(A, S, b, x, xo, omega, s);
 }
 
 template <int B, class X, class T>
@@ -654,6 +664,7 @@ __global__ void k_givens(int j, int m, double* H, double* cs, double* sn, double
   g[j] = cs[j] * g[j];
   st[0] = fabs(g[j + 1]);
   st[1] = breakdown ? 1.0 : 0.0;
+  __threadfence_system();                  // st may be host memory read after the step
 }
 
 __global__ void k_backsolve(int k, int m, const double* H, const double* g, double* y) {
@@ -683,8 +694,13 @@ hipError_t spmv_t(const SellDev& A, const void* b, const void* x, void* y, const
   const XO* bb = static_cast<const XO*>(b);
   const XI* xx = static_cast<const XI*>(x);
   XO* yy = static_cast<XO*>(y);
-#define MGQ1_SPMV(MODE, NORM) \
-  hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, MODE, NORM>), g, kThreads, 0, s, A, bb, xx, yy, mask, partials)
+#define MGQ1_SPMV(MODE, NORM)                                                                          \
+  if (A.kb == kb_alt<B>())                                                                              \
+    hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, MODE, NORM, kb_alt<B>()>), g, kThreads, 0, s, A, bb, xx, yy, \
+                       mask, partials);                                                                  \
+  else                                                                                                   \
+    hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, MODE, NORM, kb_default<B>()>), g, kThreads, 0, s, A, bb, xx, \
+                       yy, mask, partials)
   if (partials) {
     if (mode == 0) MGQ1_SPMV(0, true);
     else if (mode == 1) MGQ1_SPMV(1, true);
@@ -724,13 +740,19 @@ hipError_t sweep_t(const SellDev& A, const void* S, const void* b, const void* x
   const X* bb = static_cast<const X*>(b);
   const X* xx = static_cast<const X*>(x);
   X* oo = static_cast<X*>(xo);
+#define MGQ1_SWEEP(KIND)                                                                                 \
+  if (A.kb == kb_alt<B>())                                                                                \
+    hipLaunchKernelGGL((k_sweep<B, KIND, X, T, kb_alt<B>()>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega)); \
+  else                                                                                                     \
+    hipLaunchKernelGGL((k_sweep<B, KIND, X, T, kb_default<B>()>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega))
   switch (A.kind) {
-    case VK_F64: hipLaunchKernelGGL((k_sweep<B, VK_F64, X, T>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega)); break;
-    case VK_F32: hipLaunchKernelGGL((k_sweep<B, VK_F32, X, T>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega)); break;
-    case VK_F16: hipLaunchKernelGGL((k_sweep<B, VK_F16, X, T>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega)); break;
-    case VK_BF16: hipLaunchKernelGGL((k_sweep<B, VK_BF16, X, T>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega)); break;
+    case VK_F64: MGQ1_SWEEP(VK_F64); break;
+    case VK_F32: MGQ1_SWEEP(VK_F32); break;
+    case VK_F16: MGQ1_SWEEP(VK_F16); break;
+    case VK_BF16: MGQ1_SWEEP(VK_BF16); break;
     default: return hipErrorInvalidValue;
   }
+#undef MGQ1_SWEEP
   return hipGetLastError();
 }
 
@@ -785,6 +807,15 @@ inline unsigned vec_grid(int64_t n) {
 }  // namespace
 
 int reduction_grid(int64_t n) { return int(vec_grid(n)); }
+
+void slot_batch_choices(int B, int* kb_def, int* kb_other) {
+  switch (B) {
+    case 1: *kb_def = kb_default<1>(); *kb_other = kb_alt<1>(); break;
+    case 2: *kb_def = kb_default<2>(); *kb_other = kb_alt<2>(); break;
+    case 3: *kb_def = kb_default<3>(); *kb_other = kb_alt<3>(); break;
+    default: *kb_def = kb_default<4>(); *kb_other = kb_alt<4>(); break;
+  }
+}
 int spmv_grid(const SellDev& A) { return int(slice_grid(A.nslices)); }
 
 hipError_t launch_spmv(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask, int xk, int yk,

@@ -277,6 +277,7 @@ struct LevelDev {
   uint8_t* mask = nullptr;
   CsrDev P, R;            // from level l-1 (l >= 1)
   void *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;   // cycle vectors
+  double us_def = 0.0, us_alt = 0.0;  // measured sweep time of the two slot batches (tuning)
 };
 
 struct mg_handle : DevOwner {
@@ -300,13 +301,19 @@ struct mg_handle : DevOwner {
   double* pv[2] = {nullptr, nullptr};   // per-block partials of the vector reductions
   int* dflag = nullptr;
   double* hs = nullptr;   // pinned host scalars
+  double* hst = nullptr;  // pinned, device-mapped: Givens output of step j at [2j], [2j+1]
+  double* hst_dev = nullptr;             // the same memory as the kernels address it
+  std::vector<hipEvent_t> step_done;     // recorded after FGMRES step j
   hipStream_t cap = nullptr;             // private stream used only to capture graphs
   std::vector<hipGraphExec_t> step_graph; // FGMRES step j (V-cycle, SpMV, MGS, Givens)
   ~mg_handle() {
     for (hipGraphExec_t g : step_graph)
       if (g) (void)hipGraphExecDestroy(g);
+    for (hipEvent_t e : step_done)
+      if (e) (void)hipEventDestroy(e);
     if (cap) (void)hipStreamDestroy(cap);
     if (hs) (void)hipHostFree(hs);
+    if (hst) (void)hipHostFree(hst);
   }
 };
 
@@ -536,7 +543,9 @@ int enqueue_fgmres_step(mg_handle* h, int j, hipStream_t s) {
     MG_HIP(launch_mgs_step(N, w, vi, vn, h->pv[i & 1], h->pv[(i + 1) & 1], Hj + i, s));
   }
   MG_HIP(launch_mgs_normalize(N, w, h->pv[(j + 1) & 1], Hj + j + 1, s));
-  MG_HIP(launch_givens(j, m, h->H, h->cs, h->sn, h->g, h->dsc + 2, s));
+  // |g_{j+1}| and the breakdown flag go straight to pinned host memory (slot j), so the
+  // host can read them while step j+1 is already queued
+  MG_HIP(launch_givens(j, m, h->H, h->cs, h->sn, h->g, h->hst_dev + 2 * j, s));
   return MG_OK;
 }
 
@@ -561,6 +570,13 @@ int fgmres_step(mg_handle* h, int j, hipStream_t s) {
     h->step_graph[j] = ex;
   }
   MG_HIP(hipGraphLaunch(h->step_graph[j], s));
+  return MG_OK;
+}
+
+int enqueue_step(mg_handle* h, int j, hipStream_t s) {
+  int rc = fgmres_step(h, j, s);
+  if (rc) return rc;
+  MG_HIP(hipEventRecord(h->step_done[j], s));
   return MG_OK;
 }
 
@@ -602,17 +618,27 @@ int solve_impl(mg_handle* h, const double* b, double* x, mg_solve_stats* st, voi
       if (S.iters >= limit || beta == 0.0) { status = (fixed > 0 || beta == 0.0) ? MG_OK : MG_ENOCONV; break; }
       MG_HIP(launch_scale_div(N, h->V, h->rout, h->dsc + 0, s));
       MG_HIP(launch_init_g(m, h->g, h->dsc + 0, s));
+      // Step j+1 is queued before the host waits for step j whenever the residual
+      // estimates predict that it will be needed (a mispredicted step only costs time: it
+      // writes basis vectors and Hessenberg entries beyond the ones the update uses).
       int k = 0;
+      double last = beta, rate = 0.5;
+      if ((rc = enqueue_step(h, 0, s))) return rc;
       for (int j = 0; j < m; ++j) {
-        if ((rc = fgmres_step(h, j, s))) return rc;
         ++S.iters;
-        if ((rc = read_scalars(h, h->dsc + 2, 2, s))) return rc;
+        const bool more = j + 1 < m && S.iters < limit;
+        const bool spec = more && (fixed > 0 || last * rate > 2.0 * tol);
+        if (spec && (rc = enqueue_step(h, j + 1, s))) return rc;
+        MG_HIP(hipEventSynchronize(h->step_done[j]));
         k = j + 1;
-        const double est = h->hs[0];
-        const bool breakdown = h->hs[1] != 0.0;
+        const double est = h->hst[2 * j];
+        const bool breakdown = h->hst[2 * j + 1] != 0.0;
         if (!std::isfinite(est)) { status = MG_ENUMERIC; break; }
         if (breakdown || S.iters >= limit) break;
         if (fixed <= 0 && est <= tol) break;
+        if (est > 0.0 && last > 0.0) rate = std::min(1.0, est / last);
+        last = est;
+        if (!spec && more && (rc = enqueue_step(h, j + 1, s))) return rc;
       }
       if (status == MG_ENUMERIC) break;
       MG_HIP(launch_backsolve(k, m, h->H, h->g, h->y, s));
@@ -749,6 +775,90 @@ int check_flag(int* flag, hipStream_t s) {
   return MG_OK;
 }
 
+// Slot-batch choice per level.  slot_batch == 0: time the level's smoothing sweep with
+// both slot-batch variants (interleaved repetitions, minimum kept) and keep the faster for
+// the sweeps and defects of that level; the finest FP64 operator of a mixed-precision
+// handle is timed with the outer defect.  Otherwise the given value is used everywhere.
+// Both variants run the FMAs in the same order, so the choice never changes a result.
+int tune_levels(mg_handle* h, hipStream_t s) {
+  const int req = h->cfg.slot_batch;
+  for (LevelDev& D : h->lv) {
+    int kd, ko;
+    slot_batch_choices(D.B, &kd, &ko);
+    if (req != 0 && req != kd && req != ko)
+      return fail(MG_EINVAL, "slot_batch must be 0 or one of the two batch sizes built for this block size");
+    if (req != 0) {
+      D.Ac.kb = D.A64.kb = req;
+      continue;
+    }
+  }
+  if (req != 0) return MG_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  MG_HIP(hipEventCreate(&e0));
+  MG_HIP(hipEventCreate(&e1));
+  int rc = MG_OK;
+  auto timed = [&](auto&& launch, int reps, float* ms) -> int {
+    MG_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) MG_HIP(launch(i));
+    MG_HIP(hipEventRecord(e1, s));
+    MG_HIP(hipEventSynchronize(e1));
+    MG_HIP(hipEventElapsedTime(ms, e0, e1));
+    return MG_OK;
+  };
+  const double omega = h->cfg.omega;
+  for (size_t l = 0; l < h->lv.size() && rc == MG_OK; ++l) {
+    LevelDev& D = h->lv[l];
+    int kb[2];
+    slot_batch_choices(D.B, &kb[0], &kb[1]);
+    if ((rc = launch_fill(D.N, D.x, h->xk, 1.0, s) == hipSuccess ? MG_OK : MG_EDEVICE)) break;
+    if ((rc = launch_fill(D.N, D.b, h->xk, 1.0, s) == hipSuccess ? MG_OK : MG_EDEVICE)) break;
+    float best[2] = {1e30f, 1e30f};
+    for (int rep = 0; rep < 3 && rc == MG_OK; ++rep)
+      for (int v = 0; v < 2 && rc == MG_OK; ++v) {
+        D.Ac.kb = kb[v];
+        float ms = 0.f;
+        rc = timed([&](int i) {
+          return (i & 1) ? launch_sweep(D.Ac, D.S, D.b, D.t, D.x, omega, h->xk, s)
+                         : launch_sweep(D.Ac, D.S, D.b, D.x, D.t, omega, h->xk, s);
+        }, 10, &ms);
+        best[v] = std::min(best[v], ms);
+      }
+    const int pick = best[1] < best[0] ? 1 : 0;
+    D.Ac.kb = kb[pick];
+    if (h->xk == X_F64) D.A64.kb = kb[pick];
+    D.us_def = 100.0 * best[0];          // ms per 10 launches -> us per launch
+    D.us_alt = 100.0 * best[1];
+  }
+  if (rc == MG_OK && h->xk != X_F64) {
+    // FP64 outer defect of a mixed-precision handle: r = b - A x with norm partials
+    LevelDev& T = h->lv[h->L];
+    int kb[2];
+    slot_batch_choices(T.B, &kb[0], &kb[1]);
+    double* xb = h->V ? h->V : nullptr;
+    if (xb == nullptr) {
+      T.A64.kb = T.Ac.kb;
+    } else {
+      const int64_t N = T.N;
+      if ((rc = launch_fill(2 * N, xb, X_F64, 1.0, s) == hipSuccess ? MG_OK : MG_EDEVICE) == MG_OK) {
+        float best[2] = {1e30f, 1e30f};
+        for (int rep = 0; rep < 3 && rc == MG_OK; ++rep)
+          for (int v = 0; v < 2 && rc == MG_OK; ++v) {
+            T.A64.kb = kb[v];
+            float ms = 0.f;
+            rc = timed([&](int) {
+              return launch_spmv(T.A64, xb, xb + N, h->rout, nullptr, X_F64, X_F64, 1, h->pbig, s);
+            }, 10, &ms);
+            best[v] = std::min(best[v], ms);
+          }
+        T.A64.kb = kb[best[1] < best[0] ? 1 : 0];
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
 int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
   const mg_config& c = h->cfg;
   const int n_levels = int(H.size());
@@ -789,6 +899,7 @@ int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
   if ((rc = dalloc(h, &h->pbig, size_t(maxgrid)))) return rc;
   for (int q = 0; q < 2; ++q)
     if ((rc = dalloc(h, &h->pv[q], size_t(kMaxRedBlocks)))) return rc;
+  if ((rc = tune_levels(h, s))) return rc;
   // tail: every level up to the largest one with at most tail_dofs unknowns.  Default off:
   // on MI355X one workgroup walking several levels was measured slower (dependent-load
   // latency serialises) than separate grid launches per step.
@@ -814,6 +925,11 @@ int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
   if ((rc = dalloc(h, &h->dtail, tl.size()))) return rc;
   MG_HIP(hipMemcpyAsync(h->dtail, tl.data(), tl.size() * sizeof(TailLevel), hipMemcpyHostToDevice, s));
   MG_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hs), 16 * sizeof(double), hipHostMallocDefault));
+  MG_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hst), 2 * size_t(m) * sizeof(double),
+                       hipHostMallocMapped | hipHostMallocCoherent));
+  MG_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&h->hst_dev), h->hst, 0));
+  h->step_done.assign(size_t(m), nullptr);
+  for (hipEvent_t& e : h->step_done) MG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   h->step_graph.assign(size_t(m), nullptr);
   if (c.use_graph) MG_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
   MG_HIP(hipStreamSynchronize(s));
@@ -1496,6 +1612,18 @@ int mg_level_info(const mg_handle* h, int32_t level, int32_t* n_nodes, int32_t* 
   if (n_nodes) *n_nodes = L.n;
   if (block) *block = L.B;
   if (nnzb) *nnzb = L.nnzb;
+  return MG_OK;
+}
+
+int mg_level_tuning(const mg_handle* h, int32_t level, int32_t* slot_batch, double* us_default,
+                    double* us_other) {
+  if (!h || level < 0 || level > h->L) return fail(MG_EINVAL, "bad handle or level");
+  const LevelDev& L = h->lv[level];
+  int kd, ko;
+  slot_batch_choices(L.B, &kd, &ko);
+  if (slot_batch) *slot_batch = L.Ac.kb ? L.Ac.kb : kd;
+  if (us_default) *us_default = L.us_def;
+  if (us_other) *us_other = L.us_alt;
   return MG_OK;
 }
 

@@ -32,7 +32,8 @@ class Config(C.Structure):
     _fields_ = [("omega", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("coarse_mode", C.c_int32), ("coarse_sweeps", C.c_int32),
                 ("precision", C.c_int32), ("outer", C.c_int32), ("gmres_m", C.c_int32),
-                ("maxit", C.c_int32), ("rtol", C.c_double), ("use_graph", C.c_int32)]
+                ("maxit", C.c_int32), ("rtol", C.c_double), ("use_graph", C.c_int32),
+                ("slot_batch", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -48,7 +49,8 @@ SYMBOLS = ["mg_setup_hierarchy", "mg_vcycle", "mg_solve", "mg_solve_fixed", "mg_
            "mg_level_spmv", "mg_level_sweep", "mg_level_sweep0", "mg_level_restrict",
            "mg_level_prolong", "mg_coarse_solve", "mg_level_info", "mg_num_levels",
            "mg_validate_level", "mg_destroy", "mg_status_string", "mg_last_error",
-           "mg_setup_batch", "mg_batch_offsets", "mg_solve_batch", "mg_destroy_batch"]
+           "mg_setup_batch", "mg_batch_offsets", "mg_solve_batch", "mg_destroy_batch",
+           "mg_level_tuning"]
 
 
 def lib():
@@ -68,6 +70,7 @@ def lib():
         L.mg_level_prolong.argtypes = [vp, i32, vp, vp, vp]
         L.mg_coarse_solve.argtypes = [vp, vp, vp, vp]
         L.mg_level_info.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_int64)]
+        L.mg_level_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.mg_num_levels.argtypes = [vp]
         L.mg_num_levels.restype = i32
         L.mg_validate_level.argtypes = [C.POINTER(LevelIn), C.POINTER(LevelIn)]
@@ -153,6 +156,7 @@ def config_from(wl: W.Workload, precision="fp64", **over) -> Config:
     c.maxit = over.get("maxit", wl.maxit)
     c.rtol = over.get("rtol", wl.rtol)
     c.use_graph = over.get("use_graph", 1)
+    c.slot_batch = over.get("slot_batch", 0)
     return c
 
 
@@ -184,6 +188,12 @@ class Hierarchy:
         n, b, nnzb = C.c_int32(), C.c_int32(), C.c_int64()
         _check(lib().mg_level_info(self.h, l, C.byref(n), C.byref(b), C.byref(nnzb)))
         return n.value, b.value, nnzb.value
+
+    def tuning(self, l):
+        """(slot batch in use, measured us per sweep for the default / other size)."""
+        kb, t0, t1 = C.c_int32(), C.c_double(), C.c_double()
+        _check(lib().mg_level_tuning(self.h, l, C.byref(kb), C.byref(t0), C.byref(t1)))
+        return kb.value, t0.value, t1.value
 
     def ndof(self, l=-1):
         n, b, _ = self.sizes[l]

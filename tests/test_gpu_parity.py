@@ -254,3 +254,33 @@ def test_graph_and_eager_agree(name):
         torch.cuda.synchronize()
         assert st_g["iters"] == st_e["iters"]
         assert np.array_equal(host(xg), ge), rep
+
+
+@pytest.mark.parametrize("name", ["poisson33", "td_band", "elast17", "oseen17", "edge4"])
+def test_slot_batch_variants_bitwise_equal(name):
+    """Both slot-batch sizes (and the autotuned choice) run the FMAs in slot order, so the
+    V-cycle and the solve are bitwise identical whichever size a level uses."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    kb_pairs = {1: (8, 16), 3: (4, 8), 4: (4, 8)}[wl.block]
+    outs = []
+    for kb in (0,) + kb_pairs:
+        h = mg.Hierarchy(p.levels, mg.config_from(wl, slot_batch=kb))
+        for l in range(h.n_levels):
+            used, t0, t1 = h.tuning(l)
+            assert used in kb_pairs and (kb == 0 or used == kb)
+            assert (t0 > 0 and t1 > 0) if kb == 0 else (t0 == 0 and t1 == 0)
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        h.vcycle(dev(o.b), x)
+        xs = torch.zeros_like(x)
+        st = h.solve(dev(o.b), xs)
+        outs.append((host(x), host(xs), st["iters"]))
+    for v, s, it in outs[1:]:
+        assert np.array_equal(v, outs[0][0]) and np.array_equal(s, outs[0][1]) and it == outs[0][2]
+
+
+def test_slot_batch_rejects_unbuilt_size():
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair("td_band")
+    with pytest.raises(mg.MGError):
+        mg.Hierarchy(p.levels, mg.config_from(wl, slot_batch=5))
