@@ -68,6 +68,26 @@ def time_solves(torch, h, b, x, steps, warmup):
     return (time.perf_counter() - t0) / steps, stats
 
 
+def counter_traffic(workload_name):
+    """HBM bytes per launch of the finest-level FP64 sweep from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy), or None when
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_sweep_fp64_counters.json")
+    src = os.path.join(ROOT, "paper_2405_05047_amd", "csrc", "mgq1_kernels.hip")
+    try:
+        with open(path) as f:
+            table = json.load(f)
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    entry = table.get(workload_name)
+    if not entry or entry.get("kernels_sha256") != digest:
+        return None
+    return entry["traffic_bytes_per_launch"]
+
+
 def kernel_time(torch, h, level, n_dof, launches=50):
     """Average duration of the finest-level smoothing sweep with HIP events on the
     stream the library launches on (torch's current stream)."""
@@ -250,7 +270,8 @@ def main():
         rel = float(np.linalg.norm(prob.b - A @ xs) / np.linalg.norm(prob.b))
         results[prec] = {"dof_per_s": N / sec, "ms_per_solve": sec * 1e3, "cycles": stats[-1]["iters"],
                          "converged": all(s["converged"] for s in stats), "rel_residual": rel,
-                         "setup_s": round(t_setup, 3)}
+                         "setup_s": round(t_setup, 3),
+                         "slot_batch_per_level": [h.tuning(l)[0] for l in range(h.n_levels)]}
         handles[prec] = h
         _progress(f"{wl.name} {prec}: {sec * 1e3:.2f} ms per solve, {stats[-1]['iters']} cycles")
     base = results["fp64"]
@@ -273,7 +294,7 @@ def main():
     kbytes = sweep_bytes(n, bs, nnzb)
     achieved = kbytes / ksec / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(wl.name),
             "kernel": "k_sweep<B=%d,FP64> finest level" % bs, "bytes_per_launch": kbytes,
             "us_per_launch": round(ksec * 1e6, 2)}
 
