@@ -38,7 +38,7 @@ def build_hip():
     srcs = [os.path.join(CSRC, s) for s in HIP_SOURCES]
     cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-ffp-contract=fast", "-Wall",
+           "-ffp-contract=on", "-Wall",
            "-I", INCLUDE] + srcs + ["-o", LIB_MG + ".tmp"]
     _run(cmd)
     os.replace(LIB_MG + ".tmp", LIB_MG)

@@ -47,6 +47,25 @@ struct CsrDev {
   int f32 = 1;
 };
 
+// the same scalar transfer matrix as a sliced ELL over node rows (the layout the grid
+// kernels use): a slice holds R = 64 / (B * NR) rows, one lane per (row, component, rhs);
+// slot k of row r of slice s sits at col / w[k * R + r] with k in [sptr[s], sptr[s+1]),
+// padded slots carry weight 0 and a column of their own row
+struct TSellDev {
+  int32_t nrows = 0, ncols = 0, R = 64, nslices = 0;
+  const int32_t* sptr = nullptr;
+  const int32_t* col = nullptr;
+  const void* w = nullptr;
+  int f32 = 1;
+};
+
+// d = M_c P~^T M_f r (rows = coarse nodes; mask_f may be NULL) and x += M_f P~ M_c y
+// (rows = fine nodes), single right-hand side, with the sliced transfer matrices
+hipError_t launch_restrict_s(const TSellDev& R, int B, const void* r, void* d, const uint8_t* mask_c,
+                             const uint8_t* mask_f, int xk, hipStream_t s);
+hipError_t launch_prolong_s(const TSellDev& P, int B, const void* y, void* x, const uint8_t* mask_f,
+                            const uint8_t* mask_c, int xk, hipStream_t s);
+
 // one level of the single-workgroup tail of the V-cycle (device-resident array)
 struct TailLevel {
   SellDev A;                        // cycle operator
@@ -76,14 +95,11 @@ int spmv_grid(const SellDev& A);
 hipError_t launch_sweep(const SellDev& A, const void* S, const void* b, const void* x, void* xo,
                         double omega, int xk, hipStream_t s);
 // x_out = omega S b
+// two sweeps from x = 0 in one pass (block size 1): xo = x1 + omega S (b - A x1), x1 = omega S b
+hipError_t launch_sweep2z(const SellDev& A, const void* S, const void* b, void* xo, double omega, int xk,
+                          hipStream_t s);
 hipError_t launch_sweep0(const SellDev& A, const void* S, const void* b, void* xo, double omega,
                          int xk, hipStream_t s);
-// d = M_c P~^T M_f r; mask_f may be NULL when r is already zero on constrained fine DoFs
-hipError_t launch_restrict(const CsrDev& R, int B, const void* r, void* d, const uint8_t* mask_c,
-                           const uint8_t* mask_f, int xk, hipStream_t s);
-// x += M_f P~ M_c y
-hipError_t launch_prolong(const CsrDev& P, int B, const void* y, void* x, const uint8_t* mask_f,
-                          const uint8_t* mask_c, int xk, hipStream_t s);
 // x = Ainv b with the FP64 inverse stored row-major; b / x of kind xk
 hipError_t launch_coarse_gemv(int n, const double* Ainv, const void* b, void* x, int xk, hipStream_t s);
 // Gauss-Jordan with partial pivoting on the n x 2n augmented matrix M = [A | I]
@@ -148,7 +164,7 @@ struct BEntry {
   SellDev A;
   const void* S = nullptr;
   const uint8_t* mask = nullptr;
-  CsrDev T;
+  TSellDev Ts;                       // transfer from the next coarser level (restrict / prolong)
   const uint8_t* mask_c = nullptr;
   const void* in0 = nullptr;
   const void* in1 = nullptr;
@@ -160,7 +176,7 @@ struct BEntry {
 };
 
 // blocks of an entry for a launch kind
-int batched_blocks(int kind, const SellDev& A, const CsrDev& T, int n0, int NR);
+int batched_blocks(int kind, const SellDev& A, const TSellDev& Ts, int n0, int NR);
 // one batched step; `active[prob] == 0` skips a problem; `partials` for BK_DEFECT64
 hipError_t launch_batched(int kind, const BEntry* entries, int n_entries, int n_blocks, int B, int NR, int vkind,
                           int xk, double omega, const int* active, double* partials, hipStream_t s);

@@ -124,6 +124,44 @@ __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int r
 // val[(k * B + cc) * W + rl] with the padded row-lane stride W = 64 / NR (R * B rounded up,
 // 64 for one right-hand side).  NR = 1 is the single right-hand-side layout.  Slots are
 // consumed in batches of KB, the remainder in one shorter batch (slice-uniform branch).
+// The same batch for the second of two sweeps from x = 0 with b = 1: the iterate after the
+// first sweep, x1_j = omega * (S_j * b_j), is formed on the fly from S and b instead of being
+// read (S of node j sits at S[j] for one component and one right-hand side), with the
+// rounding of the stored value, so the result is bitwise that of the two separate sweeps.
+template <int NB, int K, class X, class T>
+__device__ __forceinline__ void sell_batch_z(const SellDev& A, int k, int rl, const X* __restrict__ S,
+                                             const X* __restrict__ b, T omega, T& acc) {
+  using VR = typename Val<K>::raw;
+  unsigned js[NB];
+  VR av[NB];
+  X sv[NB], bv[NB];
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) js[qq] = unsigned(__builtin_nontemporal_load(A.col + int64_t(k + qq) * kWave + rl));
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) av[qq] = Val<K>::load(A.val, int64_t(k + qq) * kWave + rl);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) {
+    sv[qq] = S[js[qq]];
+    bv[qq] = b[js[qq]];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) {
+    const X x1 = X(omega * (T(0) + T(sv[qq]) * T(bv[qq])));
+    acc += T(Val<K>::dec(av[qq])) * T(x1);
+  }
+}
+
+template <int N, int K, class X, class T>
+__device__ __forceinline__ void sell_rest_z(int rem, const SellDev& A, int k, int rl, const X* __restrict__ S,
+                                            const X* __restrict__ b, T omega, T& acc) {
+  if constexpr (N >= 1) {
+    if (rem == N) sell_batch_z<N, K, X, T>(A, k, rl, S, b, omega, acc);
+    else sell_rest_z<N - 1, K, X, T>(rem, A, k, rl, S, b, omega, acc);
+  }
+}
+
 // the remaining rem < KB slots of a slice as one batch of exactly rem slots
 template <int N, int B, int NR, int K, class XI, class T>
 __device__ __forceinline__ void sell_rest(int rem, const SellDev& A, int k, int r, int rl, int q,
@@ -300,6 +338,80 @@ __device__ __forceinline__ void prolong_dof(const CsrDev& P, const X* __restrict
   x[t] = X(T(x[t]) + acc);
 }
 
+// ---- sliced transfers: NB slots of one node row, loads first (straight-line), then the
+// weighted sum in slot order.  MC: apply the column mask (entries whose column DoF is
+// masked contribute 0).
+template <int NB, int B, int NR, class X, class T, class WT, bool MC>
+__device__ __forceinline__ void tsell_batch(const TSellDev& M, int k, int r, int c, int q,
+                                            const X* __restrict__ in, const uint8_t* __restrict__ mcol,
+                                            T& acc) {
+  const int R = M.R;
+  unsigned js[NB];
+  WT ws[NB];
+  X vs[NB];
+  uint8_t ms[NB];
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) {
+    js[qq] = unsigned(__builtin_nontemporal_load(M.col + int64_t(k + qq) * R + r));
+    ws[qq] = __builtin_nontemporal_load(static_cast<const WT*>(M.w) + int64_t(k + qq) * R + r);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) {
+    const uint64_t d = uint64_t(js[qq]) * B + c;
+    vs[qq] = in[d * NR + q];
+    ms[qq] = MC ? mcol[d] : uint8_t(0);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) acc += T(ws[qq]) * (ms[qq] ? T(0) : T(vs[qq]));
+}
+
+template <int N, int B, int NR, class X, class T, class WT, bool MC>
+__device__ __forceinline__ void tsell_rest(int rem, const TSellDev& M, int k, int r, int c, int q,
+                                           const X* __restrict__ in, const uint8_t* __restrict__ mcol, T& acc) {
+  if constexpr (N >= 1) {
+    if (rem == N) tsell_batch<N, B, NR, X, T, WT, MC>(M, k, r, c, q, in, mcol, acc);
+    else tsell_rest<N - 1, B, NR, X, T, WT, MC>(rem, M, k, r, c, q, in, mcol, acc);
+  }
+}
+
+// one lane of a sliced transfer.  MODE 0: out = restriction sum (zero on masked rows);
+// MODE 1: out += prolongation sum (rows whose DoF is masked are left unchanged)
+template <int B, int NR, class X, class T, class WT, bool MC, int MODE>
+__device__ __forceinline__ void tsell_lane(const TSellDev& M, int slice, int lane, const X* __restrict__ in,
+                                           X* __restrict__ out, const uint8_t* __restrict__ mrow,
+                                           const uint8_t* __restrict__ mcol) {
+  constexpr int KB = 8;
+  const int R = M.R;
+  const int r = lane / (B * NR), c = (lane / NR) % B, q = lane % NR;
+  const int node = slice * R + r;
+  if (slice >= M.nslices || lane >= R * B * NR || node >= M.nrows) return;
+  const int64_t dof = int64_t(node) * B + c;
+  const int64_t t = dof * NR + q;
+  const uint8_t masked = mrow[dof];        // issued together with the slice bounds
+  const int k1 = M.sptr[slice + 1];
+  int k = M.sptr[slice];
+  if (masked) {
+    if (MODE == 0) out[t] = X(0);
+    return;
+  }
+  T acc = T(0);
+  for (; k + KB <= k1; k += KB) tsell_batch<KB, B, NR, X, T, WT, MC>(M, k, r, c, q, in, mcol, acc);
+  tsell_rest<KB - 1, B, NR, X, T, WT, MC>(k1 - k, M, k, r, c, q, in, mcol, acc);
+  if (MODE == 0) out[t] = X(acc);
+  else out[t] = X(T(out[t]) + acc);
+}
+
+template <int B, int NR, class X, class T, class WT, bool MC, int MODE>
+__global__ __launch_bounds__(kThreads) void k_tsell(TSellDev M, const X* __restrict__ in, X* __restrict__ out,
+                                                    const uint8_t* __restrict__ mrow,
+                                                    const uint8_t* __restrict__ mcol) {
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  tsell_lane<B, NR, X, T, WT, MC, MODE>(M, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave, in, out,
+                                        mrow, mcol);
+}
+
 // ------------------------------------------------------------------ grid kernels
 template <int B, int K, class XI, class XO, class T, int MODE, bool NORM, int KB>
 __global__ __launch_bounds__(kThreads) void k_spmv(SellDev A, const XO* __restrict__ b, const XI* __restrict__ x,
@@ -323,6 +435,29 @@ __global__ __launch_bounds__(kThreads) void k_sweep(SellDev A, const X* __restri
   sweep_slice<B, 1, K, X, T, KB>(A, S, b, x, xo, omega, s);
 }
 
+// two smoothing sweeps from x = 0 in one pass, one component per node:
+// x1 = omega S b (formed per column on the fly), x2 = x1 + omega S (b - A x1)
+template <int K, class X, class T, int KB>
+__global__ __launch_bounds__(kThreads) void k_sweep2z(SellDev A, const X* __restrict__ S, const X* __restrict__ b,
+                                                      X* __restrict__ xo, T omega) {
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int slice = bid * kSliceWaves + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int64_t i = int64_t(slice) * kWave + lane;
+  if (slice >= A.nslices || i >= A.n) return;
+  const X si = S[i], bi = b[i];              // issued with the slice bounds
+  const int k1 = A.sptr[slice + 1];
+  int k = A.sptr[slice];
+  T acc = T(0);
+  for (; k + KB <= k1; k += KB) sell_batch_z<KB, K, X, T>(A, k, lane, S, b, omega, acc);
+  sell_rest_z<KB - 1, K, X, T>(k1 - k, A, k, lane, S, b, omega, acc);
+  if (K == VK_F16 || K == VK_BF16) acc *= T(ldexpf(1.0f, A.rexp[int64_t(slice) * kWave + lane]));
+  const X x1 = X(omega * (T(0) + T(si) * T(bi)));
+  const T res = T(bi) - acc;
+  const T upd = T(0) + T(si) * res;
+  xo[i] = X(T(x1) + omega * upd);
+}
+
 template <int B, class X, class T>
 __global__ __launch_bounds__(kThreads) void k_sweep0(SellDev A, const X* __restrict__ S, const X* __restrict__ b,
                                                      X* __restrict__ xo, T omega) {
@@ -330,21 +465,6 @@ __global__ __launch_bounds__(kThreads) void k_sweep0(SellDev A, const X* __restr
   sweep0_slice<B, 1, X, T>(S, b, xo, omega, s);
 }
 
-template <int B, class X, class T>
-__global__ __launch_bounds__(kThreads) void k_restrict(CsrDev R, const X* __restrict__ r, X* __restrict__ d,
-                                                       const uint8_t* __restrict__ mask_c,
-                                                       const uint8_t* __restrict__ mask_f) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < int64_t(R.nrows) * B) restrict_dof<B, 1, X, T>(R, r, d, mask_c, mask_f, t);
-}
-
-template <int B, class X, class T>
-__global__ __launch_bounds__(kThreads) void k_prolong(CsrDev P, const X* __restrict__ y, X* __restrict__ x,
-                                                      const uint8_t* __restrict__ mask_f,
-                                                      const uint8_t* __restrict__ mask_c) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < int64_t(P.nrows) * B) prolong_dof<B, 1, X, T>(P, y, x, mask_f, mask_c, t);
-}
 
 // x = Ainv b, one wavefront per row (Ainv row-major, FP64)
 template <class XI, class XO>
@@ -745,37 +865,20 @@ hipError_t sweep_t(const SellDev& A, const void* S, const void* b, const void* x
     hipLaunchKernelGGL((k_sweep<B, KIND, X, T, kb_alt<B>()>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega)); \
   else                                                                                                     \
     hipLaunchKernelGGL((k_sweep<B, KIND, X, T, kb_default<B>()>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega))
-  switch (A.kind) {
-    case VK_F64: MGQ1_SWEEP(VK_F64); break;
-    case VK_F32: MGQ1_SWEEP(VK_F32); break;
-    case VK_F16: MGQ1_SWEEP(VK_F16); break;
-    case VK_BF16: MGQ1_SWEEP(VK_BF16); break;
-    default: return hipErrorInvalidValue;
+  // FP64 vectors go with FP64 values only; FP32 vectors with the reduced formats
+  if constexpr (sizeof(X) == 8) {
+    if (A.kind != VK_F64) return hipErrorInvalidValue;
+    MGQ1_SWEEP(VK_F64);
+  } else {
+    switch (A.kind) {
+      case VK_F32: MGQ1_SWEEP(VK_F32); break;
+      case VK_F16: MGQ1_SWEEP(VK_F16); break;
+      case VK_BF16: MGQ1_SWEEP(VK_BF16); break;
+      default: return hipErrorInvalidValue;
+    }
   }
 #undef MGQ1_SWEEP
   return hipGetLastError();
-}
-
-template <int B, class X, class T>
-hipError_t transfer_t(bool restrict_op, const CsrDev& M, const void* in, void* out, const uint8_t* m1,
-                      const uint8_t* m2, hipStream_t s) {
-  const int64_t n = int64_t(M.nrows) * B;
-  if (n == 0) return hipSuccess;
-  const unsigned g = grid_for(n, kThreads);
-  if (restrict_op)
-    hipLaunchKernelGGL((k_restrict<B, X, T>), g, kThreads, 0, s, M, static_cast<const X*>(in), static_cast<X*>(out),
-                       m1, m2);
-  else
-    hipLaunchKernelGGL((k_prolong<B, X, T>), g, kThreads, 0, s, M, static_cast<const X*>(in), static_cast<X*>(out),
-                       m1, m2);
-  return hipGetLastError();
-}
-
-template <int B>
-hipError_t transfer_b(bool restrict_op, const CsrDev& M, const void* in, void* out, const uint8_t* m1,
-                      const uint8_t* m2, int xk, hipStream_t s) {
-  if (xk == X_F64) return transfer_t<B, double, double>(restrict_op, M, in, out, m1, m2, s);
-  return transfer_t<B, float, float>(restrict_op, M, in, out, m1, m2, s);
 }
 
 template <int B, int K, class X, class T>
@@ -863,6 +966,33 @@ static hipError_t sweep0_b(const SellDev& A, const void* S, const void* b, void*
   return hipGetLastError();
 }
 
+hipError_t launch_sweep2z(const SellDev& A, const void* S, const void* b, void* xo, double omega, int xk,
+                          hipStream_t s) {
+  if (A.B != 1) return hipErrorInvalidValue;
+  const unsigned g = slice_grid(A.nslices);
+  if (g == 0) return hipSuccess;
+#define MGQ1_S2Z(KIND, X, T)                                                                                 \
+  if (A.kb == kb_alt<1>())                                                                                    \
+    hipLaunchKernelGGL((k_sweep2z<KIND, X, T, kb_alt<1>()>), g, kThreads, 0, s, A, static_cast<const X*>(S),   \
+                       static_cast<const X*>(b), static_cast<X*>(xo), T(omega));                              \
+  else                                                                                                        \
+    hipLaunchKernelGGL((k_sweep2z<KIND, X, T, kb_default<1>()>), g, kThreads, 0, s, A, static_cast<const X*>(S), \
+                       static_cast<const X*>(b), static_cast<X*>(xo), T(omega))
+  if (xk == X_F64) {
+    if (A.kind != VK_F64) return hipErrorInvalidValue;
+    MGQ1_S2Z(VK_F64, double, double);
+  } else {
+    switch (A.kind) {
+      case VK_F32: MGQ1_S2Z(VK_F32, float, float); break;
+      case VK_F16: MGQ1_S2Z(VK_F16, float, float); break;
+      case VK_BF16: MGQ1_S2Z(VK_BF16, float, float); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef MGQ1_S2Z
+  return hipGetLastError();
+}
+
 hipError_t launch_sweep0(const SellDev& A, const void* S, const void* b, void* xo, double omega, int xk,
                          hipStream_t s) {
   switch (A.B) {
@@ -874,27 +1004,56 @@ hipError_t launch_sweep0(const SellDev& A, const void* S, const void* b, void* x
   }
 }
 
-hipError_t launch_restrict(const CsrDev& R, int B, const void* r, void* d, const uint8_t* mask_c,
-                           const uint8_t* mask_f, int xk, hipStream_t s) {
-  switch (B) {
-    case 1: return transfer_b<1>(true, R, r, d, mask_c, mask_f, xk, s);
-    case 2: return transfer_b<2>(true, R, r, d, mask_c, mask_f, xk, s);
-    case 3: return transfer_b<3>(true, R, r, d, mask_c, mask_f, xk, s);
-    case 4: return transfer_b<4>(true, R, r, d, mask_c, mask_f, xk, s);
-    default: return hipErrorInvalidValue;
+namespace {
+template <int B, class X, class T, class WT>
+hipError_t tsell_w(int mode, const TSellDev& M, const void* in, void* out, const uint8_t* mrow,
+                   const uint8_t* mcol, hipStream_t s) {
+  const unsigned g = slice_grid(M.nslices);
+  if (g == 0) return hipSuccess;
+  const X* ii = static_cast<const X*>(in);
+  X* oo = static_cast<X*>(out);
+  if (mode == 0) {
+    if (mcol) hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, true, 0>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
+    else hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, false, 0>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
+  } else {
+    hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, true, 1>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
   }
+  return hipGetLastError();
 }
 
-hipError_t launch_prolong(const CsrDev& P, int B, const void* y, void* x, const uint8_t* mask_f,
-                          const uint8_t* mask_c, int xk, hipStream_t s) {
+template <int B>
+hipError_t tsell_b(int mode, const TSellDev& M, const void* in, void* out, const uint8_t* mrow,
+                   const uint8_t* mcol, int xk, hipStream_t s) {
+  if (xk == X_F64)
+    return M.f32 ? tsell_w<B, double, double, float>(mode, M, in, out, mrow, mcol, s)
+                 : tsell_w<B, double, double, double>(mode, M, in, out, mrow, mcol, s);
+  return M.f32 ? tsell_w<B, float, float, float>(mode, M, in, out, mrow, mcol, s)
+               : tsell_w<B, float, float, double>(mode, M, in, out, mrow, mcol, s);
+}
+
+hipError_t tsell_launch(int mode, const TSellDev& M, int B, const void* in, void* out, const uint8_t* mrow,
+                        const uint8_t* mcol, int xk, hipStream_t s) {
+  if (M.R != kWave / B) return hipErrorInvalidValue;     // single right-hand-side layout
   switch (B) {
-    case 1: return transfer_b<1>(false, P, y, x, mask_f, mask_c, xk, s);
-    case 2: return transfer_b<2>(false, P, y, x, mask_f, mask_c, xk, s);
-    case 3: return transfer_b<3>(false, P, y, x, mask_f, mask_c, xk, s);
-    case 4: return transfer_b<4>(false, P, y, x, mask_f, mask_c, xk, s);
+    case 1: return tsell_b<1>(mode, M, in, out, mrow, mcol, xk, s);
+    case 2: return tsell_b<2>(mode, M, in, out, mrow, mcol, xk, s);
+    case 3: return tsell_b<3>(mode, M, in, out, mrow, mcol, xk, s);
+    case 4: return tsell_b<4>(mode, M, in, out, mrow, mcol, xk, s);
     default: return hipErrorInvalidValue;
   }
 }
+}  // namespace
+
+hipError_t launch_restrict_s(const TSellDev& R, int B, const void* r, void* d, const uint8_t* mask_c,
+                             const uint8_t* mask_f, int xk, hipStream_t s) {
+  return tsell_launch(0, R, B, r, d, mask_c, mask_f, xk, s);
+}
+
+hipError_t launch_prolong_s(const TSellDev& P, int B, const void* y, void* x, const uint8_t* mask_f,
+                            const uint8_t* mask_c, int xk, hipStream_t s) {
+  return tsell_launch(1, P, B, y, x, mask_f, mask_c, xk, s);
+}
+
 
 hipError_t launch_tail(const TailLevel* lv, int B, int kind, int xk, const TailParams& p, hipStream_t s) {
   switch (B) {
@@ -1118,14 +1277,29 @@ __global__ __launch_bounds__(kThreads) void k_belem(const BEntry* __restrict__ E
   const BEntry& e = E[se];
   if (active && !active[e.prob]) return;
   const int64_t t = int64_t(blockIdx.x - e.first) * kThreads + threadIdx.x;
+  if (t < int64_t(e.A.n) * B * NR) static_cast<X*>(e.out)[t] = X(0);   // BK_FILL0
+}
+
+// restriction (rows = coarse nodes, row mask M_c) and prolongation + correction (rows =
+// fine nodes, row mask M_f, column mask M_c) of every problem with the sliced transfers
+template <int B, int NR, class X, class T, int KIND>
+__global__ __launch_bounds__(kThreads) void k_btsell(const BEntry* __restrict__ E, int ne,
+                                                     const int* __restrict__ active) {
+  __shared__ int se;
+  if (threadIdx.x == 0) se = find_entry(E, ne, blockIdx.x);
+  __syncthreads();
+  const BEntry& e = E[se];
+  if (active && !active[e.prob]) return;
+  const int slice = (blockIdx.x - e.first) * kSliceWaves + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const X* in = static_cast<const X*>(e.in0);
+  X* out = static_cast<X*>(e.out);
   if (KIND == BK_RESTRICT) {
-    if (t < int64_t(e.T.nrows) * B * NR)
-      restrict_dof<B, NR, X, T>(e.T, static_cast<const X*>(e.in0), static_cast<X*>(e.out), e.mask_c, nullptr, t);
-  } else if (KIND == BK_PROLONG) {
-    if (t < int64_t(e.T.nrows) * B * NR)
-      prolong_dof<B, NR, X, T>(e.T, static_cast<const X*>(e.in0), static_cast<X*>(e.out), e.mask, e.mask_c, t);
-  } else {                                 // BK_FILL0
-    if (t < int64_t(e.A.n) * B * NR) static_cast<X*>(e.out)[t] = X(0);
+    if (e.Ts.f32) tsell_lane<B, NR, X, T, float, false, 0>(e.Ts, slice, lane, in, out, e.mask_c, nullptr);
+    else tsell_lane<B, NR, X, T, double, false, 0>(e.Ts, slice, lane, in, out, e.mask_c, nullptr);
+  } else {
+    if (e.Ts.f32) tsell_lane<B, NR, X, T, float, true, 1>(e.Ts, slice, lane, in, out, e.mask, e.mask_c);
+    else tsell_lane<B, NR, X, T, double, true, 1>(e.Ts, slice, lane, in, out, e.mask, e.mask_c);
   }
 }
 
@@ -1352,8 +1526,8 @@ hipError_t batched_t(int kind, const BEntry* E, int ne, int nb, double omega, co
     case BK_SWEEP0: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_SWEEP0>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
     case BK_SWEEP: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_SWEEP>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
     case BK_DEFECT: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_DEFECT>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
-    case BK_RESTRICT: hipLaunchKernelGGL((k_belem<B, NR, X, T, BK_RESTRICT>), nb, kThreads, 0, s, E, ne, active); break;
-    case BK_PROLONG: hipLaunchKernelGGL((k_belem<B, NR, X, T, BK_PROLONG>), nb, kThreads, 0, s, E, ne, active); break;
+    case BK_RESTRICT: hipLaunchKernelGGL((k_btsell<B, NR, X, T, BK_RESTRICT>), nb, kThreads, 0, s, E, ne, active); break;
+    case BK_PROLONG: hipLaunchKernelGGL((k_btsell<B, NR, X, T, BK_PROLONG>), nb, kThreads, 0, s, E, ne, active); break;
     case BK_FILL0: hipLaunchKernelGGL((k_belem<B, NR, X, T, BK_FILL0>), nb, kThreads, 0, s, E, ne, active); break;
     case BK_COARSE: hipLaunchKernelGGL((k_bcoarse<NR, X>), nb, kThreads, 0, s, E, ne, active); break;
     case BK_SPMV64: hipLaunchKernelGGL((k_bsell64<B, NR, X, BK_SPMV64>), nb, kThreads, 0, s, E, ne, active, partials); break;
@@ -1380,12 +1554,12 @@ hipError_t batched_bn(int kind, const BEntry* E, int ne, int nb, int vkind, int 
 
 }  // namespace
 
-int batched_blocks(int kind, const SellDev& A, const CsrDev& T, int n0, int NR) {
+int batched_blocks(int kind, const SellDev& A, const TSellDev& Ts, int n0, int NR) {
   switch (kind) {
     case BK_SWEEP0: case BK_SWEEP: case BK_DEFECT: case BK_SPMV64: case BK_DEFECT64:
       return int(slice_grid(A.nslices));
     case BK_RESTRICT: case BK_PROLONG:
-      return int(grid_for(int64_t(T.nrows) * A.B * NR, kThreads));
+      return int(slice_grid(Ts.nslices));
     case BK_FILL0:
       return int(grid_for(int64_t(A.n) * A.B * NR, kThreads));
     case BK_COARSE:

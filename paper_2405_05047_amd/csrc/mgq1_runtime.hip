@@ -234,6 +234,51 @@ struct CsrHost {
   std::vector<double> val;
 };
 
+// sliced ELL of a scalar transfer matrix for block size B and NR right-hand sides: slices
+// of R = 64 / (B * NR) node rows, slice width = longest row, padded slots weight 0 and a
+// column of their own row
+struct TSellHost {
+  int32_t nrows = 0, ncols = 0, R = 64, nslices = 0;
+  std::vector<int32_t> sptr, col;
+  std::vector<double> w;
+};
+
+TSellHost build_tsell(const CsrHost& C, int B, int NR) {
+  TSellHost S;
+  S.nrows = C.nrows;
+  S.ncols = C.ncols;
+  S.R = kWave / (B * NR);
+  S.nslices = (C.nrows + S.R - 1) / S.R;
+  S.sptr.assign(size_t(S.nslices) + 1, 0);
+  for (int32_t sl = 0; sl < S.nslices; ++sl) {
+    int32_t wd = 0;
+    for (int r = 0; r < S.R; ++r) {
+      const int64_t i = int64_t(sl) * S.R + r;
+      if (i < C.nrows) wd = std::max(wd, C.rowptr[i + 1] - C.rowptr[i]);
+    }
+    S.sptr[sl + 1] = S.sptr[sl] + wd;
+  }
+  const int64_t slots = S.sptr[S.nslices];
+  S.col.assign(size_t(slots) * S.R, 0);
+  S.w.assign(size_t(slots) * S.R, 0.0);
+  for (int32_t sl = 0; sl < S.nslices; ++sl)
+    for (int r = 0; r < S.R; ++r) {
+      const int64_t i = int64_t(sl) * S.R + r;
+      if (i >= C.nrows) continue;
+      const int32_t b0 = C.rowptr[i], len = C.rowptr[i + 1] - b0;
+      for (int32_t k = 0; k < S.sptr[sl + 1] - S.sptr[sl]; ++k) {
+        const int64_t slot = int64_t(S.sptr[sl]) + k;
+        if (k < len) {
+          S.col[slot * S.R + r] = C.col[b0 + k];
+          S.w[slot * S.R + r] = C.val[b0 + k];
+        } else {
+          S.col[slot * S.R + r] = len > 0 ? C.col[b0 + len - 1] : 0;
+        }
+      }
+    }
+  return S;
+}
+
 CsrHost transpose(int32_t nrows, int32_t ncols, const std::vector<int32_t>& rp, const std::vector<int32_t>& ci,
                   const std::vector<double>& v) {
   CsrHost T;
@@ -276,6 +321,7 @@ struct LevelDev {
   void* S = nullptr;      // smoother blocks, lane layout, cycle precision
   uint8_t* mask = nullptr;
   CsrDev P, R;            // from level l-1 (l >= 1)
+  TSellDev Ps, Rs;        // the same transfers, sliced (grid kernels)
   void *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;   // cycle vectors
   double us_def = 0.0, us_alt = 0.0;  // measured sweep time of the two slot batches (tuning)
 };
@@ -300,6 +346,7 @@ struct mg_handle : DevOwner {
   double* pbig = nullptr; // per-block partials of the outer defect norm
   double* pv[2] = {nullptr, nullptr};   // per-block partials of the vector reductions
   int* dflag = nullptr;
+  bool fuse2z = true;     // fused first two pre-sweeps for block size 1 (MGQ1_NO_FUSE=1: off)
   double* hs = nullptr;   // pinned host scalars
   double* hst = nullptr;  // pinned, device-mapped: Givens output of step j at [2j], [2j+1]
   double* hst_dev = nullptr;             // the same memory as the kernels address it
@@ -415,6 +462,35 @@ int upload_csr(DevOwner* h, const CsrHost& C, CsrDev& D, hipStream_t s) {
   return MG_OK;
 }
 
+int upload_tsell(DevOwner* h, const TSellHost& T, TSellDev& D, hipStream_t s) {
+  D.nrows = T.nrows;
+  D.ncols = T.ncols;
+  D.R = T.R;
+  D.nslices = T.nslices;
+  bool exact = true;
+  for (double w : T.w) exact = exact && (double(float(w)) == w);
+  D.f32 = exact;
+  int rc;
+  int32_t *sp, *cl;
+  if ((rc = upload(h, &sp, T.sptr, s))) return rc;
+  if ((rc = upload(h, &cl, T.col, s))) return rc;
+  D.sptr = sp;
+  D.col = cl;
+  if (exact) {
+    std::vector<float> f(T.w.begin(), T.w.end());
+    float* v;
+    if ((rc = upload(h, &v, f, s))) return rc;
+    MG_HIP(hipStreamSynchronize(s));
+    D.w = v;
+  } else {
+    double* v;
+    if ((rc = upload(h, &v, T.w, s))) return rc;
+    MG_HIP(hipStreamSynchronize(s));
+    D.w = v;
+  }
+  return MG_OK;
+}
+
 // ---------------------------------------------------------------- V-cycle
 int smooth_level(mg_handle* h, int l, const void* b, void*& cur, void*& other, int sweeps, hipStream_t s) {
   LevelDev& L = h->lv[l];
@@ -447,7 +523,14 @@ int vcycle_cycle(mg_handle* h, const void* bL, void* xL, hipStream_t s) {
   for (int l = L; l > top; --l) {
     LevelDev& Lv = h->lv[l];
     first_buffers(l, pre_pp + c.nu2);
-    if (c.nu1 >= 1) {
+    if (c.nu1 >= 2 && Lv.B == 1 && h->fuse2z) {
+      // the first two sweeps from 0 in one pass; leaves the iterate where the second
+      // separate sweep would have left it
+      MG_HIP(launch_sweep2z(Lv.Ac, Lv.S, bb[l], oth[l], c.omega, h->xk, s));
+      std::swap(cur[l], oth[l]);
+      int rc = smooth_level(h, l, bb[l], cur[l], oth[l], c.nu1 - 2, s);
+      if (rc) return rc;
+    } else if (c.nu1 >= 1) {
       MG_HIP(launch_sweep0(Lv.Ac, Lv.S, bb[l], cur[l], c.omega, h->xk, s));
       int rc = smooth_level(h, l, bb[l], cur[l], oth[l], c.nu1 - 1, s);
       if (rc) return rc;
@@ -455,7 +538,7 @@ int vcycle_cycle(mg_handle* h, const void* bL, void* xL, hipStream_t s) {
       MG_HIP(launch_fill(Lv.N, cur[l], h->xk, 0.0, s));
     }
     MG_HIP(launch_spmv(Lv.Ac, bb[l], cur[l], Lv.r, Lv.mask, h->xk, h->xk, 2, nullptr, s));
-    MG_HIP(launch_restrict(Lv.R, Lv.B, Lv.r, h->lv[l - 1].b, h->lv[l - 1].mask, nullptr, h->xk, s));
+    MG_HIP(launch_restrict_s(Lv.Rs, Lv.B, Lv.r, h->lv[l - 1].b, h->lv[l - 1].mask, nullptr, h->xk, s));
   }
   if (top == 0) {
     // coarse solve with grid-wide kernels: one wavefront per row of the dense inverse
@@ -493,7 +576,7 @@ int vcycle_cycle(mg_handle* h, const void* bL, void* xL, hipStream_t s) {
   for (int l = top + 1; l <= L; ++l) {
     LevelDev& Lv = h->lv[l];
     const void* y = (l - 1 == top) ? h->lv[top].x : cur[l - 1];
-    MG_HIP(launch_prolong(Lv.P, Lv.B, y, cur[l], Lv.mask, h->lv[l - 1].mask, h->xk, s));
+    MG_HIP(launch_prolong_s(Lv.Ps, Lv.B, y, cur[l], Lv.mask, h->lv[l - 1].mask, h->xk, s));
     int rc = smooth_level(h, l, bb[l], cur[l], oth[l], c.nu2, s);
     if (rc) return rc;
   }
@@ -732,6 +815,8 @@ int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, 
     if ((rc = upload_csr(h, P, D.P, s))) return rc;
     CsrHost R = transpose(L.n, L.pc, L.prow, L.pcol, L.pval);
     if ((rc = upload_csr(h, R, D.R, s))) return rc;
+    if ((rc = upload_tsell(h, build_tsell(P, L.B, NR), D.Ps, s))) return rc;
+    if ((rc = upload_tsell(h, build_tsell(R, L.B, NR), D.Rs, s))) return rc;
   }
   if (vectors) {
     const size_t vb = size_t(D.N) * NR * xsize(xk);
@@ -900,6 +985,7 @@ int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
   for (int q = 0; q < 2; ++q)
     if ((rc = dalloc(h, &h->pv[q], size_t(kMaxRedBlocks)))) return rc;
   if ((rc = tune_levels(h, s))) return rc;
+  if (const char* e = std::getenv("MGQ1_NO_FUSE")) h->fuse2z = std::atoi(e) == 0;
   // tail: every level up to the largest one with at most tail_dofs unknowns.  Default off:
   // on MI355X one workgroup walking several levels was measured slower (dependent-load
   // latency serialises) than separate grid launches per step.
@@ -997,7 +1083,7 @@ BLaunch add_launch(mg_batch* h, int kind, std::vector<BEntry>& es) {
   int first = 0;
   for (BEntry& e : es) {
     e.first = first;
-    first += batched_blocks(kind, e.A, e.T, e.n0, h->NR);
+    first += batched_blocks(kind, e.A, e.Ts, e.n0, h->NR);
     h->hE.push_back(e);
   }
   L.ne = int(es.size());
@@ -1100,7 +1186,7 @@ void build_plan(mg_batch* h, int j, std::vector<BLaunch>& out) {
     for (int p : ps) {
       const int l = h->pr[p].L - d;
       BEntry e = level_entry(p, l);
-      e.T = h->pr[p].lv[l].R;
+      e.Ts = h->pr[p].lv[l].Rs;
       e.mask_c = h->pr[p].lv[l - 1].mask;
       e.in0 = rr[p][l];
       e.out = bb[p][l - 1];
@@ -1133,7 +1219,7 @@ void build_plan(mg_batch* h, int j, std::vector<BLaunch>& out) {
     for (int p : ps) {
       const int l = h->pr[p].L - d;
       BEntry e = level_entry(p, l);
-      e.T = h->pr[p].lv[l].P;
+      e.Ts = h->pr[p].lv[l].Ps;
       e.mask_c = h->pr[p].lv[l - 1].mask;
       e.in0 = own[p][l - 1];
       e.out = cur[p][l];
@@ -1575,7 +1661,7 @@ int mg_level_restrict(mg_handle* h, int32_t level, const double* r_fine, double*
   if (rc) return rc;
   if (level < 1) return fail(MG_EINVAL, "restriction needs level >= 1");
   LevelDev& L = h->lv[level];
-  MG_HIP(launch_restrict(L.R, L.B, r_fine, d_coarse, h->lv[level - 1].mask, L.mask, X_F64,
+  MG_HIP(launch_restrict_s(L.Rs, L.B, r_fine, d_coarse, h->lv[level - 1].mask, L.mask, X_F64,
                          static_cast<hipStream_t>(stream)));
   return MG_OK;
 }
@@ -1585,7 +1671,7 @@ int mg_level_prolong(mg_handle* h, int32_t level, const double* y_coarse, double
   if (rc) return rc;
   if (level < 1) return fail(MG_EINVAL, "prolongation needs level >= 1");
   LevelDev& L = h->lv[level];
-  MG_HIP(launch_prolong(L.P, L.B, y_coarse, x_fine, L.mask, h->lv[level - 1].mask, X_F64,
+  MG_HIP(launch_prolong_s(L.Ps, L.B, y_coarse, x_fine, L.mask, h->lv[level - 1].mask, X_F64,
                         static_cast<hipStream_t>(stream)));
   return MG_OK;
 }

@@ -195,3 +195,54 @@ def test_batch_maxit_per_instance():
     assert rc == -5
     for s in st:
         assert s["iters"] == 3 and s["converged"] == 0
+
+
+def test_batch_of_one_problem_and_single_level_member():
+    """Degenerate batches: one problem alone, and a batch whose member has a single level
+    (the V-cycle is the exact coarse solve, so FGMRES needs one cycle)."""
+    import scipy.sparse.linalg as sla
+    from paper_2405_05047_amd import gen, mg
+    wls = [W.c2_td(band_rounds=1, uniform_rounds=1),
+           W.c2_td(band_rounds=1, uniform_rounds=0).with_(coarse_level=5)]
+    ors = [Hh.build(wl) for wl in wls]
+    assert len(ors[1].levels) == 1
+    gps = [gen.build(wl) for wl in wls]
+    for members in ([0], [0, 1], [1]):
+        cfg = mg.config_from(wls[members[0]])
+        bt = mg.Batch([gps[k].levels for k in members], cfg, nrhs=1)
+        b = np.concatenate([ors[k].b for k in members])
+        bd = torch.from_numpy(b).cuda()
+        x = torch.zeros_like(bd)
+        rc, st = bt.solve(bd, x)
+        assert rc == 0
+        xs = x.cpu().numpy()
+        for i, k in enumerate(members):
+            seg = xs[bt.offsets[i]:bt.offsets[i + 1]]
+            ref, sr = MG.Multigrid(ors[k]).solve(ors[k].b)
+            assert st[i]["iters"] == sr.iters
+            assert np.linalg.norm(seg - ref) <= 1e-10 * np.linalg.norm(ref)
+            if k == 1:
+                assert st[i]["iters"] == 1
+                exact = sla.spsolve(ors[k].finest.A.tocsc(), ors[k].b)
+                assert np.linalg.norm(seg - exact) <= 1e-10 * np.linalg.norm(exact)
+
+
+def test_batch_zero_rhs_instances():
+    """Instances with b = 0 are converged at x = 0 before any cycle; the others iterate."""
+    wls, ors, gps, b, nrhs = _group("td_nrhs8")
+    refs = _oracle_solutions("td_nrhs8")
+    bt = _batch("td_nrhs8")
+    b0 = b.copy()
+    seg = b0[bt.offsets[2]:bt.offsets[3]].reshape(ors[2].finest.ndof, nrhs)
+    seg[:, 5] = 0.0
+    bd = torch.from_numpy(b0).cuda()
+    x = torch.zeros_like(bd)
+    rc, st = bt.solve(bd, x)
+    assert rc == 0
+    z = 2 * nrhs + 5
+    assert st[z]["iters"] == 0 and st[z]["converged"] == 1
+    got = _instances(bt, x.cpu().numpy(), ors, nrhs)
+    assert np.all(got[z] == 0.0)
+    for i, ((ref, sr), g) in enumerate(zip(refs, got)):
+        if i != z:
+            assert st[i]["iters"] == sr.iters, i

@@ -284,3 +284,36 @@ def test_slot_batch_rejects_unbuilt_size():
     wl, o, mgo, p, h64 = _pair("td_band")
     with pytest.raises(mg.MGError):
         mg.Hierarchy(p.levels, mg.config_from(wl, slot_batch=5))
+
+
+@pytest.mark.parametrize("name", ["poisson33", "td_band", "td_band_cl3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16"])
+def test_fused_presmoothing_bitwise_equal(name, prec, monkeypatch):
+    """For one component per node the first two pre-sweeps run as one pass that forms
+    x1 = omega S b on the fly; it gives bitwise the V-cycle of the two separate sweeps."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    outs = []
+    for off in ("0", "1"):
+        monkeypatch.setenv("MGQ1_NO_FUSE", off)
+        h = mg.Hierarchy(p.levels, mg.config_from(wl, precision=prec))
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        h.vcycle(dev(o.b), x)
+        outs.append(host(x))
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("name", ["td_band", "elast17"])
+def test_zero_rhs_and_exact_initial_guess(name):
+    """b = 0 is solved by x = 0 without a cycle; an initial guess that already satisfies the
+    tolerance is returned unchanged."""
+    import scipy.sparse.linalg as sla
+    wl, o, mgo, p, h = _pair(name)
+    z = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(z)
+    st = h.solve(z, x)
+    assert st["iters"] == 0 and st["converged"] == 1 and np.all(host(x) == 0.0)
+    xe = sla.spsolve(o.finest.A.tocsc(), o.b)
+    x = dev(xe)
+    st = h.solve(dev(o.b), x)
+    assert st["iters"] == 0 and st["converged"] == 1 and np.array_equal(host(x), xe)
