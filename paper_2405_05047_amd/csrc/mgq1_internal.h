@@ -178,8 +178,9 @@ struct BEntry {
 // blocks of an entry for a launch kind
 int batched_blocks(int kind, const SellDev& A, const TSellDev& Ts, int n0, int NR);
 // one batched step; `active[prob] == 0` skips a problem; `partials` for BK_DEFECT64
+// kb: slot batch of the slice kernels (sweep, defect, SpMV64, defect64); 0 = default
 hipError_t launch_batched(int kind, const BEntry* entries, int n_entries, int n_blocks, int B, int NR, int vkind,
-                          int xk, double omega, const int* active, double* partials, hipStream_t s);
+                          int xk, double omega, const int* active, double* partials, int kb, hipStream_t s);
 
 // vector segments of the concatenated batch vectors: problem p owns elements
 // [off[p], off[p] + len[p]) and vector blocks [vfirst[p], vfirst[p] + vcount[p])

@@ -1213,7 +1213,7 @@ __device__ __forceinline__ int find_entry(const BEntry* __restrict__ E, int n, i
 }
 
 // V-cycle steps on slices (sweep0, sweep, masked defect) for every problem of the batch
-template <int B, int NR, int K, class X, class T, int KIND>
+template <int B, int NR, int K, class X, class T, int KIND, int KB>
 __global__ __launch_bounds__(kThreads) void k_bsell(const BEntry* __restrict__ E, int ne, T omega,
                                                     const int* __restrict__ active) {
   __shared__ int se;
@@ -1227,16 +1227,16 @@ __global__ __launch_bounds__(kThreads) void k_bsell(const BEntry* __restrict__ E
     sweep0_slice<B, NR, X, T>(static_cast<const X*>(e.S), static_cast<const X*>(e.in0), static_cast<X*>(e.out),
                               omega, s);
   else if (KIND == BK_SWEEP)
-    sweep_slice<B, NR, K, X, T>(e.A, static_cast<const X*>(e.S), static_cast<const X*>(e.in0),
-                                static_cast<const X*>(e.in1), static_cast<X*>(e.out), omega, s);
+    sweep_slice<B, NR, K, X, T, KB>(e.A, static_cast<const X*>(e.S), static_cast<const X*>(e.in0),
+                                    static_cast<const X*>(e.in1), static_cast<X*>(e.out), omega, s);
   else
-    spmv_slice<B, NR, K, X, X, T, 2>(e.A, static_cast<const X*>(e.in0), static_cast<const X*>(e.in1),
-                                     static_cast<X*>(e.out), e.mask, s);
+    spmv_slice<B, NR, K, X, X, T, 2, KB>(e.A, static_cast<const X*>(e.in0), static_cast<const X*>(e.in1),
+                                         static_cast<X*>(e.out), e.mask, s);
 }
 
 // outer-loop products with the FP64 operator: w = A z (KIND SPMV64) or r = b - A x with
 // partial sums of squares per (block, rhs) (KIND DEFECT64)
-template <int B, int NR, class XI, int KIND>
+template <int B, int NR, class XI, int KIND, int KB>
 __global__ __launch_bounds__(kThreads) void k_bsell64(const BEntry* __restrict__ E, int ne,
                                                       const int* __restrict__ active, double* __restrict__ partials) {
   __shared__ int se;
@@ -1250,12 +1250,12 @@ __global__ __launch_bounds__(kThreads) void k_bsell64(const BEntry* __restrict__
     const SliceLane s = slice_lane<B, NR>(e.A, (blockIdx.x - e.first) * kSliceWaves + threadIdx.x / kWave,
                                           threadIdx.x % kWave);
     if (KIND == BK_SPMV64)
-      out = spmv_slice<B, NR, VK_F64, XI, double, double, 0>(e.A, nullptr, static_cast<const XI*>(e.in1),
-                                                             static_cast<double*>(e.out), nullptr, s);
-    else
-      out = spmv_slice<B, NR, VK_F64, double, double, double, 1>(e.A, static_cast<const double*>(e.in0),
-                                                                 static_cast<const double*>(e.in1),
+      out = spmv_slice<B, NR, VK_F64, XI, double, double, 0, KB>(e.A, nullptr, static_cast<const XI*>(e.in1),
                                                                  static_cast<double*>(e.out), nullptr, s);
+    else
+      out = spmv_slice<B, NR, VK_F64, double, double, double, 1, KB>(e.A, static_cast<const double*>(e.in0),
+                                                                     static_cast<const double*>(e.in1),
+                                                                     static_cast<double*>(e.out), nullptr, s);
   }
   if (KIND == BK_DEFECT64) {
     lds[threadIdx.x] = out * out;         // lane % NR is the right-hand side
@@ -1519,19 +1519,31 @@ __global__ void k_bclose(int j, int n_inst, int* kk, const int* iact) {
   if (inst < n_inst && iact[inst] && kk[inst] == 0) kk[inst] = j + 1;
 }
 
+template <int B, int NR, int K, class X, class T, int KB>
+hipError_t batched_sell(int kind, const BEntry* E, int ne, int nb, double omega, const int* active,
+                        double* partials, hipStream_t s) {
+  switch (kind) {
+    case BK_SWEEP: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_SWEEP, KB>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
+    case BK_DEFECT: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_DEFECT, KB>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
+    case BK_SPMV64: hipLaunchKernelGGL((k_bsell64<B, NR, X, BK_SPMV64, KB>), nb, kThreads, 0, s, E, ne, active, partials); break;
+    case BK_DEFECT64: hipLaunchKernelGGL((k_bsell64<B, NR, double, BK_DEFECT64, KB>), nb, kThreads, 0, s, E, ne, active, partials); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int B, int NR, int K, class X, class T>
 hipError_t batched_t(int kind, const BEntry* E, int ne, int nb, double omega, const int* active, double* partials,
-                     hipStream_t s) {
+                     int kb, hipStream_t s) {
   switch (kind) {
-    case BK_SWEEP0: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_SWEEP0>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
-    case BK_SWEEP: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_SWEEP>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
-    case BK_DEFECT: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_DEFECT>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
+    case BK_SWEEP: case BK_DEFECT: case BK_SPMV64: case BK_DEFECT64:
+      if (kb == kb_alt<B>()) return batched_sell<B, NR, K, X, T, kb_alt<B>()>(kind, E, ne, nb, omega, active, partials, s);
+      return batched_sell<B, NR, K, X, T, kb_default<B>()>(kind, E, ne, nb, omega, active, partials, s);
+    case BK_SWEEP0: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_SWEEP0, kb_default<B>()>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
     case BK_RESTRICT: hipLaunchKernelGGL((k_btsell<B, NR, X, T, BK_RESTRICT>), nb, kThreads, 0, s, E, ne, active); break;
     case BK_PROLONG: hipLaunchKernelGGL((k_btsell<B, NR, X, T, BK_PROLONG>), nb, kThreads, 0, s, E, ne, active); break;
     case BK_FILL0: hipLaunchKernelGGL((k_belem<B, NR, X, T, BK_FILL0>), nb, kThreads, 0, s, E, ne, active); break;
     case BK_COARSE: hipLaunchKernelGGL((k_bcoarse<NR, X>), nb, kThreads, 0, s, E, ne, active); break;
-    case BK_SPMV64: hipLaunchKernelGGL((k_bsell64<B, NR, X, BK_SPMV64>), nb, kThreads, 0, s, E, ne, active, partials); break;
-    case BK_DEFECT64: hipLaunchKernelGGL((k_bsell64<B, NR, double, BK_DEFECT64>), nb, kThreads, 0, s, E, ne, active, partials); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1539,15 +1551,15 @@ hipError_t batched_t(int kind, const BEntry* E, int ne, int nb, double omega, co
 
 template <int B, int NR>
 hipError_t batched_bn(int kind, const BEntry* E, int ne, int nb, int vkind, int xk, double omega, const int* active,
-                      double* partials, hipStream_t s) {
+                      double* partials, int kb, hipStream_t s) {
   if (xk == X_F64) {
     if (vkind != VK_F64) return hipErrorInvalidValue;
-    return batched_t<B, NR, VK_F64, double, double>(kind, E, ne, nb, omega, active, partials, s);
+    return batched_t<B, NR, VK_F64, double, double>(kind, E, ne, nb, omega, active, partials, kb, s);
   }
   switch (vkind) {
-    case VK_F32: return batched_t<B, NR, VK_F32, float, float>(kind, E, ne, nb, omega, active, partials, s);
-    case VK_F16: return batched_t<B, NR, VK_F16, float, float>(kind, E, ne, nb, omega, active, partials, s);
-    case VK_BF16: return batched_t<B, NR, VK_BF16, float, float>(kind, E, ne, nb, omega, active, partials, s);
+    case VK_F32: return batched_t<B, NR, VK_F32, float, float>(kind, E, ne, nb, omega, active, partials, kb, s);
+    case VK_F16: return batched_t<B, NR, VK_F16, float, float>(kind, E, ne, nb, omega, active, partials, kb, s);
+    case VK_BF16: return batched_t<B, NR, VK_BF16, float, float>(kind, E, ne, nb, omega, active, partials, kb, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1570,19 +1582,19 @@ int batched_blocks(int kind, const SellDev& A, const TSellDev& Ts, int n0, int N
 }
 
 hipError_t launch_batched(int kind, const BEntry* E, int ne, int nb, int B, int NR, int vkind, int xk, double omega,
-                          const int* active, double* partials, hipStream_t s) {
+                          const int* active, double* partials, int kb, hipStream_t s) {
   if (nb == 0 || ne == 0) return hipSuccess;
   if (NR == 1) {
     switch (B) {
-      case 1: return batched_bn<1, 1>(kind, E, ne, nb, vkind, xk, omega, active, partials, s);
-      case 3: return batched_bn<3, 1>(kind, E, ne, nb, vkind, xk, omega, active, partials, s);
-      case 4: return batched_bn<4, 1>(kind, E, ne, nb, vkind, xk, omega, active, partials, s);
+      case 1: return batched_bn<1, 1>(kind, E, ne, nb, vkind, xk, omega, active, partials, kb, s);
+      case 3: return batched_bn<3, 1>(kind, E, ne, nb, vkind, xk, omega, active, partials, kb, s);
+      case 4: return batched_bn<4, 1>(kind, E, ne, nb, vkind, xk, omega, active, partials, kb, s);
       default: return hipErrorInvalidValue;
     }
   }
   if (NR == 8) {
     switch (B) {
-      case 1: return batched_bn<1, 8>(kind, E, ne, nb, vkind, xk, omega, active, partials, s);
+      case 1: return batched_bn<1, 8>(kind, E, ne, nb, vkind, xk, omega, active, partials, kb, s);
       default: return hipErrorInvalidValue;
     }
   }

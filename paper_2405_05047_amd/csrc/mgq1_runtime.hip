@@ -1030,6 +1030,8 @@ struct BLaunch {
   int kind = 0;
   size_t e0 = 0;     // first entry in the batch's entry table
   int ne = 0, nb = 0;
+  int depth = -1;    // levels below each problem's finest level (-1: outer-loop launch)
+  int kb = 0;        // slot batch of the slice kernels (0: default)
 };
 
 struct mg_batch : DevOwner {
@@ -1062,6 +1064,7 @@ struct mg_batch : DevOwner {
   std::vector<std::vector<BLaunch>> plan;   // per Krylov index: V-cycle launches
   std::vector<BLaunch> spmv64;        // per Krylov index: w = A z_j
   int nbig = 0;                       // blocks of the outer FP64 products
+  int kb64 = 0;                       // slot batch of the outer FP64 products
   hipStream_t cap = nullptr;
   std::vector<hipGraphExec_t> graphs;
   int* hkk = nullptr;                 // pinned host copy of kk (read after every step)
@@ -1076,9 +1079,10 @@ struct mg_batch : DevOwner {
 namespace {
 
 // append one launch (entries already filled except `first`) to the batch plan
-BLaunch add_launch(mg_batch* h, int kind, std::vector<BEntry>& es) {
+BLaunch add_launch(mg_batch* h, int kind, std::vector<BEntry>& es, int depth = -1) {
   BLaunch L;
   L.kind = kind;
+  L.depth = depth;
   L.e0 = h->hE.size();
   int first = 0;
   for (BEntry& e : es) {
@@ -1148,7 +1152,7 @@ void build_plan(mg_batch* h, int j, std::vector<BLaunch>& out) {
         e.out = cur[p][l];
         es.push_back(e);
       }
-      out.push_back(add_launch(h, BK_SWEEP0, es));
+      out.push_back(add_launch(h, BK_SWEEP0, es, d));
       for (int q = 1; q < c.nu1; ++q) {
         es.clear();
         for (int p : ps) {
@@ -1160,7 +1164,7 @@ void build_plan(mg_batch* h, int j, std::vector<BLaunch>& out) {
           es.push_back(e);
           std::swap(cur[p][l], oth[p][l]);
         }
-        out.push_back(add_launch(h, BK_SWEEP, es));
+        out.push_back(add_launch(h, BK_SWEEP, es, d));
       }
     } else {
       es.clear();
@@ -1170,7 +1174,7 @@ void build_plan(mg_batch* h, int j, std::vector<BLaunch>& out) {
         e.out = cur[p][l];
         es.push_back(e);
       }
-      out.push_back(add_launch(h, BK_FILL0, es));
+      out.push_back(add_launch(h, BK_FILL0, es, d));
     }
     es.clear();
     for (int p : ps) {
@@ -1181,7 +1185,7 @@ void build_plan(mg_batch* h, int j, std::vector<BLaunch>& out) {
       e.out = rr[p][l];
       es.push_back(e);
     }
-    out.push_back(add_launch(h, BK_DEFECT, es));
+    out.push_back(add_launch(h, BK_DEFECT, es, d));
     es.clear();
     for (int p : ps) {
       const int l = h->pr[p].L - d;
@@ -1192,7 +1196,7 @@ void build_plan(mg_batch* h, int j, std::vector<BLaunch>& out) {
       e.out = bb[p][l - 1];
       es.push_back(e);
     }
-    out.push_back(add_launch(h, BK_RESTRICT, es));
+    out.push_back(add_launch(h, BK_RESTRICT, es, d));
   }
   // coarse solves of all problems
   {
@@ -1225,7 +1229,7 @@ void build_plan(mg_batch* h, int j, std::vector<BLaunch>& out) {
       e.out = cur[p][l];
       es.push_back(e);
     }
-    out.push_back(add_launch(h, BK_PROLONG, es));
+    out.push_back(add_launch(h, BK_PROLONG, es, d));
     for (int q = 0; q < c.nu2; ++q) {
       es.clear();
       for (int p : ps) {
@@ -1237,15 +1241,85 @@ void build_plan(mg_batch* h, int j, std::vector<BLaunch>& out) {
         es.push_back(e);
         std::swap(cur[p][l], oth[p][l]);
       }
-      out.push_back(add_launch(h, BK_SWEEP, es));
+      out.push_back(add_launch(h, BK_SWEEP, es, d));
     }
   }
 }
 
 int run_launch(mg_batch* h, const BLaunch& L, const BEntry* table, const int* active, double* partials, hipStream_t s) {
   MG_HIP(launch_batched(L.kind, table + L.e0, L.ne, L.nb, h->B, h->NR, h->vkind, h->xk, h->cfg.omega, active,
-                        partials, s));
+                        partials, L.kb, s));
   return MG_OK;
+}
+
+// Slot-batch choice for the batch: per depth, both built sizes of that depth's sweep launch
+// are timed (3 interleaved repetitions of 5 launches, minimum kept) and the faster is used
+// by every sweep and defect launch of that depth; the outer FP64 products likewise with
+// the first SpMV launch.  Bitwise-neutral like the single-problem tuner.
+int tune_batch(mg_batch* h, hipStream_t s) {
+  int kb[2];
+  slot_batch_choices(h->B, &kb[0], &kb[1]);
+  const int req = h->cfg.slot_batch;
+  if (req != 0 && req != kb[0] && req != kb[1])
+    return fail(MG_EINVAL, "slot_batch must be 0 or one of the two batch sizes built for this block size");
+  auto apply = [&](auto&& pred, int v) {
+    for (auto& pl : h->plan)
+      for (BLaunch& L : pl)
+        if (pred(L)) L.kb = v;
+    for (BLaunch& L : h->spmv64)
+      if (pred(L)) L.kb = v;
+  };
+  auto level_kind = [](const BLaunch& L, int d) {
+    return L.depth == d && (L.kind == BK_SWEEP || L.kind == BK_DEFECT);
+  };
+  if (req != 0) {
+    for (int d = 0; d < h->Dmax; ++d) apply([&](const BLaunch& L) { return level_kind(L, d); }, req);
+    apply([](const BLaunch& L) { return L.kind == BK_SPMV64; }, req);
+    h->kb64 = req;
+    return MG_OK;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  MG_HIP(hipEventCreate(&e0));
+  MG_HIP(hipEventCreate(&e1));
+  int rc = MG_OK;
+  auto best_of = [&](BLaunch L, int* pick) -> int {
+    float best[2] = {1e30f, 1e30f};
+    for (int rep = 0; rep < 3; ++rep)
+      for (int v = 0; v < 2; ++v) {
+        L.kb = kb[v];
+        MG_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < 5; ++i) {
+          const int r = run_launch(h, L, h->dE, nullptr, nullptr, s);
+          if (r) return r;
+        }
+        MG_HIP(hipEventRecord(e1, s));
+        MG_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        MG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        best[v] = std::min(best[v], ms);
+      }
+    *pick = best[1] < best[0] ? kb[1] : kb[0];
+    return MG_OK;
+  };
+  for (int d = 0; d < h->Dmax && rc == MG_OK; ++d) {
+    const BLaunch* probe = nullptr;
+    for (const BLaunch& L : h->plan[0])
+      if (L.depth == d && L.kind == BK_SWEEP) { probe = &L; break; }
+    if (!probe) continue;
+    int pick = kb[0];
+    if ((rc = best_of(*probe, &pick))) break;
+    apply([&](const BLaunch& L) { return level_kind(L, d); }, pick);
+  }
+  if (rc == MG_OK && !h->spmv64.empty()) {
+    int pick = kb[0];
+    if ((rc = best_of(h->spmv64[0], &pick)) == MG_OK) {
+      apply([](const BLaunch& L) { return L.kind == BK_SPMV64; }, pick);
+      h->kb64 = pick;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 // one lockstep FGMRES step j for every instance
@@ -1301,6 +1375,7 @@ int batch_defect(mg_batch* h, hipStream_t s) {
   L.e0 = 0;
   L.ne = h->P;
   L.nb = h->nbig;
+  L.kb = h->kb64;
   int rc;
   if ((rc = run_launch(h, L, h->dEdef, h->pact, h->pbig, s))) return rc;
   MG_HIP(launch_bfinish(h->pbig, h->bigfirst, h->bigcount, h->n_inst, h->NR, h->beta, 1, s));
@@ -1415,6 +1490,8 @@ int setup_batch(mg_batch* h, const std::vector<std::vector<HostLevel>>& HH, hipS
     h->spmv64[j] = add_launch(h, BK_SPMV64, es);
   }
   if ((rc = upload(h, &h->dE, h->hE, s))) return rc;
+  MG_HIP(hipStreamSynchronize(s));
+  if ((rc = tune_batch(h, s))) return rc;
   MG_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hkk), sizeof(int) * ni, hipHostMallocDefault));
   h->graphs.assign(size_t(m), nullptr);
   if (c.use_graph) MG_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));

@@ -246,3 +246,20 @@ def test_batch_zero_rhs_instances():
     for i, ((ref, sr), g) in enumerate(zip(refs, got)):
         if i != z:
             assert st[i]["iters"] == sr.iters, i
+
+
+def test_batch_slot_batch_variants_bitwise_equal():
+    """The batch autotuner's choices change no bit of the result."""
+    from paper_2405_05047_amd import mg
+    wls, ors, gps, b, nrhs = _group("td_nrhs8")
+    bd = torch.from_numpy(b).cuda()
+    outs = []
+    for kb in (0, 8, 16):
+        cfg = mg.config_from(wls[0], precision="fp32", slot_batch=kb)
+        bt = mg.Batch([p.levels for p in gps], cfg, nrhs=nrhs)
+        x = torch.zeros_like(bd)
+        rc, st = bt.solve(bd, x)
+        assert rc == 0
+        outs.append((x.cpu().numpy(), [s["iters"] for s in st]))
+    for x, it in outs[1:]:
+        assert np.array_equal(x, outs[0][0]) and it == outs[0][1]
