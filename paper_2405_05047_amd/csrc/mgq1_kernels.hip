@@ -190,6 +190,9 @@ __device__ __forceinline__ T sell_dot(const SellDev& A, int slice, int lane, boo
   if (!valid) return acc;
   const int rl = lane / NR, q = lane % NR;
   const int r = rl / B;
+  // the slice is the same for the whole wave: keep it (and the slot range, the load bases)
+  // in scalar registers
+  slice = __builtin_amdgcn_readfirstlane(slice);
   const int k1 = A.sptr[slice + 1];
   int k = A.sptr[slice];
   for (; k + KB <= k1; k += KB) sell_batch<KB, B, NR, K>(A, k, r, rl, q, x, acc);
@@ -254,14 +257,20 @@ __device__ __forceinline__ SliceLane slice_lane(const SellDev& A, int slice, int
 template <int B, int NR, int K, class XI, class XO, class T, int MODE, int KB = kb_default<B>()>
 __device__ __forceinline__ T spmv_slice(const SellDev& A, const XO* __restrict__ b, const XI* __restrict__ x,
                                         XO* __restrict__ y, const uint8_t* __restrict__ mask, const SliceLane& s) {
+  XO bv = XO(0);
+  uint8_t mk = 0;
+  if (MODE != 0 && s.valid) {              // loaded before the row sum (latency overlap)
+    bv = b[s.dof];
+    if (MODE == 2) mk = mask[s.dof / NR];
+  }
   const T acc = sell_dot<B, NR, K, XI, T, KB>(A, s.slice, s.lane, s.valid, x);
   T out = T(0);
   if (s.valid) {
     if (MODE == 0) {
       out = acc;
     } else {
-      out = T(b[s.dof]) - acc;
-      if (MODE == 2 && mask[s.dof / NR]) out = T(0);
+      out = T(bv) - acc;
+      if (MODE == 2 && mk) out = T(0);
     }
     y[s.dof] = XO(out);
   }
@@ -273,17 +282,28 @@ __device__ __forceinline__ void sweep_slice(const SellDev& A, const X* __restric
                                             const X* __restrict__ x, X* __restrict__ xo, T omega,
                                             const SliceLane& s) {
   constexpr int W = kWave / NR;
-  const T acc = sell_dot<B, NR, K, X, T, KB>(A, s.slice, s.lane, s.valid, x);
-  const T res = s.valid ? T(b[s.dof]) - acc : T(0);
   const int rl = s.lane / NR, q = s.lane % NR;
+  // the lane's own b, x and smoother row are loaded before the row sum, so their latency
+  // overlaps the slot batches
+  X bv = X(0), xv = X(0), sv[B];
+#pragma unroll
+  for (int cc = 0; cc < B; ++cc) sv[cc] = X(0);
+  if (s.valid) {
+    bv = b[s.dof];
+    xv = x[s.dof];
+#pragma unroll
+    for (int cc = 0; cc < B; ++cc) sv[cc] = S[(int64_t(s.slice) * B + cc) * W + rl];
+  }
+  const T acc = sell_dot<B, NR, K, X, T, KB>(A, s.slice, s.lane, s.valid, x);
+  const T res = s.valid ? T(bv) - acc : T(0);
   const int base = (rl / B) * B;
   T upd = T(0);
 #pragma unroll
   for (int cc = 0; cc < B; ++cc) {
     const T rc = __shfl(res, ((base + cc) * NR + q) & (kWave - 1), kWave);
-    if (s.valid) upd += T(S[(int64_t(s.slice) * B + cc) * W + rl]) * rc;
+    if (s.valid) upd += T(sv[cc]) * rc;
   }
-  if (s.valid) xo[s.dof] = X(T(x[s.dof]) + omega * upd);
+  if (s.valid) xo[s.dof] = X(T(xv) + omega * upd);
 }
 
 template <int B, int NR, class X, class T>
@@ -390,8 +410,9 @@ __device__ __forceinline__ void tsell_lane(const TSellDev& M, int slice, int lan
   const int64_t dof = int64_t(node) * B + c;
   const int64_t t = dof * NR + q;
   const uint8_t masked = mrow[dof];        // issued together with the slice bounds
-  const int k1 = M.sptr[slice + 1];
-  int k = M.sptr[slice];
+  const int su = __builtin_amdgcn_readfirstlane(slice);
+  const int k1 = M.sptr[su + 1];
+  int k = M.sptr[su];
   if (masked) {
     if (MODE == 0) out[t] = X(0);
     return;
@@ -446,8 +467,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep2z(SellDev A, const X* __rest
   const int64_t i = int64_t(slice) * kWave + lane;
   if (slice >= A.nslices || i >= A.n) return;
   const X si = S[i], bi = b[i];              // issued with the slice bounds
-  const int k1 = A.sptr[slice + 1];
-  int k = A.sptr[slice];
+  const int su = __builtin_amdgcn_readfirstlane(slice);
+  const int k1 = A.sptr[su + 1];
+  int k = A.sptr[su];
   T acc = T(0);
   for (; k + KB <= k1; k += KB) sell_batch_z<KB, K, X, T>(A, k, lane, S, b, omega, acc);
   sell_rest_z<KB - 1, K, X, T>(k1 - k, A, k, lane, S, b, omega, acc);
