@@ -15,7 +15,7 @@ enum VecKind { X_F64 = 0, X_F32 = 1 };
 constexpr int kWave = 64;             // wavefront width on CDNA
 constexpr int kSliceWaves = 4;        // slices (one per wave) per 256-thread workgroup
 constexpr int kRedThreads = 256;
-constexpr int kMaxRedBlocks = 512;    // grid (= partial count) of the vector reductions
+constexpr int kMaxRedBlocks = 2048;   // grid (= partial count) of the vector reductions
 
 // Sliced ELL of a block matrix: one slice = 64 lanes = R = 64/B nodes x B components;
 // lane = r*B + c handles scalar row (node slice*R + r, component c).  For block slot k of
@@ -194,7 +194,7 @@ struct BSegs {
   int n_blocks = 0;
   int NR = 1;
 };
-constexpr int kSegBlocksMax = 256;   // vector blocks per problem (partials re-summed per block)
+constexpr int kSegBlocksMax = 1024;  // vector blocks per problem (partials re-summed per block)
 
 // partial sums per (vector block, rhs) of a.b (b == NULL: a.a)
 hipError_t launch_bdot(const BSegs& g, const double* a, const double* b, double* partials, hipStream_t s);

@@ -228,8 +228,18 @@ __device__ __forceinline__ double block_allsum(double v, double* lds) {
 
 // sum of partials[0..g) in a fixed order (every block computes the same value)
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int g, double* lds) {
+  constexpr int U = 8;                     // loads issued together, summed in index order
   double t = 0.0;
-  for (int q = threadIdx.x; q < g; q += blockDim.x) t += p[q];
+  for (int q0 = threadIdx.x; q0 < g; q0 += blockDim.x * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + u * int(blockDim.x);
+      v[u] = q < g ? p[q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) t += v[u];
+  }
   return block_allsum(t, lds);
 }
 
@@ -729,10 +739,20 @@ __global__ void k_scale_div(int64_t n, double* __restrict__ y, const double* __r
 __global__ __launch_bounds__(kRedThreads) void k_dot_partials(int64_t n, const double* __restrict__ a,
                                                               const double* __restrict__ b, double* __restrict__ out) {
   __shared__ double lds[kMaxWaves + 1];
+  constexpr int U = 4;                     // elements per thread and round, loads first
   double t = 0.0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
-    t += a[i] * (b ? b[i] : a[i]);
+  for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < n; i0 += stride * U) {
+    double av[U], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      av[u] = i < n ? a[i] : 0.0;
+      bv[u] = (b && i < n) ? b[i] : av[u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) t += av[u] * bv[u];
+  }
   const double s = block_allsum(t, lds);
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
@@ -754,12 +774,26 @@ __global__ __launch_bounds__(kRedThreads) void k_mgs_step(int64_t n, double* __r
   __shared__ double lds[kMaxWaves + 1];
   const double h = sum_partials(pin, gin, lds);
   if (blockIdx.x == 0 && threadIdx.x == 0) *hout = h;
+  constexpr int U = 4;
   double t = 0.0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const double v = w[i] - h * vi[i];
-    w[i] = v;
-    t += v * (vnext ? vnext[i] : v);
+  for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < n; i0 += stride * U) {
+    double wv[U], vv[U], nv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      const bool ok = i < n;
+      wv[u] = ok ? w[i] : 0.0;
+      vv[u] = ok ? vi[i] : 0.0;
+      nv[u] = (ok && vnext) ? vnext[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      const double v = wv[u] - h * vv[u];
+      if (i < n) w[i] = v;
+      t += v * (vnext ? nv[u] : v);
+    }
   }
   const double s = block_allsum(t, lds);
   if (threadIdx.x == 0) pout[blockIdx.x] = s;
@@ -773,8 +807,21 @@ __global__ __launch_bounds__(kRedThreads) void k_mgs_normalize(int64_t n, double
   const double nrm = sqrt(sum_partials(pin, gin, lds));
   if (blockIdx.x == 0 && threadIdx.x == 0) *hout = nrm;
   if (nrm == 0.0) return;
+  constexpr int U = 4;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) w[i] = w[i] / nrm;
+  for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < n; i0 += stride * U) {
+    double wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      wv[u] = i < n ? w[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < n) w[i] = wv[u] / nrm;
+    }
+  }
 }
 
 template <class Z>
@@ -924,7 +971,7 @@ hipError_t tail_b(const TailLevel* lv, int kind, int xk, const TailParams& p, hi
 }
 
 inline unsigned vec_grid(int64_t n) {
-  unsigned g = grid_for(n, kRedThreads);
+  unsigned g = grid_for(n, int64_t(kRedThreads) * 4);   // 4 elements per thread and round
   if (g > unsigned(kMaxRedBlocks)) g = kMaxRedBlocks;
   return g ? g : 1;
 }
@@ -1367,11 +1414,15 @@ __device__ __forceinline__ SegPos seg_pos(const BSegs& g) {
 // fixed-order sum over the block of values that belong to rhs q = tid % NR; thread q of
 // the result gets the sum for q
 __device__ __forceinline__ double block_sum_rhs(double v, int NR, double* lds) {
-  lds[threadIdx.x] = v;
+  // inside each wave a fixed shuffle tree combines the lanes of equal lane % NR, then
+  // thread q adds the per-wave results in wave order
+  for (int o = kWave / 2; o >= NR; o >>= 1) v += __shfl_down(v, o, kWave);
+  const int wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
+  if (ln < NR) lds[wv * NR + ln] = v;
   __syncthreads();
   double t = 0.0;
   if (int(threadIdx.x) < NR)
-    for (int i = threadIdx.x; i < int(blockDim.x); i += NR) t += lds[i];
+    for (int k = 0; k < int(blockDim.x) / kWave; ++k) t += lds[k * NR + threadIdx.x];
   __syncthreads();
   return t;
 }
@@ -1379,9 +1430,20 @@ __device__ __forceinline__ double block_sum_rhs(double v, int NR, double* lds) {
 // every block of problem p computes the per-rhs sums of the problem's partials
 __device__ __forceinline__ void seg_sums(const double* __restrict__ pin, const SegPos& sp, int NR, double* lds,
                                          double* out) {
+  constexpr int U = 8;                     // partial loads issued together
   double t = 0.0;
   const int q = threadIdx.x % NR;
-  for (int b = threadIdx.x / NR; b < sp.nb; b += blockDim.x / NR) t += pin[int64_t(sp.first + b) * NR + q];
+  const int step = int(blockDim.x) / NR;
+  for (int b0 = threadIdx.x / NR; b0 < sp.nb; b0 += step * U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = b0 + u * step;
+      v[u] = b < sp.nb ? pin[int64_t(sp.first + b) * NR + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) t += v[u];
+  }
   const double r = block_sum_rhs(t, NR, lds);
   if (int(threadIdx.x) < NR) out[threadIdx.x] = r;
   __syncthreads();
@@ -1392,11 +1454,19 @@ __global__ __launch_bounds__(kThreads) void k_bdot(BSegs g, const double* __rest
   __shared__ double lds[kThreads];
   const SegPos sp = seg_pos(g);
   if (!sp.on) return;                      // uniform over the block
+  constexpr int U = 4;
   double t = 0.0;
   const int64_t stride = int64_t(sp.nb) * blockDim.x;
-  for (int64_t i = int64_t(sp.lb) * blockDim.x + threadIdx.x; i < sp.len; i += stride) {
-    const double av = a[sp.off + i];
-    t += av * (b ? b[sp.off + i] : av);
+  for (int64_t i0 = int64_t(sp.lb) * blockDim.x + threadIdx.x; i0 < sp.len; i0 += stride * U) {
+    double av[U], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      av[u] = i < sp.len ? a[sp.off + i] : 0.0;
+      bv[u] = (b && i < sp.len) ? b[sp.off + i] : av[u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) t += av[u] * bv[u];
   }
   const double r = block_sum_rhs(t, g.NR, lds);
   if (int(threadIdx.x) < g.NR) out[int64_t(blockIdx.x) * g.NR + threadIdx.x] = r;
@@ -1413,13 +1483,26 @@ __global__ __launch_bounds__(kThreads) void k_bmgs_step(BSegs g, double* __restr
   seg_sums(pin, sp, g.NR, lds, hq);
   if (sp.lb == 0 && int(threadIdx.x) < g.NR) H[int64_t(sp.p * g.NR + threadIdx.x) * hstride] = hq[threadIdx.x];
   const double h = hq[threadIdx.x % g.NR];
+  constexpr int U = 4;
   double t = 0.0;
   const int64_t stride = int64_t(sp.nb) * blockDim.x;
-  for (int64_t i = int64_t(sp.lb) * blockDim.x + threadIdx.x; i < sp.len; i += stride) {
-    const int64_t k = sp.off + i;
-    const double v = w[k] - h * vi[k];
-    w[k] = v;
-    t += v * (vnext ? vnext[k] : v);
+  for (int64_t i0 = int64_t(sp.lb) * blockDim.x + threadIdx.x; i0 < sp.len; i0 += stride * U) {
+    double wv[U], vv[U], nv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      const bool ok = i < sp.len;
+      wv[u] = ok ? w[sp.off + i] : 0.0;
+      vv[u] = ok ? vi[sp.off + i] : 0.0;
+      nv[u] = (ok && vnext) ? vnext[sp.off + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      const double v = wv[u] - h * vv[u];
+      if (i < sp.len) w[sp.off + i] = v;
+      t += v * (vnext ? nv[u] : v);
+    }
   }
   const double r = block_sum_rhs(t, g.NR, lds);
   if (int(threadIdx.x) < g.NR) pout[int64_t(blockIdx.x) * g.NR + threadIdx.x] = r;
@@ -1438,8 +1521,21 @@ __global__ __launch_bounds__(kThreads) void k_bmgs_normalize(BSegs g, double* __
   if (sp.lb == 0 && int(threadIdx.x) < g.NR) H[int64_t(sp.p * g.NR + threadIdx.x) * hstride] = hq[threadIdx.x];
   const double nrm = hq[threadIdx.x % g.NR];
   if (nrm == 0.0) return;
+  constexpr int U = 4;
   const int64_t stride = int64_t(sp.nb) * blockDim.x;
-  for (int64_t i = int64_t(sp.lb) * blockDim.x + threadIdx.x; i < sp.len; i += stride) w[sp.off + i] /= nrm;
+  for (int64_t i0 = int64_t(sp.lb) * blockDim.x + threadIdx.x; i0 < sp.len; i0 += stride * U) {
+    double wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      wv[u] = i < sp.len ? w[sp.off + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < sp.len) w[sp.off + i] = wv[u] / nrm;
+    }
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_bscale(BSegs g, double* __restrict__ y, const double* __restrict__ x,

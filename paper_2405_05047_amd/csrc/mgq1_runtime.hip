@@ -1435,7 +1435,7 @@ int setup_batch(mg_batch* h, const std::vector<std::vector<HostLevel>>& HH, hipS
   for (int p = 0; p < P; ++p) {
     len[p] = h->off[p + 1] - h->off[p];
     vfirst[p] = int(blk.size());
-    vcount[p] = int(std::min<int64_t>(kSegBlocksMax, std::max<int64_t>(1, (len[p] + 255) / 256)));
+    vcount[p] = int(std::min<int64_t>(kSegBlocksMax, std::max<int64_t>(1, (len[p] + 1023) / 1024)));
     for (int b = 0; b < vcount[p]; ++b) blk.push_back(p);
   }
   int64_t *doff, *dlen;
