@@ -502,8 +502,20 @@ __global__ __launch_bounds__(kThreads) void k_sweep0(SellDev A, const X* __restr
 template <class XI, class XO>
 __device__ __forceinline__ void gemv_row(int n, const double* __restrict__ Ainv, const XI* __restrict__ b,
                                          XO* __restrict__ x, int i, int lane) {
+  constexpr int U = 8;                     // row chunks whose loads are issued together
   double acc = 0.0;
-  for (int k = lane; k < n; k += kWave) acc += Ainv[int64_t(i) * n + k] * double(b[k]);
+  const double* row = Ainv + int64_t(i) * n;
+  for (int k0 = lane; k0 < n; k0 += kWave * U) {
+    double av[U], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * kWave;
+      av[u] = k < n ? row[k] : 0.0;
+      bv[u] = k < n ? double(b[k]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += av[u] * bv[u];
+  }
   acc = wave_sum(acc);
   if (lane == 0) x[i] = XO(acc);
 }
@@ -1385,8 +1397,20 @@ __global__ __launch_bounds__(kThreads) void k_bcoarse(const BEntry* __restrict__
   if (i >= e.n0) return;
   const int lane = threadIdx.x % kWave, q = lane % NR;
   const X* b = static_cast<const X*>(e.in0);
+  constexpr int U = 8;
   double acc = 0.0;
-  for (int k = lane / NR; k < e.n0; k += kWave / NR) acc += e.Ainv[int64_t(i) * e.n0 + k] * double(b[int64_t(k) * NR + q]);
+  const double* row = e.Ainv + int64_t(i) * e.n0;
+  for (int k0 = lane / NR; k0 < e.n0; k0 += (kWave / NR) * U) {
+    double av[U], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * (kWave / NR);
+      av[u] = k < e.n0 ? row[k] : 0.0;
+      bv[u] = k < e.n0 ? double(b[int64_t(k) * NR + q]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += av[u] * bv[u];
+  }
 #pragma unroll
   for (int o = kWave / 2; o >= NR; o >>= 1) acc += __shfl_down(acc, o, kWave);
   if (lane < NR) static_cast<X*>(e.out)[int64_t(i) * NR + lane] = X(acc);
