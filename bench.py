@@ -48,10 +48,11 @@ WORKLOADS = {
 }
 
 
-def sweep_bytes(n, b, nnzb):
-    """Algorithmic bytes of one FP64 smoothing sweep: A values + int32 column indices +
-    int32 row pointers, x and b read, x_out written, nodal b x b inverse blocks read."""
-    return nnzb * (b * b * 8 + 4) + 4 * (n + 1) + 3 * n * b * 8 + n * b * b * 8
+def sweep_bytes(n, b, nnzb, col_bytes=4):
+    """Algorithmic bytes of one FP64 smoothing sweep: A values + column indices (4 B, or 2 B
+    when the operator is stored with 16-bit column differences) + int32 row pointers, x
+    and b read, x_out written, nodal b x b inverse blocks read."""
+    return nnzb * (b * b * 8 + col_bytes) + 4 * (n + 1) + 3 * n * b * 8 + n * b * b * 8
 
 
 def time_solves(torch, h, b, x, steps, warmup):
@@ -291,7 +292,7 @@ def main():
     L = h64.n_levels - 1
     n, bs, nnzb = h64.sizes[L]
     ksec = kernel_time(torch, h64, L, n * bs)
-    kbytes = sweep_bytes(n, bs, nnzb)
+    kbytes = sweep_bytes(n, bs, nnzb, h64.col_bytes(L))
     achieved = kbytes / ksec / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(wl.name),

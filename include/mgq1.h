@@ -143,10 +143,13 @@ int mg_level_info(const mg_handle* h, int32_t level, int32_t* n_nodes, int32_t* 
                   int64_t* nnzb);
 int32_t mg_num_levels(const mg_handle* h);
 
-/* Slot batch used on level `level` and the sweep times (microseconds per launch) that the
- * setup measured for the default and the other size (0 when slot_batch was fixed). */
-int mg_level_tuning(const mg_handle* h, int32_t level, int32_t* slot_batch, double* us_default,
-                    double* us_other);
+/* Slot batch used on level `level`, the bytes per stored column index of its operators
+ * (2 when every column differs from its row's node by less than 2^15 and the kernels read
+ * 16-bit differences, else 4), and the sweep times (microseconds per launch) that the
+ * setup measured for the default and the other slot batch (0 when slot_batch was fixed).
+ * Any output pointer may be NULL. */
+int mg_level_tuning(const mg_handle* h, int32_t level, int32_t* slot_batch, int32_t* col_bytes,
+                    double* us_default, double* us_other);
 
 /* Host-only structural validation of one level (and its coarser neighbour for P~);
  * no device is touched.  Returns MG_OK or MG_EINVAL with a message. */

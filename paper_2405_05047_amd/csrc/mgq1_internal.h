@@ -31,6 +31,8 @@ struct SellDev {
   const int8_t* rexp = nullptr;     // nslices * 64 power-of-two row exponents (F16 / BF16)
   int kind = VK_F64;
   int kb = 0;                       // block slots per load batch (0: the default for B)
+  const int16_t* col16 = nullptr;   // col - (row node) as 16 bits when every difference
+                                    // fits (NULL: the kernels read col)
 };
 
 // the two slot-batch sizes the slice kernels are built for (default, alternative)
@@ -178,7 +180,8 @@ struct BEntry {
 // blocks of an entry for a launch kind
 int batched_blocks(int kind, const SellDev& A, const TSellDev& Ts, int n0, int NR);
 // one batched step; `active[prob] == 0` skips a problem; `partials` for BK_DEFECT64
-// kb: slot batch of the slice kernels (sweep, defect, SpMV64, defect64); 0 = default
+// kb: slot batch of the slice kernels (sweep, defect, SpMV64, defect64); 0 = default;
+// negative: -kb with the 16-bit column format (all entries of the launch must have it)
 hipError_t launch_batched(int kind, const BEntry* entries, int n_entries, int n_blocks, int B, int NR, int vkind,
                           int xk, double omega, const int* active, double* partials, int kb, hipStream_t s);
 

@@ -83,8 +83,15 @@ template <> struct Val<VK_BF16> {
 // x load of the batch, then the FMAs, so the batch costs two memory round trips.  NB is a
 // compile-time constant, so no load sits in a conditional block (a conditional load whose
 // result is widened inside the block would force a wait per slot).
-template <int NB, int B, int NR, int K, class XI, class T>
-__device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int rl, int q,
+// C16: column indices are stored as 16-bit differences to the row's own node.
+template <bool C16>
+__device__ __forceinline__ unsigned slot_col(const SellDev& A, int64_t idx, int node) {
+  if constexpr (C16) return unsigned(node + int(__builtin_nontemporal_load(A.col16 + idx)));
+  else return unsigned(__builtin_nontemporal_load(A.col + idx));
+}
+
+template <int NB, int B, int NR, int K, class XI, class T, bool C16>
+__device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int node, int rl, int q,
                                            const XI* __restrict__ x, T& acc) {
   constexpr int R = kWave / (B * NR);
   constexpr int W = kWave / NR;
@@ -96,8 +103,7 @@ __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int r
   VR av[NB][B];
   XI xv[NB][B];
 #pragma unroll
-  for (int qq = 0; qq < NB; ++qq)
-    js[qq] = unsigned(__builtin_nontemporal_load(A.col + int64_t(k + qq) * R + r));
+  for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16>(A, int64_t(k + qq) * R + r, node);
 #pragma unroll
   for (int qq = 0; qq < NB; ++qq) {
     const int64_t vb = int64_t(k + qq) * B * W + rl;
@@ -118,25 +124,19 @@ __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int r
     for (int cc = 0; cc < B; ++cc) acc += T(Val<K>::dec(av[qq][cc])) * T(xv[qq][cc]);
 }
 
-// per-lane row dot product of a slice: sum_k sum_cc a(k, cc) x[(col_k * B + cc) * NR + q].
-// NR right-hand sides share every matrix entry: lane = (r * B + c) * NR + q, the slice
-// holds R = 64 / (B * NR) nodes, and the values of row lane rl = lane / NR sit at
-// val[(k * B + cc) * W + rl] with the padded row-lane stride W = 64 / NR (R * B rounded up,
-// 64 for one right-hand side).  NR = 1 is the single right-hand-side layout.  Slots are
-// consumed in batches of KB, the remainder in one shorter batch (slice-uniform branch).
 // The same batch for the second of two sweeps from x = 0 with b = 1: the iterate after the
 // first sweep, x1_j = omega * (S_j * b_j), is formed on the fly from S and b instead of being
 // read (S of node j sits at S[j] for one component and one right-hand side), with the
 // rounding of the stored value, so the result is bitwise that of the two separate sweeps.
-template <int NB, int K, class X, class T>
-__device__ __forceinline__ void sell_batch_z(const SellDev& A, int k, int rl, const X* __restrict__ S,
+template <int NB, int K, class X, class T, bool C16>
+__device__ __forceinline__ void sell_batch_z(const SellDev& A, int k, int rl, int node, const X* __restrict__ S,
                                              const X* __restrict__ b, T omega, T& acc) {
   using VR = typename Val<K>::raw;
   unsigned js[NB];
   VR av[NB];
   X sv[NB], bv[NB];
 #pragma unroll
-  for (int qq = 0; qq < NB; ++qq) js[qq] = unsigned(__builtin_nontemporal_load(A.col + int64_t(k + qq) * kWave + rl));
+  for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16>(A, int64_t(k + qq) * kWave + rl, node);
 #pragma unroll
   for (int qq = 0; qq < NB; ++qq) av[qq] = Val<K>::load(A.val, int64_t(k + qq) * kWave + rl);
   __builtin_amdgcn_sched_barrier(0);
@@ -153,22 +153,22 @@ __device__ __forceinline__ void sell_batch_z(const SellDev& A, int k, int rl, co
   }
 }
 
-template <int N, int K, class X, class T>
-__device__ __forceinline__ void sell_rest_z(int rem, const SellDev& A, int k, int rl, const X* __restrict__ S,
-                                            const X* __restrict__ b, T omega, T& acc) {
+template <int N, int K, class X, class T, bool C16>
+__device__ __forceinline__ void sell_rest_z(int rem, const SellDev& A, int k, int rl, int node,
+                                            const X* __restrict__ S, const X* __restrict__ b, T omega, T& acc) {
   if constexpr (N >= 1) {
-    if (rem == N) sell_batch_z<N, K, X, T>(A, k, rl, S, b, omega, acc);
-    else sell_rest_z<N - 1, K, X, T>(rem, A, k, rl, S, b, omega, acc);
+    if (rem == N) sell_batch_z<N, K, X, T, C16>(A, k, rl, node, S, b, omega, acc);
+    else sell_rest_z<N - 1, K, X, T, C16>(rem, A, k, rl, node, S, b, omega, acc);
   }
 }
 
 // the remaining rem < KB slots of a slice as one batch of exactly rem slots
-template <int N, int B, int NR, int K, class XI, class T>
-__device__ __forceinline__ void sell_rest(int rem, const SellDev& A, int k, int r, int rl, int q,
+template <int N, int B, int NR, int K, class XI, class T, bool C16>
+__device__ __forceinline__ void sell_rest(int rem, const SellDev& A, int k, int r, int node, int rl, int q,
                                           const XI* __restrict__ x, T& acc) {
   if constexpr (N >= 1) {
-    if (rem == N) sell_batch<N, B, NR, K>(A, k, r, rl, q, x, acc);
-    else sell_rest<N - 1, B, NR, K>(rem, A, k, r, rl, q, x, acc);
+    if (rem == N) sell_batch<N, B, NR, K, XI, T, C16>(A, k, r, node, rl, q, x, acc);
+    else sell_rest<N - 1, B, NR, K, XI, T, C16>(rem, A, k, r, node, rl, q, x, acc);
   }
 }
 
@@ -182,10 +182,11 @@ template <int B> constexpr int kb_alt() { return B <= 2 ? 16 : 8; }
 // 64 for one right-hand side).  NR = 1 is the single right-hand-side layout.  Slots are
 // consumed in batches of KB, the remainder in one shorter batch (slice-uniform branch);
 // the FMAs run in slot order whatever KB is, so every KB gives the same bits.
-template <int B, int NR, int K, class XI, class T, int KB = kb_default<B>()>
+template <int B, int NR, int K, class XI, class T, int KB = kb_default<B>(), bool C16 = false>
 __device__ __forceinline__ T sell_dot(const SellDev& A, int slice, int lane, bool valid,
                                       const XI* __restrict__ x) {
   constexpr int W = kWave / NR;
+  constexpr int R = kWave / (B * NR);
   T acc = T(0);
   if (!valid) return acc;
   const int rl = lane / NR, q = lane % NR;
@@ -193,10 +194,11 @@ __device__ __forceinline__ T sell_dot(const SellDev& A, int slice, int lane, boo
   // the slice is the same for the whole wave: keep it (and the slot range, the load bases)
   // in scalar registers
   slice = __builtin_amdgcn_readfirstlane(slice);
+  const int node = slice * R + r;
   const int k1 = A.sptr[slice + 1];
   int k = A.sptr[slice];
-  for (; k + KB <= k1; k += KB) sell_batch<KB, B, NR, K>(A, k, r, rl, q, x, acc);
-  sell_rest<KB - 1, B, NR, K>(k1 - k, A, k, r, rl, q, x, acc);
+  for (; k + KB <= k1; k += KB) sell_batch<KB, B, NR, K, XI, T, C16>(A, k, r, node, rl, q, x, acc);
+  sell_rest<KB - 1, B, NR, K, XI, T, C16>(k1 - k, A, k, r, node, rl, q, x, acc);
   if (K == VK_F16 || K == VK_BF16) acc *= T(ldexpf(1.0f, A.rexp[int64_t(slice) * W + rl]));
   return acc;
 }
@@ -264,7 +266,7 @@ __device__ __forceinline__ SliceLane slice_lane(const SellDev& A, int slice, int
 }
 
 // y = A x (MODE 0), b - A x (MODE 1), M (b - A x) (MODE 2); returns the written value
-template <int B, int NR, int K, class XI, class XO, class T, int MODE, int KB = kb_default<B>()>
+template <int B, int NR, int K, class XI, class XO, class T, int MODE, int KB = kb_default<B>(), bool C16 = false>
 __device__ __forceinline__ T spmv_slice(const SellDev& A, const XO* __restrict__ b, const XI* __restrict__ x,
                                         XO* __restrict__ y, const uint8_t* __restrict__ mask, const SliceLane& s) {
   XO bv = XO(0);
@@ -273,7 +275,7 @@ __device__ __forceinline__ T spmv_slice(const SellDev& A, const XO* __restrict__
     bv = b[s.dof];
     if (MODE == 2) mk = mask[s.dof / NR];
   }
-  const T acc = sell_dot<B, NR, K, XI, T, KB>(A, s.slice, s.lane, s.valid, x);
+  const T acc = sell_dot<B, NR, K, XI, T, KB, C16>(A, s.slice, s.lane, s.valid, x);
   T out = T(0);
   if (s.valid) {
     if (MODE == 0) {
@@ -287,7 +289,7 @@ __device__ __forceinline__ T spmv_slice(const SellDev& A, const XO* __restrict__
   return out;
 }
 
-template <int B, int NR, int K, class X, class T, int KB = kb_default<B>()>
+template <int B, int NR, int K, class X, class T, int KB = kb_default<B>(), bool C16 = false>
 __device__ __forceinline__ void sweep_slice(const SellDev& A, const X* __restrict__ S, const X* __restrict__ b,
                                             const X* __restrict__ x, X* __restrict__ xo, T omega,
                                             const SliceLane& s) {
@@ -304,7 +306,7 @@ __device__ __forceinline__ void sweep_slice(const SellDev& A, const X* __restric
 #pragma unroll
     for (int cc = 0; cc < B; ++cc) sv[cc] = S[(int64_t(s.slice) * B + cc) * W + rl];
   }
-  const T acc = sell_dot<B, NR, K, X, T, KB>(A, s.slice, s.lane, s.valid, x);
+  const T acc = sell_dot<B, NR, K, X, T, KB, C16>(A, s.slice, s.lane, s.valid, x);
   const T res = s.valid ? T(bv) - acc : T(0);
   const int base = (rl / B) * B;
   T upd = T(0);
@@ -444,13 +446,13 @@ __global__ __launch_bounds__(kThreads) void k_tsell(TSellDev M, const X* __restr
 }
 
 // ------------------------------------------------------------------ grid kernels
-template <int B, int K, class XI, class XO, class T, int MODE, bool NORM, int KB>
+template <int B, int K, class XI, class XO, class T, int MODE, bool NORM, int KB, bool C16>
 __global__ __launch_bounds__(kThreads) void k_spmv(SellDev A, const XO* __restrict__ b, const XI* __restrict__ x,
                                                    XO* __restrict__ y, const uint8_t* __restrict__ mask,
                                                    double* __restrict__ partials) {
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const SliceLane s = slice_lane<B, 1>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
-  const T out = spmv_slice<B, 1, K, XI, XO, T, MODE, KB>(A, b, x, y, mask, s);
+  const T out = spmv_slice<B, 1, K, XI, XO, T, MODE, KB, C16>(A, b, x, y, mask, s);
   if (NORM) {
     __shared__ double lds[kMaxWaves + 1];
     const double p = block_allsum(double(out) * double(out), lds);
@@ -458,17 +460,17 @@ __global__ __launch_bounds__(kThreads) void k_spmv(SellDev A, const XO* __restri
   }
 }
 
-template <int B, int K, class X, class T, int KB>
+template <int B, int K, class X, class T, int KB, bool C16>
 __global__ __launch_bounds__(kThreads) void k_sweep(SellDev A, const X* __restrict__ S, const X* __restrict__ b,
                                                     const X* __restrict__ x, X* __restrict__ xo, T omega) {
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const SliceLane s = slice_lane<B, 1>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
-  sweep_slice<B, 1, K, X, T, KB>(A, S, b, x, xo, omega, s);
+  sweep_slice<B, 1, K, X, T, KB, C16>(A, S, b, x, xo, omega, s);
 }
 
 // two smoothing sweeps from x = 0 in one pass, one component per node:
 // x1 = omega S b (formed per column on the fly), x2 = x1 + omega S (b - A x1)
-template <int K, class X, class T, int KB>
+template <int K, class X, class T, int KB, bool C16>
 __global__ __launch_bounds__(kThreads) void k_sweep2z(SellDev A, const X* __restrict__ S, const X* __restrict__ b,
                                                       X* __restrict__ xo, T omega) {
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -481,8 +483,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep2z(SellDev A, const X* __rest
   const int k1 = A.sptr[su + 1];
   int k = A.sptr[su];
   T acc = T(0);
-  for (; k + KB <= k1; k += KB) sell_batch_z<KB, K, X, T>(A, k, lane, S, b, omega, acc);
-  sell_rest_z<KB - 1, K, X, T>(k1 - k, A, k, lane, S, b, omega, acc);
+  const int node = int(i);
+  for (; k + KB <= k1; k += KB) sell_batch_z<KB, K, X, T, C16>(A, k, lane, node, S, b, omega, acc);
+  sell_rest_z<KB - 1, K, X, T, C16>(k1 - k, A, k, lane, node, S, b, omega, acc);
   if (K == VK_F16 || K == VK_BF16) acc *= T(ldexpf(1.0f, A.rexp[int64_t(slice) * kWave + lane]));
   const X x1 = X(omega * (T(0) + T(si) * T(bi)));
   const T res = T(bi) - acc;
@@ -895,22 +898,25 @@ hipError_t spmv_t(const SellDev& A, const void* b, const void* x, void* y, const
   const XO* bb = static_cast<const XO*>(b);
   const XI* xx = static_cast<const XI*>(x);
   XO* yy = static_cast<XO*>(y);
-#define MGQ1_SPMV(MODE, NORM)                                                                          \
-  if (A.kb == kb_alt<B>())                                                                              \
-    hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, MODE, NORM, kb_alt<B>()>), g, kThreads, 0, s, A, bb, xx, yy, \
-                       mask, partials);                                                                  \
-  else                                                                                                   \
-    hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, MODE, NORM, kb_default<B>()>), g, kThreads, 0, s, A, bb, xx, \
-                       yy, mask, partials)
-  if (partials) {
-    if (mode == 0) MGQ1_SPMV(0, true);
-    else if (mode == 1) MGQ1_SPMV(1, true);
-    else MGQ1_SPMV(2, true);
-  } else {
-    if (mode == 0) MGQ1_SPMV(0, false);
-    else if (mode == 1) MGQ1_SPMV(1, false);
-    else MGQ1_SPMV(2, false);
+  // slot batch and column format are runtime properties of the operator
+#define MGQ1_SPMV4(MODE, NORM, KB, C16) \
+  hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, MODE, NORM, KB, C16>), g, kThreads, 0, s, A, bb, xx, yy, mask, partials)
+#define MGQ1_SPMV(MODE, NORM)                                                             \
+  if (A.col16) {                                                                          \
+    if (A.kb == kb_alt<B>()) MGQ1_SPMV4(MODE, NORM, kb_alt<B>(), true);                   \
+    else MGQ1_SPMV4(MODE, NORM, kb_default<B>(), true);                                   \
+  } else {                                                                                \
+    if (A.kb == kb_alt<B>()) MGQ1_SPMV4(MODE, NORM, kb_alt<B>(), false);                  \
+    else MGQ1_SPMV4(MODE, NORM, kb_default<B>(), false);                                  \
   }
+  // the combinations the library uses: y = Ax, b - Ax with or without norm partials,
+  // masked defect
+  if (mode == 0 && !partials) MGQ1_SPMV(0, false)
+  else if (mode == 1 && partials) MGQ1_SPMV(1, true)
+  else if (mode == 1) MGQ1_SPMV(1, false)
+  else if (mode == 2 && !partials) MGQ1_SPMV(2, false)
+  else return hipErrorInvalidValue;
+#undef MGQ1_SPMV4
 #undef MGQ1_SPMV
   return hipGetLastError();
 }
@@ -941,11 +947,16 @@ hipError_t sweep_t(const SellDev& A, const void* S, const void* b, const void* x
   const X* bb = static_cast<const X*>(b);
   const X* xx = static_cast<const X*>(x);
   X* oo = static_cast<X*>(xo);
-#define MGQ1_SWEEP(KIND)                                                                                 \
-  if (A.kb == kb_alt<B>())                                                                                \
-    hipLaunchKernelGGL((k_sweep<B, KIND, X, T, kb_alt<B>()>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega)); \
-  else                                                                                                     \
-    hipLaunchKernelGGL((k_sweep<B, KIND, X, T, kb_default<B>()>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega))
+#define MGQ1_SWEEP4(KIND, KB, C16) \
+  hipLaunchKernelGGL((k_sweep<B, KIND, X, T, KB, C16>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega))
+#define MGQ1_SWEEP(KIND)                                                   \
+  if (A.col16) {                                                           \
+    if (A.kb == kb_alt<B>()) MGQ1_SWEEP4(KIND, kb_alt<B>(), true);         \
+    else MGQ1_SWEEP4(KIND, kb_default<B>(), true);                         \
+  } else {                                                                 \
+    if (A.kb == kb_alt<B>()) MGQ1_SWEEP4(KIND, kb_alt<B>(), false);        \
+    else MGQ1_SWEEP4(KIND, kb_default<B>(), false);                        \
+  }
   // FP64 vectors go with FP64 values only; FP32 vectors with the reduced formats
   if constexpr (sizeof(X) == 8) {
     if (A.kind != VK_F64) return hipErrorInvalidValue;
@@ -959,6 +970,7 @@ hipError_t sweep_t(const SellDev& A, const void* S, const void* b, const void* x
     }
   }
 #undef MGQ1_SWEEP
+#undef MGQ1_SWEEP4
   return hipGetLastError();
 }
 
@@ -1052,13 +1064,17 @@ hipError_t launch_sweep2z(const SellDev& A, const void* S, const void* b, void* 
   if (A.B != 1) return hipErrorInvalidValue;
   const unsigned g = slice_grid(A.nslices);
   if (g == 0) return hipSuccess;
-#define MGQ1_S2Z(KIND, X, T)                                                                                 \
-  if (A.kb == kb_alt<1>())                                                                                    \
-    hipLaunchKernelGGL((k_sweep2z<KIND, X, T, kb_alt<1>()>), g, kThreads, 0, s, A, static_cast<const X*>(S),   \
-                       static_cast<const X*>(b), static_cast<X*>(xo), T(omega));                              \
-  else                                                                                                        \
-    hipLaunchKernelGGL((k_sweep2z<KIND, X, T, kb_default<1>()>), g, kThreads, 0, s, A, static_cast<const X*>(S), \
-                       static_cast<const X*>(b), static_cast<X*>(xo), T(omega))
+#define MGQ1_S2Z4(KIND, X, T, KB, C16)                                                              \
+  hipLaunchKernelGGL((k_sweep2z<KIND, X, T, KB, C16>), g, kThreads, 0, s, A, static_cast<const X*>(S), \
+                     static_cast<const X*>(b), static_cast<X*>(xo), T(omega))
+#define MGQ1_S2Z(KIND, X, T)                                                     \
+  if (A.col16) {                                                                 \
+    if (A.kb == kb_alt<1>()) MGQ1_S2Z4(KIND, X, T, kb_alt<1>(), true);           \
+    else MGQ1_S2Z4(KIND, X, T, kb_default<1>(), true);                           \
+  } else {                                                                       \
+    if (A.kb == kb_alt<1>()) MGQ1_S2Z4(KIND, X, T, kb_alt<1>(), false);          \
+    else MGQ1_S2Z4(KIND, X, T, kb_default<1>(), false);                          \
+  }
   if (xk == X_F64) {
     if (A.kind != VK_F64) return hipErrorInvalidValue;
     MGQ1_S2Z(VK_F64, double, double);
@@ -1071,6 +1087,7 @@ hipError_t launch_sweep2z(const SellDev& A, const void* S, const void* b, void* 
     }
   }
 #undef MGQ1_S2Z
+#undef MGQ1_S2Z4
   return hipGetLastError();
 }
 
@@ -1294,7 +1311,7 @@ __device__ __forceinline__ int find_entry(const BEntry* __restrict__ E, int n, i
 }
 
 // V-cycle steps on slices (sweep0, sweep, masked defect) for every problem of the batch
-template <int B, int NR, int K, class X, class T, int KIND, int KB>
+template <int B, int NR, int K, class X, class T, int KIND, int KB, bool C16>
 __global__ __launch_bounds__(kThreads) void k_bsell(const BEntry* __restrict__ E, int ne, T omega,
                                                     const int* __restrict__ active) {
   __shared__ int se;
@@ -1308,16 +1325,16 @@ __global__ __launch_bounds__(kThreads) void k_bsell(const BEntry* __restrict__ E
     sweep0_slice<B, NR, X, T>(static_cast<const X*>(e.S), static_cast<const X*>(e.in0), static_cast<X*>(e.out),
                               omega, s);
   else if (KIND == BK_SWEEP)
-    sweep_slice<B, NR, K, X, T, KB>(e.A, static_cast<const X*>(e.S), static_cast<const X*>(e.in0),
+    sweep_slice<B, NR, K, X, T, KB, C16>(e.A, static_cast<const X*>(e.S), static_cast<const X*>(e.in0),
                                     static_cast<const X*>(e.in1), static_cast<X*>(e.out), omega, s);
   else
-    spmv_slice<B, NR, K, X, X, T, 2, KB>(e.A, static_cast<const X*>(e.in0), static_cast<const X*>(e.in1),
+    spmv_slice<B, NR, K, X, X, T, 2, KB, C16>(e.A, static_cast<const X*>(e.in0), static_cast<const X*>(e.in1),
                                          static_cast<X*>(e.out), e.mask, s);
 }
 
 // outer-loop products with the FP64 operator: w = A z (KIND SPMV64) or r = b - A x with
 // partial sums of squares per (block, rhs) (KIND DEFECT64)
-template <int B, int NR, class XI, int KIND, int KB>
+template <int B, int NR, class XI, int KIND, int KB, bool C16>
 __global__ __launch_bounds__(kThreads) void k_bsell64(const BEntry* __restrict__ E, int ne,
                                                       const int* __restrict__ active, double* __restrict__ partials) {
   __shared__ int se;
@@ -1331,10 +1348,10 @@ __global__ __launch_bounds__(kThreads) void k_bsell64(const BEntry* __restrict__
     const SliceLane s = slice_lane<B, NR>(e.A, (blockIdx.x - e.first) * kSliceWaves + threadIdx.x / kWave,
                                           threadIdx.x % kWave);
     if (KIND == BK_SPMV64)
-      out = spmv_slice<B, NR, VK_F64, XI, double, double, 0, KB>(e.A, nullptr, static_cast<const XI*>(e.in1),
+      out = spmv_slice<B, NR, VK_F64, XI, double, double, 0, KB, C16>(e.A, nullptr, static_cast<const XI*>(e.in1),
                                                                  static_cast<double*>(e.out), nullptr, s);
     else
-      out = spmv_slice<B, NR, VK_F64, double, double, double, 1, KB>(e.A, static_cast<const double*>(e.in0),
+      out = spmv_slice<B, NR, VK_F64, double, double, double, 1, KB, C16>(e.A, static_cast<const double*>(e.in0),
                                                                      static_cast<const double*>(e.in1),
                                                                      static_cast<double*>(e.out), nullptr, s);
   }
@@ -1661,14 +1678,14 @@ __global__ void k_bclose(int j, int n_inst, int* kk, const int* iact) {
   if (inst < n_inst && iact[inst] && kk[inst] == 0) kk[inst] = j + 1;
 }
 
-template <int B, int NR, int K, class X, class T, int KB>
+template <int B, int NR, int K, class X, class T, int KB, bool C16>
 hipError_t batched_sell(int kind, const BEntry* E, int ne, int nb, double omega, const int* active,
                         double* partials, hipStream_t s) {
   switch (kind) {
-    case BK_SWEEP: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_SWEEP, KB>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
-    case BK_DEFECT: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_DEFECT, KB>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
-    case BK_SPMV64: hipLaunchKernelGGL((k_bsell64<B, NR, X, BK_SPMV64, KB>), nb, kThreads, 0, s, E, ne, active, partials); break;
-    case BK_DEFECT64: hipLaunchKernelGGL((k_bsell64<B, NR, double, BK_DEFECT64, KB>), nb, kThreads, 0, s, E, ne, active, partials); break;
+    case BK_SWEEP: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_SWEEP, KB, C16>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
+    case BK_DEFECT: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_DEFECT, KB, C16>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
+    case BK_SPMV64: hipLaunchKernelGGL((k_bsell64<B, NR, X, BK_SPMV64, KB, C16>), nb, kThreads, 0, s, E, ne, active, partials); break;
+    case BK_DEFECT64: hipLaunchKernelGGL((k_bsell64<B, NR, double, BK_DEFECT64, KB, C16>), nb, kThreads, 0, s, E, ne, active, partials); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1679,9 +1696,14 @@ hipError_t batched_t(int kind, const BEntry* E, int ne, int nb, double omega, co
                      int kb, hipStream_t s) {
   switch (kind) {
     case BK_SWEEP: case BK_DEFECT: case BK_SPMV64: case BK_DEFECT64:
-      if (kb == kb_alt<B>()) return batched_sell<B, NR, K, X, T, kb_alt<B>()>(kind, E, ne, nb, omega, active, partials, s);
-      return batched_sell<B, NR, K, X, T, kb_default<B>()>(kind, E, ne, nb, omega, active, partials, s);
-    case BK_SWEEP0: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_SWEEP0, kb_default<B>()>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
+      // kb < 0 selects the 16-bit column format (every entry of the launch has it)
+      if (kb < 0) {
+        if (-kb == kb_alt<B>()) return batched_sell<B, NR, K, X, T, kb_alt<B>(), true>(kind, E, ne, nb, omega, active, partials, s);
+        return batched_sell<B, NR, K, X, T, kb_default<B>(), true>(kind, E, ne, nb, omega, active, partials, s);
+      }
+      if (kb == kb_alt<B>()) return batched_sell<B, NR, K, X, T, kb_alt<B>(), false>(kind, E, ne, nb, omega, active, partials, s);
+      return batched_sell<B, NR, K, X, T, kb_default<B>(), false>(kind, E, ne, nb, omega, active, partials, s);
+    case BK_SWEEP0: hipLaunchKernelGGL((k_bsell<B, NR, K, X, T, BK_SWEEP0, kb_default<B>(), false>), nb, kThreads, 0, s, E, ne, T(omega), active); break;
     case BK_RESTRICT: hipLaunchKernelGGL((k_btsell<B, NR, X, T, BK_RESTRICT>), nb, kThreads, 0, s, E, ne, active); break;
     case BK_PROLONG: hipLaunchKernelGGL((k_btsell<B, NR, X, T, BK_PROLONG>), nb, kThreads, 0, s, E, ne, active); break;
     case BK_FILL0: hipLaunchKernelGGL((k_belem<B, NR, X, T, BK_FILL0>), nb, kThreads, 0, s, E, ne, active); break;

@@ -402,6 +402,26 @@ int upload_sell(DevOwner* h, const HostSell& S, int kind, SellDev& D, hipStream_
   if ((rc = upload(h, &cl, S.col, s))) return rc;
   D.sptr = sp;
   D.col = cl;
+  // 16-bit column differences to the row's node, when every one fits (rows past the end
+  // of the last slice store 0)
+  bool fits = true;
+  std::vector<int16_t> c16(S.col.size(), 0);
+  for (int32_t sl = 0; sl < S.nslices && fits; ++sl)
+    for (int64_t k = S.sptr[sl]; k < S.sptr[sl + 1] && fits; ++k)
+      for (int r = 0; r < S.R; ++r) {
+        const int64_t node = int64_t(sl) * S.R + r;
+        if (node >= S.n) continue;
+        const int64_t d = int64_t(S.col[size_t(k) * S.R + r]) - node;
+        if (d < -32768 || d > 32767) { fits = false; break; }
+        c16[size_t(k) * S.R + r] = int16_t(d);
+      }
+  const char* off = std::getenv("MGQ1_NO_COL16");
+  if (fits && !(off && std::atoi(off) != 0)) {
+    int16_t* c;
+    if ((rc = upload(h, &c, c16, s))) return rc;
+    MG_HIP(hipStreamSynchronize(s));
+    D.col16 = c;
+  }
   const size_t nv = S.val.size();
   if (kind == VK_F64) {
     double* v;
@@ -1065,6 +1085,7 @@ struct mg_batch : DevOwner {
   std::vector<BLaunch> spmv64;        // per Krylov index: w = A z_j
   int nbig = 0;                       // blocks of the outer FP64 products
   int kb64 = 0;                       // slot batch of the outer FP64 products
+  bool c16 = false;                   // all operators carry 16-bit column differences
   hipStream_t cap = nullptr;
   std::vector<hipGraphExec_t> graphs;
   int* hkk = nullptr;                 // pinned host copy of kk (read after every step)
@@ -1247,8 +1268,14 @@ void build_plan(mg_batch* h, int j, std::vector<BLaunch>& out) {
 }
 
 int run_launch(mg_batch* h, const BLaunch& L, const BEntry* table, const int* active, double* partials, hipStream_t s) {
+  int kb = L.kb;
+  if (h->c16) {                       // every operator of the batch has 16-bit columns
+    int kd, ko;
+    slot_batch_choices(h->B, &kd, &ko);
+    kb = -(kb ? kb : kd);
+  }
   MG_HIP(launch_batched(L.kind, table + L.e0, L.ne, L.nb, h->B, h->NR, h->vkind, h->xk, h->cfg.omega, active,
-                        partials, L.kb, s));
+                        partials, kb, s));
   return MG_OK;
 }
 
@@ -1403,6 +1430,9 @@ int setup_batch(mg_batch* h, const std::vector<std::vector<HostLevel>>& HH, hipS
     h->off[p + 1] = h->off[p] + pr.lv[pr.L].N * NR;
   }
   if ((rc = check_flag(flag, s))) return rc;
+  h->c16 = true;
+  for (const auto& pr : h->pr)
+    for (const LevelDev& D : pr.lv) h->c16 = h->c16 && D.Ac.col16 && D.A64.col16;
   const int64_t N = h->Ntot = h->off[P];
   const int m = c.gmres_m;
   const size_t xs = xsize(h->xk);
@@ -1778,13 +1808,14 @@ int mg_level_info(const mg_handle* h, int32_t level, int32_t* n_nodes, int32_t* 
   return MG_OK;
 }
 
-int mg_level_tuning(const mg_handle* h, int32_t level, int32_t* slot_batch, double* us_default,
-                    double* us_other) {
+int mg_level_tuning(const mg_handle* h, int32_t level, int32_t* slot_batch, int32_t* col_bytes,
+                    double* us_default, double* us_other) {
   if (!h || level < 0 || level > h->L) return fail(MG_EINVAL, "bad handle or level");
   const LevelDev& L = h->lv[level];
   int kd, ko;
   slot_batch_choices(L.B, &kd, &ko);
   if (slot_batch) *slot_batch = L.Ac.kb ? L.Ac.kb : kd;
+  if (col_bytes) *col_bytes = L.A64.col16 ? 2 : 4;
   if (us_default) *us_default = L.us_def;
   if (us_other) *us_other = L.us_alt;
   return MG_OK;

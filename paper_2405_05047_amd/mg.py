@@ -70,7 +70,8 @@ def lib():
         L.mg_level_prolong.argtypes = [vp, i32, vp, vp, vp]
         L.mg_coarse_solve.argtypes = [vp, vp, vp, vp]
         L.mg_level_info.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_int64)]
-        L.mg_level_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.mg_level_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]
         L.mg_num_levels.argtypes = [vp]
         L.mg_num_levels.restype = i32
         L.mg_validate_level.argtypes = [C.POINTER(LevelIn), C.POINTER(LevelIn)]
@@ -192,8 +193,14 @@ class Hierarchy:
     def tuning(self, l):
         """(slot batch in use, measured us per sweep for the default / other size)."""
         kb, t0, t1 = C.c_int32(), C.c_double(), C.c_double()
-        _check(lib().mg_level_tuning(self.h, l, C.byref(kb), C.byref(t0), C.byref(t1)))
+        _check(lib().mg_level_tuning(self.h, l, C.byref(kb), None, C.byref(t0), C.byref(t1)))
         return kb.value, t0.value, t1.value
+
+    def col_bytes(self, l):
+        """Bytes per stored column index of level l's operators (2 or 4)."""
+        cb = C.c_int32()
+        _check(lib().mg_level_tuning(self.h, l, None, C.byref(cb), None, None))
+        return cb.value
 
     def ndof(self, l=-1):
         n, b, _ = self.sizes[l]

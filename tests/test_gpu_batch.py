@@ -263,3 +263,17 @@ def test_batch_slot_batch_variants_bitwise_equal():
         outs.append((x.cpu().numpy(), [s["iters"] for s in st]))
     for x, it in outs[1:]:
         assert np.array_equal(x, outs[0][0]) and it == outs[0][1]
+
+
+def test_batch_column_formats_bitwise_equal(monkeypatch):
+    wls, ors, gps, b, nrhs = _group("td_nrhs8")
+    bd = torch.from_numpy(b).cuda()
+    outs = []
+    for off in ("0", "1"):
+        monkeypatch.setenv("MGQ1_NO_COL16", off)
+        bt = _batch("td_nrhs8", precision="fp16")
+        x = torch.zeros_like(bd)
+        rc, st = bt.solve(bd, x)
+        assert rc == 0
+        outs.append(x.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])

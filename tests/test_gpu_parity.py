@@ -317,3 +317,20 @@ def test_zero_rhs_and_exact_initial_guess(name):
     x = dev(xe)
     st = h.solve(dev(o.b), x)
     assert st["iters"] == 0 and st["converged"] == 1 and np.array_equal(host(x), xe)
+
+
+@pytest.mark.parametrize("name", ["poisson33", "td_band", "elast17", "oseen17", "edge4"])
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_column_formats_bitwise_equal(name, prec, monkeypatch):
+    """Operators whose column differences fit 16 bits are read in that format; the result
+    is bitwise the one of the 32-bit column indices."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    outs = []
+    for off in ("0", "1"):
+        monkeypatch.setenv("MGQ1_NO_COL16", off)
+        h = mg.Hierarchy(p.levels, mg.config_from(wl, precision=prec))
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        st = h.solve(dev(o.b), x)
+        outs.append((host(x), st["iters"]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
