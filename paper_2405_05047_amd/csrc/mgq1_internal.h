@@ -91,7 +91,8 @@ struct TailParams {
 // DoFs (mode 2); with `partials` != NULL every block also writes the sum of squares of
 // its y entries to partials[block] (spmv_grid(A) entries).  xk / yk: vector kinds.
 hipError_t launch_spmv(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask,
-                       int xk, int yk, int mode, double* partials, hipStream_t s);
+                       int xk, int yk, int mode, double* partials, hipStream_t s,
+                       const double* dotv = nullptr);
 int spmv_grid(const SellDev& A);
 // x_out = x + omega S (b - A x); S in lane layout, same kind as the vectors
 hipError_t launch_sweep(const SellDev& A, const void* S, const void* b, const void* x, void* xo,
@@ -119,26 +120,29 @@ hipError_t launch_fill(int64_t n, void* y, int yk, double v, hipStream_t s);
 hipError_t launch_convert(int64_t n, const void* x, int xk, void* y, int yk, hipStream_t s);
 hipError_t launch_axpy(int64_t n, void* y, int yk, const void* x, int xk, double sign,
                        const double* alpha, hipStream_t s);          // y += sign * (*alpha) * x
+// y = x / *denom (if != 0), and in FP32 to yc when given
 hipError_t launch_scale_div(int64_t n, double* y, const double* x, const double* denom,
-                            hipStream_t s);                          // y = x / *denom (if != 0)
+                            hipStream_t s, float* yc = nullptr);
 // deterministic reductions without atomics: producers write one partial per block
 // (reduction_grid(n) of them); consumers re-sum them in a fixed order
 int reduction_grid(int64_t n);
 hipError_t launch_dot_partials(int64_t n, const double* a, const double* b, double* partials, hipStream_t s);
 hipError_t launch_finish(const double* partials, int g, double* out, int sqrt_out, hipStream_t s);
-// MGS step: h = sum(pin) -> *hout; w -= h vi; partials of (w, vnext) (vnext NULL: (w, w))
+// MGS step: h = sum(pin) -> *hout; w -= h vi; partials of (w, vnext) (vnext NULL: (w, w));
+// gin = number of partials in pin (0: reduction_grid(n))
 hipError_t launch_mgs_step(int64_t n, double* w, const double* vi, const double* vnext, const double* pin,
-                           double* pout, double* hout, hipStream_t s);
-// nrm = sqrt(sum(pin)) -> *hout; w /= nrm unless nrm == 0
-hipError_t launch_mgs_normalize(int64_t n, double* w, const double* pin, double* hout, hipStream_t s);
+                           double* pout, double* hout, hipStream_t s, int gin = 0);
+// nrm = sqrt(sum(pin)) -> *hout; w /= nrm unless nrm == 0.  With H given, Givens step gj
+// of GMRES on the (m+1) x m Hessenberg H (column-major, ld = m+1) follows in the same
+// kernel: rotate column gj by the previous rotations, form rotation gj, update g;
+// st[0] = |g[gj+1]|, st[1] = 1 if H[gj+1][gj] was 0 before the rotation.  With wc given,
+// w is also written there in FP32.
+hipError_t launch_mgs_normalize(int64_t n, double* w, const double* pin, double* hout, hipStream_t s, int gj = 0,
+                                int gm = 0, double* H = nullptr, double* cs = nullptr, double* sn = nullptr,
+                                double* gg = nullptr, double* st = nullptr, float* wc = nullptr);
 // x += sum_{i<k} y[i] Z_i, Z_i = Z + i*ldz of kind zk
 hipError_t launch_update_x(int64_t n, double* x, const void* Z, int zk, int64_t ldz, const double* y,
                            int k, hipStream_t s);
-// Givens step j of GMRES on the (m+1) x m Hessenberg H (column-major, ld = m+1):
-// rotate column j by the previous rotations, form rotation j, update g.
-// st[0] = |g[j+1]|, st[1] = 1 if H[j+1][j] was 0 before the rotation
-hipError_t launch_givens(int j, int m, double* H, double* cs, double* sn, double* g, double* st,
-                         hipStream_t s);
 // y = H[:k,:k]^{-1} g[:k] (upper triangular)
 hipError_t launch_backsolve(int k, int m, const double* H, const double* g, double* y, hipStream_t s);
 // g = (beta, 0, ..., 0), beta read from the device

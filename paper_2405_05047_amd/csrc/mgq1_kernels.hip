@@ -446,16 +446,17 @@ __global__ __launch_bounds__(kThreads) void k_tsell(TSellDev M, const X* __restr
 }
 
 // ------------------------------------------------------------------ grid kernels
+// NORM: per-block partial sums of out * out, or of out * dotv[row] when dotv is given
 template <int B, int K, class XI, class XO, class T, int MODE, bool NORM, int KB, bool C16>
 __global__ __launch_bounds__(kThreads) void k_spmv(SellDev A, const XO* __restrict__ b, const XI* __restrict__ x,
                                                    XO* __restrict__ y, const uint8_t* __restrict__ mask,
-                                                   double* __restrict__ partials) {
+                                                   double* __restrict__ partials, const double* __restrict__ dotv) {
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const SliceLane s = slice_lane<B, 1>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
   const T out = spmv_slice<B, 1, K, XI, XO, T, MODE, KB, C16>(A, b, x, y, mask, s);
   if (NORM) {
     __shared__ double lds[kMaxWaves + 1];
-    const double p = block_allsum(double(out) * double(out), lds);
+    const double p = block_allsum(double(out) * (dotv ? (s.valid ? dotv[s.dof] : 0.0) : double(out)), lds);
     if (threadIdx.x == 0) partials[blockIdx.x] = p;
   }
 }
@@ -743,11 +744,15 @@ __global__ void k_axpy(int64_t n, Y* __restrict__ y, const X* __restrict__ x, do
 }
 
 __global__ void k_scale_div(int64_t n, double* __restrict__ y, const double* __restrict__ x,
-                            const double* __restrict__ denom) {
+                            const double* __restrict__ denom, float* __restrict__ yc) {
   const double d = *denom;
   if (d == 0.0) return;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < n) y[t] = x[t] / d;
+  if (t < n) {
+    const double v = x[t] / d;
+    y[t] = v;
+    if (yc) yc[t] = float(v);
+  }
 }
 
 // partial sums of a.b (b == nullptr: a.a), one per block
@@ -814,43 +819,10 @@ __global__ __launch_bounds__(kRedThreads) void k_mgs_step(int64_t n, double* __r
   if (threadIdx.x == 0) pout[blockIdx.x] = s;
 }
 
-// nrm = sqrt(sum(pin)), stored by block 0; w /= nrm (unless nrm == 0)
-__global__ __launch_bounds__(kRedThreads) void k_mgs_normalize(int64_t n, double* __restrict__ w,
-                                                               const double* __restrict__ pin, int gin,
-                                                               double* __restrict__ hout) {
-  __shared__ double lds[kMaxWaves + 1];
-  const double nrm = sqrt(sum_partials(pin, gin, lds));
-  if (blockIdx.x == 0 && threadIdx.x == 0) *hout = nrm;
-  if (nrm == 0.0) return;
-  constexpr int U = 4;
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < n; i0 += stride * U) {
-    double wv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = i0 + u * stride;
-      wv[u] = i < n ? w[i] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = i0 + u * stride;
-      if (i < n) w[i] = wv[u] / nrm;
-    }
-  }
-}
-
-template <class Z>
-__global__ void k_update_x(int64_t n, double* __restrict__ x, const Z* __restrict__ Zm, int64_t ldz,
-                           const double* __restrict__ y, int k) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  double acc = x[t];
-  for (int i = 0; i < k; ++i) acc += y[i] * double(Zm[int64_t(i) * ldz + t]);
-  x[t] = acc;
-}
-
-__global__ void k_givens(int j, int m, double* H, double* cs, double* sn, double* g, double* st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Givens rotation j of the Hessenberg column j (applies the previous rotations, forms the
+// new one, rotates g); st receives |g_{j+1}| and the breakdown flag
+__device__ __forceinline__ void givens_column(int j, int m, double* H, double* cs, double* sn, double* g,
+                                              double* st) {
   const int ld = m + 1;
   double* h = H + int64_t(j) * ld;
   const bool breakdown = h[j + 1] == 0.0;
@@ -870,6 +842,66 @@ __global__ void k_givens(int j, int m, double* H, double* cs, double* sn, double
   st[1] = breakdown ? 1.0 : 0.0;
   __threadfence_system();                  // st may be host memory read after the step
 }
+
+// nrm = sqrt(sum(pin)), stored by block 0; w /= nrm (unless nrm == 0).  With gv given,
+// block 0 then applies Givens rotation gv->j to the finished Hessenberg column; with wc
+// given, the normalised vector is also written in FP32 (the next V-cycle's input).
+struct GivensArgs {
+  int j, m;
+  double *H, *cs, *sn, *g, *st;
+};
+
+// hout is the Hessenberg entry (j+1, j) that the Givens step reads back through gv.H: it
+// must not be declared non-aliasing
+__global__ __launch_bounds__(kRedThreads) void k_mgs_normalize(int64_t n, double* __restrict__ w,
+                                                               const double* __restrict__ pin, int gin,
+                                                               double* hout, GivensArgs gv,
+                                                               float* __restrict__ wc) {
+  __shared__ double lds[kMaxWaves + 1];
+  const double nrm = sqrt(sum_partials(pin, gin, lds));
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *hout = nrm;
+    if (gv.H) givens_column(gv.j, gv.m, gv.H, gv.cs, gv.sn, gv.g, gv.st);
+  }
+  if (nrm == 0.0) {
+    if (wc) {
+      const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+      for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) wc[i] = float(w[i]);
+    }
+    return;
+  }
+  constexpr int U = 4;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < n; i0 += stride * U) {
+    double wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      wv[u] = i < n ? w[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < n) {
+        const double v = wv[u] / nrm;
+        w[i] = v;
+        if (wc) wc[i] = float(v);
+      }
+    }
+  }
+}
+
+template <class Z>
+__global__ void k_update_x(int64_t n, double* __restrict__ x, const Z* __restrict__ Zm, int64_t ldz,
+                           const double* __restrict__ y, int k) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double acc = x[t];
+  for (int i = 0; i < k; ++i) acc += y[i] * double(Zm[int64_t(i) * ldz + t]);
+  x[t] = acc;
+}
+
+
 
 __global__ void k_backsolve(int k, int m, const double* H, const double* g, double* y) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -892,15 +924,16 @@ inline unsigned slice_grid(int nslices) { return unsigned((nslices + kSliceWaves
 
 template <int B, int K, class XI, class XO, class T>
 hipError_t spmv_t(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask, int mode,
-                  double* partials, hipStream_t s) {
+                  double* partials, const double* dotv, hipStream_t s) {
   const unsigned g = slice_grid(A.nslices);
   if (g == 0) return hipSuccess;
   const XO* bb = static_cast<const XO*>(b);
   const XI* xx = static_cast<const XI*>(x);
   XO* yy = static_cast<XO*>(y);
   // slot batch and column format are runtime properties of the operator
-#define MGQ1_SPMV4(MODE, NORM, KB, C16) \
-  hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, MODE, NORM, KB, C16>), g, kThreads, 0, s, A, bb, xx, yy, mask, partials)
+#define MGQ1_SPMV4(MODE, NORM, KB, C16)                                                                     \
+  hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, MODE, NORM, KB, C16>), g, kThreads, 0, s, A, bb, xx, yy, mask, partials, \
+                     dotv)
 #define MGQ1_SPMV(MODE, NORM)                                                             \
   if (A.col16) {                                                                          \
     if (A.kb == kb_alt<B>()) MGQ1_SPMV4(MODE, NORM, kb_alt<B>(), true);                   \
@@ -912,7 +945,8 @@ hipError_t spmv_t(const SellDev& A, const void* b, const void* x, void* y, const
   // the combinations the library uses: y = Ax, b - Ax with or without norm partials,
   // masked defect
   if (mode == 0 && !partials) MGQ1_SPMV(0, false)
-  else if (mode == 1 && partials) MGQ1_SPMV(1, true)
+  else if (mode == 0 && dotv) MGQ1_SPMV(0, true)
+  else if (mode == 1 && partials && !dotv) MGQ1_SPMV(1, true)
   else if (mode == 1) MGQ1_SPMV(1, false)
   else if (mode == 2 && !partials) MGQ1_SPMV(2, false)
   else return hipErrorInvalidValue;
@@ -923,17 +957,17 @@ hipError_t spmv_t(const SellDev& A, const void* b, const void* x, void* y, const
 
 template <int B>
 hipError_t spmv_b(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask, int xk, int yk,
-                  int mode, double* partials, hipStream_t s) {
+                  int mode, double* partials, const double* dotv, hipStream_t s) {
   if (A.kind == VK_F64) {
-    if (xk == X_F64 && yk == X_F64) return spmv_t<B, VK_F64, double, double, double>(A, b, x, y, mask, mode, partials, s);
-    if (xk == X_F32 && yk == X_F64) return spmv_t<B, VK_F64, float, double, double>(A, b, x, y, mask, mode, partials, s);
+    if (xk == X_F64 && yk == X_F64) return spmv_t<B, VK_F64, double, double, double>(A, b, x, y, mask, mode, partials, dotv, s);
+    if (xk == X_F32 && yk == X_F64) return spmv_t<B, VK_F64, float, double, double>(A, b, x, y, mask, mode, partials, dotv, s);
     return hipErrorInvalidValue;
   }
   if (xk != X_F32 || yk != X_F32) return hipErrorInvalidValue;
   switch (A.kind) {
-    case VK_F32: return spmv_t<B, VK_F32, float, float, float>(A, b, x, y, mask, mode, partials, s);
-    case VK_F16: return spmv_t<B, VK_F16, float, float, float>(A, b, x, y, mask, mode, partials, s);
-    case VK_BF16: return spmv_t<B, VK_BF16, float, float, float>(A, b, x, y, mask, mode, partials, s);
+    case VK_F32: return spmv_t<B, VK_F32, float, float, float>(A, b, x, y, mask, mode, partials, dotv, s);
+    case VK_F16: return spmv_t<B, VK_F16, float, float, float>(A, b, x, y, mask, mode, partials, dotv, s);
+    case VK_BF16: return spmv_t<B, VK_BF16, float, float, float>(A, b, x, y, mask, mode, partials, dotv, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1015,12 +1049,12 @@ void slot_batch_choices(int B, int* kb_def, int* kb_other) {
 int spmv_grid(const SellDev& A) { return int(slice_grid(A.nslices)); }
 
 hipError_t launch_spmv(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask, int xk, int yk,
-                       int mode, double* partials, hipStream_t s) {
+                       int mode, double* partials, hipStream_t s, const double* dotv) {
   switch (A.B) {
-    case 1: return spmv_b<1>(A, b, x, y, mask, xk, yk, mode, partials, s);
-    case 2: return spmv_b<2>(A, b, x, y, mask, xk, yk, mode, partials, s);
-    case 3: return spmv_b<3>(A, b, x, y, mask, xk, yk, mode, partials, s);
-    case 4: return spmv_b<4>(A, b, x, y, mask, xk, yk, mode, partials, s);
+    case 1: return spmv_b<1>(A, b, x, y, mask, xk, yk, mode, partials, dotv, s);
+    case 2: return spmv_b<2>(A, b, x, y, mask, xk, yk, mode, partials, dotv, s);
+    case 3: return spmv_b<3>(A, b, x, y, mask, xk, yk, mode, partials, dotv, s);
+    case 4: return spmv_b<4>(A, b, x, y, mask, xk, yk, mode, partials, dotv, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1242,9 +1276,9 @@ hipError_t launch_axpy(int64_t n, void* y, int yk, const void* x, int xk, double
   return hipGetLastError();
 }
 
-hipError_t launch_scale_div(int64_t n, double* y, const double* x, const double* denom, hipStream_t s) {
+hipError_t launch_scale_div(int64_t n, double* y, const double* x, const double* denom, hipStream_t s, float* yc) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scale_div, grid_for(n, 256), 256, 0, s, n, y, x, denom);
+  hipLaunchKernelGGL(k_scale_div, grid_for(n, 256), 256, 0, s, n, y, x, denom, yc);
   return hipGetLastError();
 }
 
@@ -1259,15 +1293,17 @@ hipError_t launch_finish(const double* partials, int g, double* out, int sqrt_ou
 }
 
 hipError_t launch_mgs_step(int64_t n, double* w, const double* vi, const double* vnext, const double* pin,
-                           double* pout, double* hout, hipStream_t s) {
+                           double* pout, double* hout, hipStream_t s, int gin) {
   const unsigned g = vec_grid(n);
-  hipLaunchKernelGGL(k_mgs_step, g, kRedThreads, 0, s, n, w, vi, vnext, pin, int(g), pout, hout);
+  hipLaunchKernelGGL(k_mgs_step, g, kRedThreads, 0, s, n, w, vi, vnext, pin, gin > 0 ? gin : int(g), pout, hout);
   return hipGetLastError();
 }
 
-hipError_t launch_mgs_normalize(int64_t n, double* w, const double* pin, double* hout, hipStream_t s) {
+hipError_t launch_mgs_normalize(int64_t n, double* w, const double* pin, double* hout, hipStream_t s, int gj,
+                                int gm, double* H, double* cs, double* sn, double* gg, double* st, float* wc) {
   const unsigned g = vec_grid(n);
-  hipLaunchKernelGGL(k_mgs_normalize, g, kRedThreads, 0, s, n, w, pin, int(g), hout);
+  GivensArgs gv{gj, gm, H, cs, sn, gg, st};
+  hipLaunchKernelGGL(k_mgs_normalize, g, kRedThreads, 0, s, n, w, pin, int(g), hout, gv, wc);
   return hipGetLastError();
 }
 
@@ -1279,11 +1315,6 @@ hipError_t launch_update_x(int64_t n, double* x, const void* Z, int zk, int64_t 
     hipLaunchKernelGGL(k_update_x<double>, g, 256, 0, s, n, x, static_cast<const double*>(Z), ldz, y, k);
   else
     hipLaunchKernelGGL(k_update_x<float>, g, 256, 0, s, n, x, static_cast<const float*>(Z), ldz, y, k);
-  return hipGetLastError();
-}
-
-hipError_t launch_givens(int j, int m, double* H, double* cs, double* sn, double* g, double* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_givens, 1, 64, 0, s, j, m, H, cs, sn, g, st);
   return hipGetLastError();
 }
 

@@ -603,10 +603,11 @@ int vcycle_cycle(mg_handle* h, const void* bL, void* xL, hipStream_t s) {
   return MG_OK;
 }
 
-// z = V(v) with v FP64 (finest), z in cycle precision
-int precond(mg_handle* h, const double* v, void* z, hipStream_t s) {
+// z = V(v) with v FP64 (finest), z in cycle precision; converted = the cycle-precision
+// copy of v is already in bcyc
+int precond(mg_handle* h, const double* v, void* z, hipStream_t s, bool converted = false) {
   if (h->xk == X_F64) return vcycle_cycle(h, v, z, s);
-  MG_HIP(launch_convert(h->lv[h->L].N, v, X_F64, h->bcyc, h->xk, s));
+  if (!converted) MG_HIP(launch_convert(h->lv[h->L].N, v, X_F64, h->bcyc, h->xk, s));
   return vcycle_cycle(h, h->bcyc, z, s);
 }
 
@@ -634,21 +635,25 @@ int enqueue_fgmres_step(mg_handle* h, int j, hipStream_t s) {
   double* w = h->V + int64_t(j + 1) * N;
   void* zj = static_cast<char*>(h->Z) + size_t(j) * N * xsize(h->xk);
   int rc;
-  if ((rc = precond(h, vj, zj, s))) return rc;
-  MG_HIP(launch_spmv(T.A64, nullptr, zj, w, nullptr, h->xk, X_F64, 0, nullptr, s));
+  // the cycle-precision copy of v_j was written by the kernel that produced v_j
+  if ((rc = precond(h, vj, zj, s, true))) return rc;
+  // w = A z_j together with the partial sums of (w, v_0) for the first Gram-Schmidt step
+  MG_HIP(launch_spmv(T.A64, nullptr, zj, w, nullptr, h->xk, X_F64, 0, h->pbig, s, h->V));
   double* Hj = h->H + int64_t(j) * (m + 1);
   // each step subtracts the projection on v_i and forms the partial dot products with
   // v_{i+1} (or with w itself after the last step)
-  MG_HIP(launch_dot_partials(N, w, h->V, h->pv[0], s));
   for (int i = 0; i <= j; ++i) {
     const double* vi = h->V + int64_t(i) * N;
     const double* vn = (i < j) ? h->V + int64_t(i + 1) * N : nullptr;
-    MG_HIP(launch_mgs_step(N, w, vi, vn, h->pv[i & 1], h->pv[(i + 1) & 1], Hj + i, s));
+    const double* pin = (i == 0) ? h->pbig : h->pv[i & 1];
+    MG_HIP(launch_mgs_step(N, w, vi, vn, pin, h->pv[(i + 1) & 1], Hj + i, s, i == 0 ? spmv_grid(T.A64) : 0));
   }
-  MG_HIP(launch_mgs_normalize(N, w, h->pv[(j + 1) & 1], Hj + j + 1, s));
-  // |g_{j+1}| and the breakdown flag go straight to pinned host memory (slot j), so the
+  // v_{j+1} = w / ||w|| (and its cycle-precision copy for step j+1), then Givens rotation
+  // j, whose |g_{j+1}| and breakdown flag go straight to pinned host memory (slot j) so the
   // host can read them while step j+1 is already queued
-  MG_HIP(launch_givens(j, m, h->H, h->cs, h->sn, h->g, h->hst_dev + 2 * j, s));
+  float* wc = h->xk == X_F64 ? nullptr : static_cast<float*>(h->bcyc);
+  MG_HIP(launch_mgs_normalize(N, w, h->pv[(j + 1) & 1], Hj + j + 1, s, j, m, h->H, h->cs, h->sn, h->g,
+                              h->hst_dev + 2 * j, wc));
   return MG_OK;
 }
 
@@ -719,7 +724,8 @@ int solve_impl(mg_handle* h, const double* b, double* x, mg_solve_stats* st, voi
       if (!std::isfinite(beta) || beta > 1e6 * std::max(S.res0, 1e-300)) { status = MG_ENUMERIC; break; }
       if (fixed <= 0 && beta <= tol) { S.converged = 1; break; }
       if (S.iters >= limit || beta == 0.0) { status = (fixed > 0 || beta == 0.0) ? MG_OK : MG_ENOCONV; break; }
-      MG_HIP(launch_scale_div(N, h->V, h->rout, h->dsc + 0, s));
+      MG_HIP(launch_scale_div(N, h->V, h->rout, h->dsc + 0, s,
+                              h->xk == X_F64 ? nullptr : static_cast<float*>(h->bcyc)));
       MG_HIP(launch_init_g(m, h->g, h->dsc + 0, s));
       // Step j+1 is queued before the host waits for step j whenever the residual
       // estimates predict that it will be needed (a mispredicted step only costs time: it
