@@ -214,10 +214,10 @@ hipError_t launch_bfinish(const double* partials, const int* pfirst, const int* 
 hipError_t launch_bmgs_step(const BSegs& g, double* w, const double* vi, const double* vnext, const double* pin,
                             double* pout, double* H, int64_t hstride, hipStream_t s);
 hipError_t launch_bmgs_normalize(const BSegs& g, double* w, const double* pin, double* H, int64_t hstride,
-                                 hipStream_t s);
+                                 hipStream_t s, float* wc = nullptr);
 // y = x / beta[inst] (0 where beta == 0 or the instance is inactive)
 hipError_t launch_bscale(const BSegs& g, double* y, const double* x, const double* beta, const int* iact,
-                         hipStream_t s);
+                         hipStream_t s, float* yc = nullptr);
 // x += sum_{i < kk[inst]} yv[inst][i] Z_i   (Z_i = Z + i * ldz of kind zk)
 hipError_t launch_bupdate(const BSegs& g, double* x, const void* Z, int zk, int64_t ldz, const double* yv, int m,
                           const int* kk, hipStream_t s);

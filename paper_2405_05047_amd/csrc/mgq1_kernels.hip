@@ -1363,6 +1363,22 @@ __global__ __launch_bounds__(kThreads) void k_bsell(const BEntry* __restrict__ E
                                          static_cast<X*>(e.out), e.mask, s);
 }
 
+// fixed-order sum over the block of values that belong to rhs q = tid % NR; thread q of
+// the result gets the sum for q
+__device__ __forceinline__ double block_sum_rhs(double v, int NR, double* lds) {
+  // inside each wave a fixed shuffle tree combines the lanes of equal lane % NR, then
+  // thread q adds the per-wave results in wave order
+  for (int o = kWave / 2; o >= NR; o >>= 1) v += __shfl_down(v, o, kWave);
+  const int wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
+  if (ln < NR) lds[wv * NR + ln] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (int(threadIdx.x) < NR)
+    for (int k = 0; k < int(blockDim.x) / kWave; ++k) t += lds[k * NR + threadIdx.x];
+  __syncthreads();
+  return t;
+}
+
 // outer-loop products with the FP64 operator: w = A z (KIND SPMV64) or r = b - A x with
 // partial sums of squares per (block, rhs) (KIND DEFECT64)
 template <int B, int NR, class XI, int KIND, int KB, bool C16>
@@ -1374,26 +1390,23 @@ __global__ __launch_bounds__(kThreads) void k_bsell64(const BEntry* __restrict__
   __syncthreads();
   const BEntry& e = E[se];
   const bool on = !(active && !active[e.prob]);
-  double out = 0.0;
+  double out = 0.0, other = 0.0;
   if (on) {
     const SliceLane s = slice_lane<B, NR>(e.A, (blockIdx.x - e.first) * kSliceWaves + threadIdx.x / kWave,
                                           threadIdx.x % kWave);
-    if (KIND == BK_SPMV64)
+    if (KIND == BK_SPMV64) {
       out = spmv_slice<B, NR, VK_F64, XI, double, double, 0, KB, C16>(e.A, nullptr, static_cast<const XI*>(e.in1),
                                                                  static_cast<double*>(e.out), nullptr, s);
-    else
+    } else {
       out = spmv_slice<B, NR, VK_F64, double, double, double, 1, KB, C16>(e.A, static_cast<const double*>(e.in0),
                                                                      static_cast<const double*>(e.in1),
                                                                      static_cast<double*>(e.out), nullptr, s);
-  }
-  if (KIND == BK_DEFECT64) {
-    lds[threadIdx.x] = out * out;         // lane % NR is the right-hand side
-    __syncthreads();
-    if (threadIdx.x < NR) {
-      double t = 0.0;
-      for (int i = threadIdx.x; i < kThreads; i += NR) t += lds[i];
-      partials[int64_t(blockIdx.x) * NR + threadIdx.x] = t;
+      other = out;
     }
+  }
+  if (KIND == BK_DEFECT64) {               // lane % NR is the right-hand side
+    const double t = block_sum_rhs(out * other, NR, lds);
+    if (threadIdx.x < NR) partials[int64_t(blockIdx.x) * NR + threadIdx.x] = t;
   }
 }
 
@@ -1483,22 +1496,6 @@ __device__ __forceinline__ SegPos seg_pos(const BSegs& g) {
   return s;
 }
 
-// fixed-order sum over the block of values that belong to rhs q = tid % NR; thread q of
-// the result gets the sum for q
-__device__ __forceinline__ double block_sum_rhs(double v, int NR, double* lds) {
-  // inside each wave a fixed shuffle tree combines the lanes of equal lane % NR, then
-  // thread q adds the per-wave results in wave order
-  for (int o = kWave / 2; o >= NR; o >>= 1) v += __shfl_down(v, o, kWave);
-  const int wv = threadIdx.x / kWave, ln = threadIdx.x % kWave;
-  if (ln < NR) lds[wv * NR + ln] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (int(threadIdx.x) < NR)
-    for (int k = 0; k < int(blockDim.x) / kWave; ++k) t += lds[k * NR + threadIdx.x];
-  __syncthreads();
-  return t;
-}
-
 // every block of problem p computes the per-rhs sums of the problem's partials
 __device__ __forceinline__ void seg_sums(const double* __restrict__ pin, const SegPos& sp, int NR, double* lds,
                                          double* out) {
@@ -1506,12 +1503,13 @@ __device__ __forceinline__ void seg_sums(const double* __restrict__ pin, const S
   double t = 0.0;
   const int q = threadIdx.x % NR;
   const int step = int(blockDim.x) / NR;
-  for (int b0 = threadIdx.x / NR; b0 < sp.nb; b0 += step * U) {
+  const int first = sp.first, nb = sp.nb;
+  for (int b0 = threadIdx.x / NR; b0 < nb; b0 += step * U) {
     double v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int b = b0 + u * step;
-      v[u] = b < sp.nb ? pin[int64_t(sp.first + b) * NR + q] : 0.0;
+      v[u] = b < nb ? pin[int64_t(first + b) * NR + q] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) t += v[u];
@@ -1582,7 +1580,7 @@ __global__ __launch_bounds__(kThreads) void k_bmgs_step(BSegs g, double* __restr
 
 __global__ __launch_bounds__(kThreads) void k_bmgs_normalize(BSegs g, double* __restrict__ w,
                                                              const double* __restrict__ pin, double* __restrict__ H,
-                                                             int64_t hstride) {
+                                                             int64_t hstride, float* __restrict__ wc) {
   __shared__ double lds[kThreads];
   __shared__ double hq[64];
   const SegPos sp = seg_pos(g);
@@ -1592,7 +1590,14 @@ __global__ __launch_bounds__(kThreads) void k_bmgs_normalize(BSegs g, double* __
   __syncthreads();
   if (sp.lb == 0 && int(threadIdx.x) < g.NR) H[int64_t(sp.p * g.NR + threadIdx.x) * hstride] = hq[threadIdx.x];
   const double nrm = hq[threadIdx.x % g.NR];
-  if (nrm == 0.0) return;
+  if (nrm == 0.0) {
+    if (wc) {
+      const int64_t stride = int64_t(sp.nb) * blockDim.x;
+      for (int64_t i = int64_t(sp.lb) * blockDim.x + threadIdx.x; i < sp.len; i += stride)
+        wc[sp.off + i] = float(w[sp.off + i]);
+    }
+    return;
+  }
   constexpr int U = 4;
   const int64_t stride = int64_t(sp.nb) * blockDim.x;
   for (int64_t i0 = int64_t(sp.lb) * blockDim.x + threadIdx.x; i0 < sp.len; i0 += stride * U) {
@@ -1605,21 +1610,29 @@ __global__ __launch_bounds__(kThreads) void k_bmgs_normalize(BSegs g, double* __
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = i0 + u * stride;
-      if (i < sp.len) w[sp.off + i] = wv[u] / nrm;
+      if (i < sp.len) {
+        const double v = wv[u] / nrm;
+        w[sp.off + i] = v;
+        if (wc) wc[sp.off + i] = float(v);
+      }
     }
   }
 }
 
 __global__ __launch_bounds__(kThreads) void k_bscale(BSegs g, double* __restrict__ y, const double* __restrict__ x,
-                                                     const double* __restrict__ beta, const int* __restrict__ iact) {
+                                                     const double* __restrict__ beta, const int* __restrict__ iact,
+                                                     float* __restrict__ yc) {
   const SegPos sp = seg_pos(g);
   if (!sp.on) return;                      // uniform over the block
   const int inst = sp.p * g.NR + threadIdx.x % g.NR;
   const double bt = beta[inst];
   const bool on = iact[inst] && bt != 0.0;
   const int64_t stride = int64_t(sp.nb) * blockDim.x;
-  for (int64_t i = int64_t(sp.lb) * blockDim.x + threadIdx.x; i < sp.len; i += stride)
-    y[sp.off + i] = on ? x[sp.off + i] / bt : 0.0;
+  for (int64_t i = int64_t(sp.lb) * blockDim.x + threadIdx.x; i < sp.len; i += stride) {
+    const double v = on ? x[sp.off + i] / bt : 0.0;
+    y[sp.off + i] = v;
+    if (yc) yc[sp.off + i] = float(v);
+  }
 }
 
 template <class Z>
@@ -1814,14 +1827,14 @@ hipError_t launch_bmgs_step(const BSegs& g, double* w, const double* vi, const d
 }
 
 hipError_t launch_bmgs_normalize(const BSegs& g, double* w, const double* pin, double* H, int64_t hstride,
-                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_bmgs_normalize, g.n_blocks, kThreads, 0, s, g, w, pin, H, hstride);
+                                 hipStream_t s, float* wc) {
+  hipLaunchKernelGGL(k_bmgs_normalize, g.n_blocks, kThreads, 0, s, g, w, pin, H, hstride, wc);
   return hipGetLastError();
 }
 
 hipError_t launch_bscale(const BSegs& g, double* y, const double* x, const double* beta, const int* iact,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_bscale, g.n_blocks, kThreads, 0, s, g, y, x, beta, iact);
+                         hipStream_t s, float* yc) {
+  hipLaunchKernelGGL(k_bscale, g.n_blocks, kThreads, 0, s, g, y, x, beta, iact, yc);
   return hipGetLastError();
 }
 

@@ -1360,9 +1360,12 @@ int enqueue_batch_step(mg_batch* h, int j, hipStream_t s) {
   const int m = h->cfg.gmres_m;
   const int64_t N = h->Ntot;
   int rc;
-  if (h->xk != X_F64) MG_HIP(launch_convert(N, h->V + int64_t(j) * N, X_F64, h->btop, h->xk, s));
+  // the cycle-precision copy of v_j (btop) was written by the kernel that produced v_j
   for (const BLaunch& L : h->plan[j])
     if ((rc = run_launch(h, L, h->dE, h->pstep, nullptr, s))) return rc;
+  // w = A z_j.  (The first Gram-Schmidt dot is a separate pass here: the SpMV's blocks are
+  // far more numerous than the vector blocks, and re-summing their partials per block of
+  // the first step would cost more than the pass.)
   if ((rc = run_launch(h, h->spmv64[j], h->dE, h->pstep, nullptr, s))) return rc;
   double* w = h->V + int64_t(j + 1) * N;
   const int64_t hs = int64_t(m + 1) * m;
@@ -1374,7 +1377,8 @@ int enqueue_batch_step(mg_batch* h, int j, hipStream_t s) {
     const double* vn = (i < j) ? h->V + int64_t(i + 1) * N : nullptr;
     MG_HIP(launch_bmgs_step(sg, w, vi, vn, h->pvec[i & 1], h->pvec[(i + 1) & 1], Hj + i, hs, s));
   }
-  MG_HIP(launch_bmgs_normalize(sg, w, h->pvec[(j + 1) & 1], Hj + j + 1, hs, s));
+  float* wc = h->xk == X_F64 ? nullptr : static_cast<float*>(h->btop);
+  MG_HIP(launch_bmgs_normalize(sg, w, h->pvec[(j + 1) & 1], Hj + j + 1, hs, s, wc));
   MG_HIP(launch_bgivens(j, m, h->n_inst, h->H, h->cs, h->sn, h->g, h->st, h->tolv, h->kk, h->iact, s));
   return MG_OK;
 }
@@ -1599,7 +1603,8 @@ int solve_batch_impl(mg_batch* h, const double* b, double* x, mg_solve_stats* st
     if ((rc = to_dev(h->pact, pact.data(), P, s))) return rc;
     std::vector<int> pstep(pact);
     if ((rc = to_dev(h->pstep, pstep.data(), P, s))) return rc;
-    MG_HIP(launch_bscale(h->segs_act, h->V, h->rout, h->beta, h->iact, s));
+    MG_HIP(launch_bscale(h->segs_act, h->V, h->rout, h->beta, h->iact, s,
+                         h->xk == X_F64 ? nullptr : static_cast<float*>(h->btop)));
     MG_HIP(launch_binit(m, ni, h->g, h->beta, h->kk, s));
     int jl = 0;
     for (int j = 0; j < m; ++j) {
