@@ -111,11 +111,26 @@ __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int n
     for (int cc = 0; cc < B; ++cc) av[qq][cc] = Val<K>::load(A.val, vb + cc * W);
   }
   __builtin_amdgcn_sched_barrier(0);
+  if constexpr (B > 1 && NR == 1) {
+    // each lane gathers only its own component of the neighbour node (the B lanes of a
+    // node read one contiguous B-vector together) and takes the others from its node's
+    // lanes by wave shuffles
+    const int c = rl % B, base = rl - c;
+    XI xo[NB];
 #pragma unroll
-  for (int qq = 0; qq < NB; ++qq) {
-    const XI* xj = x + uint64_t(js[qq]) * (B * NR) + q;
+    for (int qq = 0; qq < NB; ++qq) xo[qq] = x[uint64_t(js[qq]) * B + c];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int cc = 0; cc < B; ++cc) xv[qq][cc] = xj[cc * NR];
+    for (int qq = 0; qq < NB; ++qq)
+#pragma unroll
+      for (int cc = 0; cc < B; ++cc) xv[qq][cc] = __shfl(xo[qq], base + cc, kWave);
+  } else {
+#pragma unroll
+    for (int qq = 0; qq < NB; ++qq) {
+      const XI* xj = x + uint64_t(js[qq]) * (B * NR) + q;
+#pragma unroll
+      for (int cc = 0; cc < B; ++cc) xv[qq][cc] = xj[cc * NR];
+    }
   }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
