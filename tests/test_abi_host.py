@@ -100,3 +100,36 @@ def test_batch_setup_rejects_unsupported_requests(levels, bad):
     with pytest.raises(mg.MGError) as e:
         mg.Batch(problems, cfg, nrhs=nrhs, stream=C.c_void_p(0))
     assert e.value.code == want
+
+
+def test_empty_inputs_rejected(levels):
+    """A level without nodes and a hierarchy without levels are refused with MG_EINVAL
+    before any device work."""
+    import copy
+    import ctypes as C
+    e = copy.deepcopy(levels[0])
+    e.n = 0
+    e.rowptr = np.zeros(1, np.int32)
+    e.col = np.zeros(0, np.int32)
+    e.val = np.zeros((0, 1, 1))
+    e.mask = np.zeros((0, 1), np.uint8)
+    assert mg.validate_level(e, None) == -1
+    L = mg.lib()
+    h = C.c_void_p()
+    arr = (mg.LevelIn * 1)()
+    cfg = mg.config_from(W.c2_td())
+    assert L.mg_setup_hierarchy(arr, 0, C.byref(cfg), 0, None, C.byref(h)) == -1
+    assert not h.value
+
+
+@pytest.mark.parametrize("field,value", [("omega", 0.0), ("nu1", -1), ("gmres_m", 0), ("gmres_m", 65),
+                                         ("precision", 7), ("outer", 3), ("rtol", -1.0)])
+def test_invalid_config_rejected(levels, field, value):
+    """Invalid solver settings are refused by setup before any device work."""
+    import ctypes as C
+    cfg = mg.config_from(W.c2_td())
+    setattr(cfg, field, value)
+    arr, keep = mg.level_structs(levels)
+    h = C.c_void_p()
+    assert mg.lib().mg_setup_hierarchy(arr, len(levels), C.byref(cfg), 0, None, C.byref(h)) == -1
+    assert mg.last_error()
