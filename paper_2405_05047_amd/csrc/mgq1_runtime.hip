@@ -696,14 +696,16 @@ int solve_impl(mg_handle* h, const double* b, double* x, mg_solve_stats* st, voi
   const int64_t N = T.N;
   mg_solve_stats S{};
   int rc;
-  // ||b||
+  // ||b|| (to dsc[4]) and the initial defect r = b - A x with ||r|| (to dsc[0]), read
+  // back with one synchronisation
   MG_HIP(launch_dot_partials(N, b, nullptr, h->pv[0], s));
-  MG_HIP(launch_finish(h->pv[0], reduction_grid(N), h->dsc + 0, 1, s));
-  if ((rc = read_scalars(h, h->dsc, 1, s))) return rc;
-  const double bn = h->hs[0];
+  MG_HIP(launch_finish(h->pv[0], reduction_grid(N), h->dsc + 4, 1, s));
+  MG_HIP(launch_spmv(T.A64, b, x, h->rout, nullptr, X_F64, X_F64, 1, h->pbig, s));
+  MG_HIP(launch_finish(h->pbig, spmv_grid(T.A64), h->dsc + 0, 1, s));
+  if ((rc = read_scalars(h, h->dsc, 5, s))) return rc;
+  const double bn = h->hs[4];
   const double tol = c.rtol * bn;
   const int limit = fixed > 0 ? fixed : c.maxit;
-  if ((rc = outer_defect(h, b, x, s))) return rc;
   double beta = h->hs[0];
   S.res0 = beta;
   int status = MG_OK;
