@@ -144,10 +144,10 @@ int mg_level_info(const mg_handle* h, int32_t level, int32_t* n_nodes, int32_t* 
 int32_t mg_num_levels(const mg_handle* h);
 
 /* Slot batch used on level `level`, the bytes per stored column index of its operators
- * (2 when every column differs from its row's node by less than 2^15 and the kernels read
- * 16-bit differences, else 4), and the sweep times (microseconds per launch) that the
- * setup measured for the default and the other slot batch (0 when slot_batch was fixed).
- * Any output pointer may be NULL. */
+ * (2 when, in every slice, each block slot's columns span less than 2^16 and the kernels
+ * read 16-bit offsets from a per-slot base, else 4), and the sweep times (microseconds per
+ * launch) that the setup measured for the default and the other slot batch (0 when
+ * slot_batch was fixed).  Any output pointer may be NULL. */
 int mg_level_tuning(const mg_handle* h, int32_t level, int32_t* slot_batch, int32_t* col_bytes,
                     double* us_default, double* us_other);
 

@@ -31,8 +31,8 @@ struct SellDev {
   const int8_t* rexp = nullptr;     // nslices * 64 power-of-two row exponents (F16 / BF16)
   int kind = VK_F64;
   int kb = 0;                       // block slots per load batch (0: the default for B)
-  const int16_t* col16 = nullptr;   // col - (row node) as 16 bits when every difference
-                                    // fits (NULL: the kernels read col)
+  const uint16_t* col16 = nullptr;  // col - colbase[slot] as 16 bits when every slot's
+  const int32_t* colbase = nullptr; // columns span less than 2^16 (NULL: the kernels read col)
 };
 
 // the two slot-batch sizes the slice kernels are built for (default, alternative)

@@ -83,10 +83,11 @@ template <> struct Val<VK_BF16> {
 // x load of the batch, then the FMAs, so the batch costs two memory round trips.  NB is a
 // compile-time constant, so no load sits in a conditional block (a conditional load whose
 // result is widened inside the block would force a wait per slot).
-// C16: column indices are stored as 16-bit differences to the row's own node.
+// C16: column indices are stored as 16-bit offsets from a per-slot base (the smallest
+// column of that slot in the slice, wave-uniform, so a scalar load).
 template <bool C16>
-__device__ __forceinline__ unsigned slot_col(const SellDev& A, int64_t idx, int node) {
-  if constexpr (C16) return unsigned(node + int(__builtin_nontemporal_load(A.col16 + idx)));
+__device__ __forceinline__ unsigned slot_col(const SellDev& A, int k, int64_t idx) {
+  if constexpr (C16) return unsigned(A.colbase[k]) + unsigned(__builtin_nontemporal_load(A.col16 + idx));
   else return unsigned(__builtin_nontemporal_load(A.col + idx));
 }
 
@@ -103,7 +104,7 @@ __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int n
   VR av[NB][B];
   XI xv[NB][B];
 #pragma unroll
-  for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16>(A, int64_t(k + qq) * R + r, node);
+  for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16>(A, k + qq, int64_t(k + qq) * R + r);
 #pragma unroll
   for (int qq = 0; qq < NB; ++qq) {
     const int64_t vb = int64_t(k + qq) * B * W + rl;
@@ -151,7 +152,7 @@ __device__ __forceinline__ void sell_batch_z(const SellDev& A, int k, int rl, in
   VR av[NB];
   X sv[NB], bv[NB];
 #pragma unroll
-  for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16>(A, int64_t(k + qq) * kWave + rl, node);
+  for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16>(A, k + qq, int64_t(k + qq) * kWave + rl);
 #pragma unroll
   for (int qq = 0; qq < NB; ++qq) av[qq] = Val<K>::load(A.val, int64_t(k + qq) * kWave + rl);
   __builtin_amdgcn_sched_barrier(0);

@@ -402,25 +402,34 @@ int upload_sell(DevOwner* h, const HostSell& S, int kind, SellDev& D, hipStream_
   if ((rc = upload(h, &cl, S.col, s))) return rc;
   D.sptr = sp;
   D.col = cl;
-  // 16-bit column differences to the row's node, when every one fits (rows past the end
-  // of the last slice store 0)
+  // 16-bit column offsets from a per-slot base (the smallest column of the slot over the
+  // slice's rows), when every slot's columns span less than 2^16; rows past the end of the
+  // last slice store offset 0
   bool fits = true;
-  std::vector<int16_t> c16(S.col.size(), 0);
+  std::vector<uint16_t> c16(S.col.size(), 0);
+  std::vector<int32_t> base(size_t(S.slots), 0);
   for (int32_t sl = 0; sl < S.nslices && fits; ++sl)
-    for (int64_t k = S.sptr[sl]; k < S.sptr[sl + 1] && fits; ++k)
-      for (int r = 0; r < S.R; ++r) {
-        const int64_t node = int64_t(sl) * S.R + r;
-        if (node >= S.n) continue;
-        const int64_t d = int64_t(S.col[size_t(k) * S.R + r]) - node;
-        if (d < -32768 || d > 32767) { fits = false; break; }
-        c16[size_t(k) * S.R + r] = int16_t(d);
-      }
+    for (int64_t k = S.sptr[sl]; k < S.sptr[sl + 1] && fits; ++k) {
+      int32_t lo = INT32_MAX, hi = INT32_MIN;
+      for (int r = 0; r < S.R; ++r)
+        if (int64_t(sl) * S.R + r < S.n) {
+          lo = std::min(lo, S.col[size_t(k) * S.R + r]);
+          hi = std::max(hi, S.col[size_t(k) * S.R + r]);
+        }
+      if (int64_t(hi) - lo > 65535) { fits = false; break; }
+      base[size_t(k)] = lo;
+      for (int r = 0; r < S.R; ++r)
+        if (int64_t(sl) * S.R + r < S.n) c16[size_t(k) * S.R + r] = uint16_t(S.col[size_t(k) * S.R + r] - lo);
+    }
   const char* off = std::getenv("MGQ1_NO_COL16");
   if (fits && !(off && std::atoi(off) != 0)) {
-    int16_t* c;
+    uint16_t* c;
+    int32_t* bs;
     if ((rc = upload(h, &c, c16, s))) return rc;
+    if ((rc = upload(h, &bs, base, s))) return rc;
     MG_HIP(hipStreamSynchronize(s));
     D.col16 = c;
+    D.colbase = bs;
   }
   const size_t nv = S.val.size();
   if (kind == VK_F64) {
