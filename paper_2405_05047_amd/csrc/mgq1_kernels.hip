@@ -6,22 +6,33 @@
 // chains of dependent loads on small levels, and deterministic reductions (no atomics).
 //
 //   SELL slice kernels (defect / SpMV, smoothing sweep): one wavefront per slice of
-//   64/B nodes; lane = node*B + component owns one scalar row.  Block slots are consumed
-//   in batches: the column indices of a batch are loaded first, then all value and x
-//   loads of the batch are issued together, then the FMAs run, so a row of 9 (2D) or 27
-//   (3D) blocks costs 2-8 memory round trips instead of one per block.  Each value load of
-//   a wave is one contiguous 512-byte (FP64) stream.  The smoother exchanges the B residual
-//   components of a node across its lanes with wave shuffles and applies the stored block
-//   inverse.  Workgroup ids are remapped so that each XCD (round-robin dispatch over 8
-//   XCDs) walks a contiguous range of slices and keeps its own L2 warm.
+//   64/(B*NR) nodes; lane = (node*B + component)*NR + rhs owns one scalar row of one
+//   right-hand side.  Block slots are consumed in batches of KB (chosen per level by the
+//   setup's autotuner): column indices and values of a batch are loaded first, then the x
+//   gathers, then the FMAs in slot order, as straight-line code between scheduling
+//   barriers, so a row of 9 (2D) or 27 (3D) blocks costs a few memory round trips instead
+//   of one per block.  Each value load of a wave is one contiguous stream.  For block
+//   operators each lane gathers only its own component of a neighbour node and takes the
+//   others from the node's lanes by wave shuffles; the smoother exchanges the B residual
+//   components of a node the same way and applies the stored block inverse.  Column
+//   indices are 32-bit, or 16-bit offsets from a per-slot base where they fit.
+//   Workgroup ids are remapped so that each XCD (round-robin dispatch over 8 XCDs) walks a
+//   contiguous range of slices and keeps its own L2 warm.
+//
+//   Transfers: the scalar P~ and R = P~^T in the same sliced layout over node rows, applied
+//   per component with the constraint masks (pull-style, no atomics).
 //
 //   Reductions: every block writes one partial sum; the consumer (the next kernel in the
 //   chain) re-sums all partials in a fixed order in every block, so the result is
 //   deterministic, identical in all blocks and needs no atomics (same-address atomics
 //   serialise at roughly 30 ns each).
 //
-//   Tail kernel: the levels below a size threshold and the coarse solve run as one
-//   single-workgroup launch with workgroup barriers between the steps of the V-cycle.
+//   Tail kernel (optional, off by default): the levels below a size threshold and the
+//   coarse solve as one single-workgroup launch with barriers between the steps.
+//
+//   Batched form: the same slice bodies over the entries of many problems per launch
+//   (each block finds its entry by binary search over the entries' first blocks), and
+//   segmented Krylov kernels (each block belongs to one problem's vector segment).
 //
 // Paper correspondence: smoother x + omega S (b - A x), transfers P and R = P^T and the
 // coarse solve (Sec. 4.1 "Geometric Multigrid CUDA", Algorithm "Geometric multigrid
