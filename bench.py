@@ -45,12 +45,17 @@ WORKLOADS = {
     "c4b": (lambda: W.c4_oseen(rounds=6, tall=True).with_(coarse_level=2),
             "3D Oseen step Q1/Q1 129x129x65 nodes, 4x4 blocks, 7-level hierarchy with the exact coarse solve "
             "on level 2 (1,620 DoFs), FGMRES(10) + V(2,2) point-Vanka, rtol 1e-8"),
+    "c3f": (lambda: W.c3_adaptive("face", 6),
+            "3D elasticity Q1 on the face-refined cube mesh (8^3 coarse cubes, 5 rounds refining the cells "
+            "next to the face x = 0), 683,741 nodes x 3 components with edge and face hanging nodes, 6-level "
+            "hierarchy with the exact coarse solve on the 9^3-node level, FGMRES(10) + V(2,2) nodal "
+            "block-Jacobi w=0.6, rtol 1e-8"),
 }
 
 
 def sweep_bytes(n, b, nnzb, col_bytes=4):
     """Algorithmic bytes of one FP64 smoothing sweep: A values + column indices (4 B, or 2 B
-    when the operator is stored with 16-bit column differences) + int32 row pointers, x
+    when the operator is stored with 16-bit offsets from a per-slot base) + int32 row pointers, x
     and b read, x_out written, nodal b x b inverse blocks read."""
     return nnzb * (b * b * 8 + col_bytes) + 4 * (n + 1) + 3 * n * b * 8 + n * b * b * 8
 

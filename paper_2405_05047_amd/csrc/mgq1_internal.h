@@ -24,6 +24,8 @@ constexpr int kMaxRedBlocks = 2048;   // grid (= partial count) of the vector re
 // sptr[slice]).  Padding slots hold value 0 and the row's own node as column.
 struct SellDev {
   int32_t n = 0, B = 1, R = 64, nslices = 0;
+  int32_t ell = 0;                  // > 0: every slice has this width (sptr[s] = s * ell), so
+                                    // the kernels need no load for the slot range
   int64_t slots = 0;
   const int32_t* sptr = nullptr;    // nslices + 1
   const int32_t* col = nullptr;     // slots * R
@@ -33,6 +35,8 @@ struct SellDev {
   int kb = 0;                       // block slots per load batch (0: the default for B)
   const uint16_t* col16 = nullptr;  // col - colbase[slot] as 16 bits when every slot's
   const int32_t* colbase = nullptr; // columns span less than 2^16 (NULL: the kernels read col)
+  const int32_t* perm = nullptr;    // node at row position slice*R + r (NULL: the position
+                                    // itself); rows sorted by length inside windows of slices
 };
 
 // the two slot-batch sizes the slice kernels are built for (default, alternative)
@@ -55,6 +59,7 @@ struct CsrDev {
 // padded slots carry weight 0 and a column of their own row
 struct TSellDev {
   int32_t nrows = 0, ncols = 0, R = 64, nslices = 0;
+  int32_t ell = 0;                  // > 0: uniform slice width, as in SellDev
   const int32_t* sptr = nullptr;
   const int32_t* col = nullptr;
   const void* w = nullptr;

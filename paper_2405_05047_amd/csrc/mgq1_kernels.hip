@@ -102,6 +102,19 @@ __device__ __forceinline__ unsigned slot_col(const SellDev& A, int k, int64_t id
   else return unsigned(__builtin_nontemporal_load(A.col + idx));
 }
 
+// slot range [k, k1) of slice su (wave-uniform): computed for uniform-width slices, else
+// read from the slice pointers (one dependent round trip before the first slot load)
+template <class M>
+__device__ __forceinline__ void slot_range(const M& A, int su, int& k, int& k1) {
+  if (A.ell > 0) {
+    k = su * A.ell;
+    k1 = k + A.ell;
+  } else {
+    k = A.sptr[su];
+    k1 = A.sptr[su + 1];
+  }
+}
+
 template <int NB, int B, int NR, int K, class XI, class T, bool C16>
 __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int node, int rl, int q,
                                            const XI* __restrict__ x, T& acc) {
@@ -222,8 +235,8 @@ __device__ __forceinline__ T sell_dot(const SellDev& A, int slice, int lane, boo
   // in scalar registers
   slice = __builtin_amdgcn_readfirstlane(slice);
   const int node = slice * R + r;
-  const int k1 = A.sptr[slice + 1];
-  int k = A.sptr[slice];
+  int k, k1;
+  slot_range(A, slice, k, k1);
   for (; k + KB <= k1; k += KB) sell_batch<KB, B, NR, K, XI, T, C16>(A, k, r, node, rl, q, x, acc);
   sell_rest<KB - 1, B, NR, K, XI, T, C16>(k1 - k, A, k, r, node, rl, q, x, acc);
   if (K == VK_F16 || K == VK_BF16) acc *= T(ldexpf(1.0f, A.rexp[int64_t(slice) * W + rl]));
@@ -286,9 +299,10 @@ __device__ __forceinline__ SliceLane slice_lane(const SellDev& A, int slice, int
   SliceLane s;
   s.slice = slice;
   s.lane = lane;
-  s.node = slice * R + lane / (B * NR);
-  s.dof = int64_t(slice) * R * B * NR + lane;
-  s.valid = slice < A.nslices && lane < R * B * NR && s.node < A.n;
+  const int pos = slice * R + lane / (B * NR);   // row position of the lane's node
+  s.valid = slice < A.nslices && lane < R * B * NR && pos < A.n;
+  s.node = (A.perm != nullptr && s.valid) ? A.perm[pos] : pos;
+  s.dof = int64_t(s.node) * B * NR + lane % (B * NR);
   return s;
 }
 
@@ -448,19 +462,20 @@ __device__ __forceinline__ void tsell_lane(const TSellDev& M, int slice, int lan
   if (slice >= M.nslices || lane >= R * B * NR || node >= M.nrows) return;
   const int64_t dof = int64_t(node) * B + c;
   const int64_t t = dof * NR + q;
-  const uint8_t masked = mrow[dof];        // issued together with the slice bounds
+  // the row mask and (prolongation) the old value are loaded with the first slots; masked
+  // rows run the sum too (their columns are valid indices) and drop it at the end, so no
+  // branch waits for the mask before the slot loads are issued
+  const uint8_t masked = mrow[dof];
+  X old = X(0);
+  if (MODE == 1) old = out[t];
   const int su = __builtin_amdgcn_readfirstlane(slice);
-  const int k1 = M.sptr[su + 1];
-  int k = M.sptr[su];
-  if (masked) {
-    if (MODE == 0) out[t] = X(0);
-    return;
-  }
+  int k, k1;
+  slot_range(M, su, k, k1);
   T acc = T(0);
   for (; k + KB <= k1; k += KB) tsell_batch<KB, B, NR, X, T, WT, MC>(M, k, r, c, q, in, mcol, acc);
   tsell_rest<KB - 1, B, NR, X, T, WT, MC>(k1 - k, M, k, r, c, q, in, mcol, acc);
-  if (MODE == 0) out[t] = X(acc);
-  else out[t] = X(T(out[t]) + acc);
+  if (MODE == 0) out[t] = masked ? X(0) : X(acc);
+  else if (!masked) out[t] = X(T(old) + acc);
 }
 
 template <int B, int NR, class X, class T, class WT, bool MC, int MODE>
@@ -508,8 +523,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep2z(SellDev A, const X* __rest
   if (slice >= A.nslices || i >= A.n) return;
   const X si = S[i], bi = b[i];              // issued with the slice bounds
   const int su = __builtin_amdgcn_readfirstlane(slice);
-  const int k1 = A.sptr[su + 1];
-  int k = A.sptr[su];
+  int k, k1;
+  slot_range(A, su, k, k1);
   T acc = T(0);
   const int node = int(i);
   for (; k + KB <= k1; k += KB) sell_batch_z<KB, K, X, T, C16>(A, k, lane, node, S, b, omega, acc);
@@ -530,10 +545,11 @@ __global__ __launch_bounds__(kThreads) void k_sweep0(SellDev A, const X* __restr
 
 
 // x = Ainv b, one wavefront per row (Ainv row-major, FP64)
-template <class XI, class XO>
+// U row chunks of 64 elements have their loads issued together; every lane sums its
+// elements in increasing column order whatever U is, so U does not change the result
+template <class XI, class XO, int U = 8>
 __device__ __forceinline__ void gemv_row(int n, const double* __restrict__ Ainv, const XI* __restrict__ b,
                                          XO* __restrict__ x, int i, int lane) {
-  constexpr int U = 8;                     // row chunks whose loads are issued together
   double acc = 0.0;
   const double* row = Ainv + int64_t(i) * n;
   for (int k0 = lane; k0 < n; k0 += kWave * U) {
@@ -555,7 +571,7 @@ template <class XI, class XO>
 __global__ __launch_bounds__(kThreads) void k_coarse_gemv(int n, const double* __restrict__ Ainv,
                                                           const XI* __restrict__ b, XO* __restrict__ x) {
   const int i = blockIdx.x * kSliceWaves + threadIdx.x / kWave;
-  if (i < n) gemv_row<XI, XO>(n, Ainv, b, x, i, threadIdx.x % kWave);
+  if (i < n) gemv_row<XI, XO, 32>(n, Ainv, b, x, i, threadIdx.x % kWave);   // rows up to 2048 in one pass
 }
 
 // ------------------------------------------------------------------ tail kernel
@@ -717,9 +733,10 @@ template <int B, int NR, class ST>
 __global__ __launch_bounds__(256) void k_block_invert(SellDev A, ST* __restrict__ S, int* flag) {
   constexpr int R = kWave / (B * NR);
   constexpr int W = kWave / NR;
-  const int node = blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= A.n) return;
-  const int slice = node / R, r = node % R;
+  const int pos = blockIdx.x * blockDim.x + threadIdx.x;   // row position; S in lane layout
+  if (pos >= A.n) return;
+  const int node = A.perm ? A.perm[pos] : pos;
+  const int slice = pos / R, r = pos % R;
   const double* val = static_cast<const double*>(A.val);
   int kd = -1;
   for (int k = A.sptr[slice]; k < A.sptr[slice + 1]; ++k)
@@ -1122,7 +1139,7 @@ static hipError_t sweep0_b(const SellDev& A, const void* S, const void* b, void*
 
 hipError_t launch_sweep2z(const SellDev& A, const void* S, const void* b, void* xo, double omega, int xk,
                           hipStream_t s) {
-  if (A.B != 1) return hipErrorInvalidValue;
+  if (A.B != 1 || A.perm != nullptr) return hipErrorInvalidValue;   // node order = lane order
   const unsigned g = slice_grid(A.nslices);
   if (g == 0) return hipSuccess;
 #define MGQ1_S2Z4(KIND, X, T, KB, C16)                                                              \
@@ -1358,14 +1375,27 @@ hipError_t launch_init_g(int m, double* g, const double* beta, hipStream_t s) {
 // ======================================================================== batched form
 namespace {
 
-__device__ __forceinline__ int find_entry(const BEntry* __restrict__ E, int n, int blk) {
-  int lo = 0, hi = n - 1;                 // largest e with E[e].first <= blk
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (E[mid].first <= blk) lo = mid;
-    else hi = mid - 1;
+// the entry of block blk: the largest e with E[e].first <= blk (entries are sorted by
+// first and E[0].first = 0).  Called by the whole first wave: each lane tests one entry, so
+// 64 entries cost one round trip instead of a chain of dependent loads.
+__device__ __forceinline__ int find_entry_wave(const BEntry* __restrict__ E, int n, int blk) {
+  const int lane = threadIdx.x % kWave;
+  int cnt = 0;
+  for (int e0 = 0; e0 < n; e0 += kWave) {
+    const int e = e0 + lane;
+    const bool le = e < n && E[e].first <= blk;
+    cnt += __popcll(__ballot(le));
+    if (cnt < e0 + kWave) break;           // this chunk holds the first entry past blk
   }
-  return lo;
+  return cnt - 1;
+}
+
+__device__ __forceinline__ void block_entry(const BEntry* __restrict__ E, int n, int& se) {
+  if (threadIdx.x < kWave) {
+    const int e = find_entry_wave(E, n, blockIdx.x);
+    if (threadIdx.x == 0) se = e;
+  }
+  __syncthreads();
 }
 
 // V-cycle steps on slices (sweep0, sweep, masked defect) for every problem of the batch
@@ -1373,8 +1403,7 @@ template <int B, int NR, int K, class X, class T, int KIND, int KB, bool C16>
 __global__ __launch_bounds__(kThreads) void k_bsell(const BEntry* __restrict__ E, int ne, T omega,
                                                     const int* __restrict__ active) {
   __shared__ int se;
-  if (threadIdx.x == 0) se = find_entry(E, ne, blockIdx.x);
-  __syncthreads();
+  block_entry(E, ne, se);
   const BEntry& e = E[se];
   if (active && !active[e.prob]) return;
   const SliceLane s = slice_lane<B, NR>(e.A, (blockIdx.x - e.first) * kSliceWaves + threadIdx.x / kWave,
@@ -1413,8 +1442,7 @@ __global__ __launch_bounds__(kThreads) void k_bsell64(const BEntry* __restrict__
                                                       const int* __restrict__ active, double* __restrict__ partials) {
   __shared__ int se;
   __shared__ double lds[kThreads];
-  if (threadIdx.x == 0) se = find_entry(E, ne, blockIdx.x);
-  __syncthreads();
+  block_entry(E, ne, se);
   const BEntry& e = E[se];
   const bool on = !(active && !active[e.prob]);
   double out = 0.0, other = 0.0;
@@ -1441,8 +1469,7 @@ template <int B, int NR, class X, class T, int KIND>
 __global__ __launch_bounds__(kThreads) void k_belem(const BEntry* __restrict__ E, int ne,
                                                     const int* __restrict__ active) {
   __shared__ int se;
-  if (threadIdx.x == 0) se = find_entry(E, ne, blockIdx.x);
-  __syncthreads();
+  block_entry(E, ne, se);
   const BEntry& e = E[se];
   if (active && !active[e.prob]) return;
   const int64_t t = int64_t(blockIdx.x - e.first) * kThreads + threadIdx.x;
@@ -1455,8 +1482,7 @@ template <int B, int NR, class X, class T, int KIND>
 __global__ __launch_bounds__(kThreads) void k_btsell(const BEntry* __restrict__ E, int ne,
                                                      const int* __restrict__ active) {
   __shared__ int se;
-  if (threadIdx.x == 0) se = find_entry(E, ne, blockIdx.x);
-  __syncthreads();
+  block_entry(E, ne, se);
   const BEntry& e = E[se];
   if (active && !active[e.prob]) return;
   const int slice = (blockIdx.x - e.first) * kSliceWaves + threadIdx.x / kWave;
@@ -1477,8 +1503,7 @@ template <int NR, class X>
 __global__ __launch_bounds__(kThreads) void k_bcoarse(const BEntry* __restrict__ E, int ne,
                                                       const int* __restrict__ active) {
   __shared__ int se;
-  if (threadIdx.x == 0) se = find_entry(E, ne, blockIdx.x);
-  __syncthreads();
+  block_entry(E, ne, se);
   const BEntry& e = E[se];
   if (active && !active[e.prob]) return;
   const int i = (blockIdx.x - e.first) * kSliceWaves + threadIdx.x / kWave;

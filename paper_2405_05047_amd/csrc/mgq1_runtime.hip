@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -171,12 +172,70 @@ uint16_t to_bf16_bits(double v) {
 }
 
 struct HostSell {
-  int32_t n = 0, B = 1, R = 64, W = 64, nslices = 0;
+  int32_t n = 0, B = 1, R = 64, W = 64, nslices = 0, ell = 0;
   int64_t slots = 0;
+  std::vector<int32_t> perm;                        // node at each row position (empty: itself)
   std::vector<int32_t> sptr, col;
   std::vector<double> val;                          // slots * B * W
   std::vector<int8_t> rexp;                         // nslices * W
 };
+
+// Uniform slice width (plain ELL) when padding every slice to the widest one costs little:
+// at most 2% more slots, or at most 12.5% on levels of up to 2^18 scalar rows, whose kernels
+// wait on memory latency rather than bandwidth; the kernels then compute a slice's slot
+// range instead of loading it.  Padding slots contribute exact zeros, so the results are
+// those of the variable widths (MGQ1_NO_ELL=1 keeps those, for tests).
+bool want_ell(int64_t slots, int64_t nslices, int32_t maxw, int64_t rows) {
+  const char* off = std::getenv("MGQ1_NO_ELL");
+  if (off && std::atoi(off) != 0) return false;
+  const int64_t ell = nslices * int64_t(maxw);
+  if (maxw <= 0 || ell >= (int64_t(1) << 31)) return false;
+  return ell * 50 <= slots * 51 || (rows <= (int64_t(1) << 18) && ell * 8 <= slots * 9);
+}
+
+// slice pointers of uniform width w
+void make_uniform(std::vector<int32_t>& sptr, int32_t nslices, int32_t w) {
+  for (int32_t s = 0; s <= nslices; ++s) sptr[s] = s * w;
+}
+
+int32_t max_width(const std::vector<int32_t>& sptr, int32_t nslices) {
+  int32_t w = 0;
+  for (int32_t s = 0; s < nslices; ++s) w = std::max(w, sptr[s + 1] - sptr[s]);
+  return w;
+}
+
+// Rows of block systems (B >= 2) are sorted by length, longest first and otherwise in node
+// order, inside windows of kSortSlices slices when that saves at least 3% of the slots: on
+// adaptive meshes a constrained node (one diagonal block) or a master next to hanging nodes
+// (up to 43 blocks in 3D) would otherwise set the width of a whole slice.  Every row keeps
+// its slot order, so its sum is unchanged; only the lane that computes it moves.  One
+// component per node is left in node order (the fused two-sweep kernel relies on it).
+// MGQ1_NO_SORT=1 keeps the node order everywhere (tests).
+constexpr int kSortSlices = 16;
+
+std::vector<int32_t> sorted_positions(const HostLevel& L, int R) {
+  std::vector<int32_t> perm;
+  const char* off = std::getenv("MGQ1_NO_SORT");
+  if (L.B < 2 || L.n == 0 || (off && std::atoi(off) != 0)) return perm;
+  auto len = [&](int32_t i) { return L.rowptr[i + 1] - L.rowptr[i]; };
+  auto slots_of = [&](const std::vector<int32_t>* p) {
+    int64_t t = 0;
+    for (int64_t s0 = 0; s0 < L.n; s0 += R) {
+      int32_t w = 0;
+      for (int64_t q = s0; q < std::min<int64_t>(s0 + R, L.n); ++q) w = std::max(w, len(p ? (*p)[q] : int32_t(q)));
+      t += w;
+    }
+    return t;
+  };
+  perm.resize(size_t(L.n));
+  std::iota(perm.begin(), perm.end(), 0);
+  const int64_t win = int64_t(R) * kSortSlices;
+  for (int64_t w0 = 0; w0 < L.n; w0 += win)
+    std::stable_sort(perm.begin() + w0, perm.begin() + std::min<int64_t>(w0 + win, L.n),
+                     [&](int32_t a, int32_t c) { return len(a) > len(c); });
+  if (slots_of(&perm) * 100 > slots_of(nullptr) * 97) perm.clear();
+  return perm;
+}
 
 // sliced ELL with slices of R = 64 / (B * NR) nodes and padded row-lane stride W = 64 / NR
 HostSell build_sell(const HostLevel& L, int NR = 1) {
@@ -186,14 +245,23 @@ HostSell build_sell(const HostLevel& L, int NR = 1) {
   S.R = kWave / (L.B * NR);
   S.W = kWave / NR;
   S.nslices = (L.n + S.R - 1) / S.R;
+  S.perm = sorted_positions(L, S.R);
+  auto node_at = [&](int64_t pos) -> int64_t { return S.perm.empty() ? pos : S.perm[size_t(pos)]; };
   S.sptr.assign(size_t(S.nslices) + 1, 0);
   for (int32_t s = 0; s < S.nslices; ++s) {
     int32_t w = 0;
     for (int r = 0; r < S.R; ++r) {
-      const int64_t i = int64_t(s) * S.R + r;
-      if (i < L.n) w = std::max(w, L.rowptr[i + 1] - L.rowptr[i]);
+      const int64_t pos = int64_t(s) * S.R + r;
+      if (pos >= L.n) continue;
+      const int64_t i = node_at(pos);
+      w = std::max(w, L.rowptr[i + 1] - L.rowptr[i]);
     }
     S.sptr[s + 1] = S.sptr[s] + w;
+  }
+  const int32_t maxw = max_width(S.sptr, S.nslices);
+  if (want_ell(S.sptr[S.nslices], S.nslices, maxw, int64_t(L.n) * L.B)) {
+    S.ell = maxw;
+    make_uniform(S.sptr, S.nslices, maxw);
   }
   S.slots = S.sptr[S.nslices];
   const int B = L.B, W = S.W;
@@ -203,8 +271,9 @@ HostSell build_sell(const HostLevel& L, int NR = 1) {
   for (int32_t s = 0; s < S.nslices; ++s) {
     const int32_t w = S.sptr[s + 1] - S.sptr[s];
     for (int r = 0; r < S.R; ++r) {
-      const int64_t i = int64_t(s) * S.R + r;
-      if (i >= L.n) continue;
+      const int64_t pos = int64_t(s) * S.R + r;
+      if (pos >= L.n) continue;
+      const int64_t i = node_at(pos);
       const int32_t len = L.rowptr[i + 1] - L.rowptr[i];
       std::vector<double> mx(B, 0.0);
       for (int32_t k = 0; k < w; ++k) {
@@ -238,7 +307,7 @@ struct CsrHost {
 // of R = 64 / (B * NR) node rows, slice width = longest row, padded slots weight 0 and a
 // column of their own row
 struct TSellHost {
-  int32_t nrows = 0, ncols = 0, R = 64, nslices = 0;
+  int32_t nrows = 0, ncols = 0, R = 64, nslices = 0, ell = 0;
   std::vector<int32_t> sptr, col;
   std::vector<double> w;
 };
@@ -257,6 +326,11 @@ TSellHost build_tsell(const CsrHost& C, int B, int NR) {
       if (i < C.nrows) wd = std::max(wd, C.rowptr[i + 1] - C.rowptr[i]);
     }
     S.sptr[sl + 1] = S.sptr[sl] + wd;
+  }
+  const int32_t maxw = max_width(S.sptr, S.nslices);
+  if (want_ell(S.sptr[S.nslices], S.nslices, maxw, int64_t(C.nrows) * B)) {
+    S.ell = maxw;
+    make_uniform(S.sptr, S.nslices, maxw);
   }
   const int64_t slots = S.sptr[S.nslices];
   S.col.assign(size_t(slots) * S.R, 0);
@@ -393,6 +467,7 @@ int upload_sell(DevOwner* h, const HostSell& S, int kind, SellDev& D, hipStream_
   D.B = S.B;
   D.R = S.R;
   D.nslices = S.nslices;
+  D.ell = S.ell;
   D.slots = S.slots;
   D.kind = kind;
   int rc;
@@ -402,6 +477,11 @@ int upload_sell(DevOwner* h, const HostSell& S, int kind, SellDev& D, hipStream_
   if ((rc = upload(h, &cl, S.col, s))) return rc;
   D.sptr = sp;
   D.col = cl;
+  if (!S.perm.empty()) {
+    int32_t* pm;
+    if ((rc = upload(h, &pm, S.perm, s))) return rc;
+    D.perm = pm;
+  }
   // 16-bit column offsets from a per-slot base (the smallest column of the slot over the
   // slice's rows), when every slot's columns span less than 2^16; rows past the end of the
   // last slice store offset 0
@@ -496,6 +576,7 @@ int upload_tsell(DevOwner* h, const TSellHost& T, TSellDev& D, hipStream_t s) {
   D.ncols = T.ncols;
   D.R = T.R;
   D.nslices = T.nslices;
+  D.ell = T.ell;
   bool exact = true;
   for (double w : T.w) exact = exact && (double(float(w)) == w);
   D.f32 = exact;

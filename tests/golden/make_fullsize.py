@@ -4,7 +4,7 @@ For each benchmark workload at its full size this runs the oracle (FP64, test-on
 stores, at a seeded sample of DoF indices: one finest-level smoothing sweep of seeded
 vectors, one V-cycle of the workload's right-hand side from zero, and the converged
 FGMRES solution, plus the norms the tolerances are scaled by and the iteration count.
-Run from the repository root:  python tests/golden/make_fullsize.py c2 c4 c3
+Run from the repository root:  python tests/golden/make_fullsize.py c2 c4 c3 c3f
 """
 import json
 import os
@@ -23,6 +23,7 @@ FULL = {
     "c2": lambda: W.c2_td().with_(coarse_level=3),
     "c3": lambda: W.c3_elasticity().with_(coarse_level=2),
     "c4": lambda: W.c4_oseen().with_(coarse_level=2),
+    "c3f": lambda: W.c3_adaptive("face", 6),
 }
 N_SAMPLES = 400
 

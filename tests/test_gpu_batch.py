@@ -277,3 +277,17 @@ def test_batch_column_formats_bitwise_equal(monkeypatch):
         assert rc == 0
         outs.append(x.cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_batch_slice_widths_bitwise_equal(monkeypatch):
+    wls, ors, gps, b, nrhs = _group("td_nrhs8")
+    bd = torch.from_numpy(b).cuda()
+    outs = []
+    for off in ("0", "1"):
+        monkeypatch.setenv("MGQ1_NO_ELL", off)
+        bt = _batch("td_nrhs8", precision="fp32")
+        x = torch.zeros_like(bd)
+        rc, st = bt.solve(bd, x)
+        assert rc == 0
+        outs.append(x.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])

@@ -29,6 +29,7 @@ FULL = {
     "c2": lambda: W.c2_td().with_(coarse_level=3),
     "c3": lambda: W.c3_elasticity().with_(coarse_level=2),
     "c4": lambda: W.c4_oseen().with_(coarse_level=2),
+    "c3f": lambda: W.c3_adaptive("face", 6),
 }
 GOLDEN = sorted(os.path.basename(p)[9:-5] for p in glob.glob(os.path.join(HERE, "golden", "fullsize_*.json")))
 

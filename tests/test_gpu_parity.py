@@ -334,3 +334,44 @@ def test_column_formats_bitwise_equal(name, prec, monkeypatch):
         st = h.solve(dev(o.b), x)
         outs.append((host(x), st["iters"]))
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+
+
+@pytest.mark.parametrize("name", ["poisson33", "td_band", "elast17", "oseen17", "edge4"])
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_slice_widths_bitwise_equal(name, prec, monkeypatch):
+    """Levels whose slices are padded to one uniform width (the kernels then compute each
+    slice's slot range) give bitwise the result of variable slice widths: padding slots add
+    exact zeros.  Also covers the transfer matrices, which follow the same rule."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    outs = []
+    for off in ("0", "1"):
+        monkeypatch.setenv("MGQ1_NO_ELL", off)
+        h = mg.Hierarchy(p.levels, mg.config_from(wl, precision=prec))
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        st = h.solve(dev(o.b), x)
+        outs.append((host(x), st["iters"]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+
+
+@pytest.mark.parametrize("name", ["elast17", "oseen17", "edge4"])
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_sorted_rows_neutral(name, prec, monkeypatch):
+    """Block rows sorted by length inside windows of slices (a row keeps its own slot
+    order, only its lane moves): the V-cycle is bitwise that of node order; solves differ
+    only by the summation order of the Krylov inner products."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    vc, sol = [], []
+    for off in ("0", "1"):
+        monkeypatch.setenv("MGQ1_NO_SORT", off)
+        h = mg.Hierarchy(p.levels, mg.config_from(wl, precision=prec))
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        h.vcycle(dev(o.b), x)
+        vc.append(host(x))
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        st = h.solve(dev(o.b), x)
+        sol.append((host(x), st["iters"]))
+    assert np.array_equal(vc[0], vc[1])
+    assert abs(sol[0][1] - sol[1][1]) <= 1
+    assert np.linalg.norm(sol[0][0] - sol[1][0]) <= 1e-8 * np.linalg.norm(sol[1][0])

@@ -230,5 +230,6 @@ def by_name(name: str) -> Workload:
         "c3": c3_elasticity().with_(coarse_level=2),
         "c4": c4_oseen().with_(coarse_level=2),
         "c4b": c4_oseen(rounds=6, tall=True).with_(coarse_level=2),
+        "c3f": c3_adaptive("face", 6),
     }
     return table[name]
