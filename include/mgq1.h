@@ -144,8 +144,9 @@ int mg_level_info(const mg_handle* h, int32_t level, int32_t* n_nodes, int32_t* 
 int32_t mg_num_levels(const mg_handle* h);
 
 /* Slot batch used on level `level`, the bytes per stored column index of its operators
- * (2 when, in every slice, each block slot's columns span less than 2^16 and the kernels
- * read 16-bit offsets from a per-slot base, else 4), and the sweep times (microseconds per
+ * (2 when the kernels read 16-bit offsets from a per-slot base: in every slice whose block
+ * slots each span less than 2^16 columns, the others, at most 1/8 of the slots, reading
+ * 32-bit indices; else 4), and the sweep times (microseconds per
  * launch) that the setup measured for the default and the other slot batch (0 when
  * slot_batch was fixed).  Any output pointer may be NULL. */
 int mg_level_tuning(const mg_handle* h, int32_t level, int32_t* slot_batch, int32_t* col_bytes,

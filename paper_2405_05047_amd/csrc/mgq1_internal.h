@@ -33,8 +33,10 @@ struct SellDev {
   const int8_t* rexp = nullptr;     // nslices * 64 power-of-two row exponents (F16 / BF16)
   int kind = VK_F64;
   int kb = 0;                       // block slots per load batch (0: the default for B)
-  const uint16_t* col16 = nullptr;  // col - colbase[slot] as 16 bits when every slot's
-  const int32_t* colbase = nullptr; // columns span less than 2^16 (NULL: the kernels read col)
+  const uint16_t* col16 = nullptr;  // col - colbase[slot] as 16 bits where the slot's columns
+  const int32_t* colbase = nullptr; // span less than 2^16 (NULL: the kernels read col)
+  const uint32_t* wide = nullptr;   // with col16: bit s set = slice s reads col instead
+                                    // (some slot spans 2^16 or more); NULL: no such slice
   const int32_t* perm = nullptr;    // node at row position slice*R + r (NULL: the position
                                     // itself); rows sorted by length inside windows of slices
 };

@@ -115,6 +115,11 @@ __device__ __forceinline__ void slot_range(const M& A, int su, int& k, int& k1) 
   }
 }
 
+// slice su (wave-uniform) of a 16-bit-column operator reads the 32-bit columns instead
+__device__ __forceinline__ bool is_wide(const SellDev& A, int su) {
+  return A.wide != nullptr && ((A.wide[su >> 5] >> (su & 31)) & 1u);
+}
+
 template <int NB, int B, int NR, int K, class XI, class T, bool C16>
 __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int node, int rl, int q,
                                            const XI* __restrict__ x, T& acc) {
@@ -237,8 +242,13 @@ __device__ __forceinline__ T sell_dot(const SellDev& A, int slice, int lane, boo
   const int node = slice * R + r;
   int k, k1;
   slot_range(A, slice, k, k1);
-  for (; k + KB <= k1; k += KB) sell_batch<KB, B, NR, K, XI, T, C16>(A, k, r, node, rl, q, x, acc);
-  sell_rest<KB - 1, B, NR, K, XI, T, C16>(k1 - k, A, k, r, node, rl, q, x, acc);
+  if (C16 && is_wide(A, slice)) {
+    for (; k + KB <= k1; k += KB) sell_batch<KB, B, NR, K, XI, T, false>(A, k, r, node, rl, q, x, acc);
+    sell_rest<KB - 1, B, NR, K, XI, T, false>(k1 - k, A, k, r, node, rl, q, x, acc);
+  } else {
+    for (; k + KB <= k1; k += KB) sell_batch<KB, B, NR, K, XI, T, C16>(A, k, r, node, rl, q, x, acc);
+    sell_rest<KB - 1, B, NR, K, XI, T, C16>(k1 - k, A, k, r, node, rl, q, x, acc);
+  }
   if (K == VK_F16 || K == VK_BF16) acc *= T(ldexpf(1.0f, A.rexp[int64_t(slice) * W + rl]));
   return acc;
 }
@@ -527,8 +537,13 @@ __global__ __launch_bounds__(kThreads) void k_sweep2z(SellDev A, const X* __rest
   slot_range(A, su, k, k1);
   T acc = T(0);
   const int node = int(i);
-  for (; k + KB <= k1; k += KB) sell_batch_z<KB, K, X, T, C16>(A, k, lane, node, S, b, omega, acc);
-  sell_rest_z<KB - 1, K, X, T, C16>(k1 - k, A, k, lane, node, S, b, omega, acc);
+  if (C16 && is_wide(A, su)) {
+    for (; k + KB <= k1; k += KB) sell_batch_z<KB, K, X, T, false>(A, k, lane, node, S, b, omega, acc);
+    sell_rest_z<KB - 1, K, X, T, false>(k1 - k, A, k, lane, node, S, b, omega, acc);
+  } else {
+    for (; k + KB <= k1; k += KB) sell_batch_z<KB, K, X, T, C16>(A, k, lane, node, S, b, omega, acc);
+    sell_rest_z<KB - 1, K, X, T, C16>(k1 - k, A, k, lane, node, S, b, omega, acc);
+  }
   if (K == VK_F16 || K == VK_BF16) acc *= T(ldexpf(1.0f, A.rexp[int64_t(slice) * kWave + lane]));
   const X x1 = X(omega * (T(0) + T(si) * T(bi)));
   const T res = T(bi) - acc;
@@ -836,13 +851,10 @@ __global__ __launch_bounds__(kRedThreads) void k_mgs_step(int64_t n, double* __r
                                                           const double* __restrict__ pin, int gin,
                                                           double* __restrict__ pout, double* __restrict__ hout) {
   __shared__ double lds[kMaxWaves + 1];
-  const double h = sum_partials(pin, gin, lds);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *hout = h;
   constexpr int U = 4;
-  double t = 0.0;
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < n; i0 += stride * U) {
-    double wv[U], vv[U], nv[U];
+  double wv[U], vv[U], nv[U];
+  auto load = [&](int64_t i0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = i0 + u * stride;
@@ -851,6 +863,16 @@ __global__ __launch_bounds__(kRedThreads) void k_mgs_step(int64_t n, double* __r
       vv[u] = ok ? vi[i] : 0.0;
       nv[u] = (ok && vnext) ? vnext[i] : 0.0;
     }
+  };
+  // the first chunk's loads do not depend on h: issue them before the partial sums are
+  // combined, so the two latencies overlap
+  const int64_t first = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  load(first);
+  const double h = sum_partials(pin, gin, lds);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *hout = h;
+  double t = 0.0;
+  for (int64_t i0 = first; i0 < n; i0 += stride * U) {
+    if (i0 != first) load(i0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = i0 + u * stride;
@@ -902,27 +924,30 @@ __global__ __launch_bounds__(kRedThreads) void k_mgs_normalize(int64_t n, double
                                                                double* hout, GivensArgs gv,
                                                                float* __restrict__ wc) {
   __shared__ double lds[kMaxWaves + 1];
+  constexpr int U = 4;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  double wv[U];
+  auto load = [&](int64_t i0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      wv[u] = i < n ? w[i] : 0.0;
+    }
+  };
+  const int64_t first = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  load(first);                             // independent of the norm (latency overlap)
   const double nrm = sqrt(sum_partials(pin, gin, lds));
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *hout = nrm;
     if (gv.H) givens_column(gv.j, gv.m, gv.H, gv.cs, gv.sn, gv.g, gv.st);
   }
   if (nrm == 0.0) {
-    if (wc) {
-      const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-      for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) wc[i] = float(w[i]);
-    }
+    if (wc)
+      for (int64_t i = first; i < n; i += stride) wc[i] = float(w[i]);
     return;
   }
-  constexpr int U = 4;
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < n; i0 += stride * U) {
-    double wv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = i0 + u * stride;
-      wv[u] = i < n ? w[i] : 0.0;
-    }
+  for (int64_t i0 = first; i0 < n; i0 += stride * U) {
+    if (i0 != first) load(i0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = i0 + u * stride;

@@ -483,12 +483,18 @@ int upload_sell(DevOwner* h, const HostSell& S, int kind, SellDev& D, hipStream_
     D.perm = pm;
   }
   // 16-bit column offsets from a per-slot base (the smallest column of the slot over the
-  // slice's rows), when every slot's columns span less than 2^16; rows past the end of the
-  // last slice store offset 0
-  bool fits = true;
+  // slice's rows) in every slice whose slots all span less than 2^16; the other ("wide")
+  // slices read the 32-bit columns, marked in a bit mask.  Used when the wide slices hold at
+  // most 1/8 of the slots.  Rows past the end of the last slice store offset 0.
+  // MGQ1_WIDE_EVERY=n also marks every n-th slice wide (tests of the mixed format).
+  int every = 0;
+  if (const char* e = std::getenv("MGQ1_WIDE_EVERY")) every = std::max(0, std::atoi(e));
   std::vector<uint16_t> c16(S.col.size(), 0);
   std::vector<int32_t> base(size_t(S.slots), 0);
-  for (int32_t sl = 0; sl < S.nslices && fits; ++sl)
+  std::vector<uint32_t> wide((size_t(S.nslices) + 31) / 32, 0u);
+  int64_t wide_slots = 0;
+  for (int32_t sl = 0; sl < S.nslices; ++sl) {
+    bool fits = !(every > 0 && sl % every == 0);
     for (int64_t k = S.sptr[sl]; k < S.sptr[sl + 1] && fits; ++k) {
       int32_t lo = INT32_MAX, hi = INT32_MIN;
       for (int r = 0; r < S.R; ++r)
@@ -501,12 +507,26 @@ int upload_sell(DevOwner* h, const HostSell& S, int kind, SellDev& D, hipStream_
       for (int r = 0; r < S.R; ++r)
         if (int64_t(sl) * S.R + r < S.n) c16[size_t(k) * S.R + r] = uint16_t(S.col[size_t(k) * S.R + r] - lo);
     }
+    if (!fits) {
+      wide[size_t(sl) / 32] |= 1u << (sl % 32);
+      wide_slots += S.sptr[sl + 1] - S.sptr[sl];
+      for (int64_t k = S.sptr[sl]; k < S.sptr[sl + 1]; ++k) {
+        base[size_t(k)] = 0;
+        for (int r = 0; r < S.R; ++r) c16[size_t(k) * S.R + r] = 0;
+      }
+    }
+  }
   const char* off = std::getenv("MGQ1_NO_COL16");
-  if (fits && !(off && std::atoi(off) != 0)) {
+  if (wide_slots * 8 <= S.slots && !(off && std::atoi(off) != 0)) {
     uint16_t* c;
     int32_t* bs;
     if ((rc = upload(h, &c, c16, s))) return rc;
     if ((rc = upload(h, &bs, base, s))) return rc;
+    if (wide_slots > 0) {
+      uint32_t* wm;
+      if ((rc = upload(h, &wm, wide, s))) return rc;
+      D.wide = wm;
+    }
     MG_HIP(hipStreamSynchronize(s));
     D.col16 = c;
     D.colbase = bs;

@@ -291,3 +291,18 @@ def test_batch_slice_widths_bitwise_equal(monkeypatch):
         assert rc == 0
         outs.append(x.cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_batch_mixed_column_format_bitwise_equal(monkeypatch):
+    wls, ors, gps, b, nrhs = _group("td_nrhs8")
+    bd = torch.from_numpy(b).cuda()
+    outs = []
+    for every, off in (("17", "0"), ("0", "1")):
+        monkeypatch.setenv("MGQ1_WIDE_EVERY", every)
+        monkeypatch.setenv("MGQ1_NO_COL16", off)
+        bt = _batch("td_nrhs8", precision="fp16")
+        x = torch.zeros_like(bd)
+        rc, st = bt.solve(bd, x)
+        assert rc == 0
+        outs.append(x.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])

@@ -375,3 +375,24 @@ def test_sorted_rows_neutral(name, prec, monkeypatch):
     assert np.array_equal(vc[0], vc[1])
     assert abs(sol[0][1] - sol[1][1]) <= 1
     assert np.linalg.norm(sol[0][0] - sol[1][0]) <= 1e-8 * np.linalg.norm(sol[1][0])
+
+
+@pytest.mark.parametrize("name", ["poisson33", "td_band", "elast17", "edge4"])
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_mixed_column_format_bitwise_equal(name, prec, monkeypatch):
+    """Slices whose columns do not fit 16-bit offsets read the 32-bit indices while the
+    others read the offsets (here every 17th slice is forced to the 32-bit form); the
+    result is bitwise that of 32-bit indices everywhere."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    outs = []
+    for env in ({"MGQ1_WIDE_EVERY": "17", "MGQ1_NO_COL16": "0"}, {"MGQ1_WIDE_EVERY": "0", "MGQ1_NO_COL16": "1"}):
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        h = mg.Hierarchy(p.levels, mg.config_from(wl, precision=prec))
+        if env["MGQ1_NO_COL16"] == "0":
+            assert h.col_bytes(h.n_levels - 1) == 2
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        st = h.solve(dev(o.b), x)
+        outs.append((host(x), st["iters"]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
