@@ -15,7 +15,10 @@
 //   operators each lane gathers only its own component of a neighbour node and takes the
 //   others from the node's lanes by wave shuffles; the smoother exchanges the B residual
 //   components of a node the same way and applies the stored block inverse.  Column
-//   indices are 32-bit, or 16-bit offsets from a per-slot base where they fit.
+//   indices are 16-bit offsets from a per-slot base, except in slices whose columns span
+//   2^16 or more (a per-slice bit selects the 32-bit indices there).  Uniform-width levels
+//   compute a slice's slot range instead of loading it; block rows may be sorted by
+//   length inside windows of slices (a permutation maps each row position to its node).
 //   Workgroup ids are remapped so that each XCD (round-robin dispatch over 8 XCDs) walks a
 //   contiguous range of slices and keeps its own L2 warm.
 //
@@ -568,15 +571,16 @@ __device__ __forceinline__ void gemv_row(int n, const double* __restrict__ Ainv,
   double acc = 0.0;
   const double* row = Ainv + int64_t(i) * n;
   for (int k0 = lane; k0 < n; k0 += kWave * U) {
-    double av[U], bv[U];
-#pragma unroll
+    double av[U];
+    XI bv[U];                                // widened only when used: a conditional load
+#pragma unroll                               // converted in place would wait per element
     for (int u = 0; u < U; ++u) {
       const int k = k0 + u * kWave;
       av[u] = k < n ? row[k] : 0.0;
-      bv[u] = k < n ? double(b[k]) : 0.0;
+      bv[u] = k < n ? b[k] : XI(0);
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc += av[u] * bv[u];
+    for (int u = 0; u < U; ++u) acc += av[u] * double(bv[u]);
   }
   acc = wave_sum(acc);
   if (lane == 0) x[i] = XO(acc);
@@ -1539,15 +1543,16 @@ __global__ __launch_bounds__(kThreads) void k_bcoarse(const BEntry* __restrict__
   double acc = 0.0;
   const double* row = e.Ainv + int64_t(i) * e.n0;
   for (int k0 = lane / NR; k0 < e.n0; k0 += (kWave / NR) * U) {
-    double av[U], bv[U];
+    double av[U];
+    X bv[U];                                 // widened when used (no wait per element)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = k0 + u * (kWave / NR);
       av[u] = k < e.n0 ? row[k] : 0.0;
-      bv[u] = k < e.n0 ? double(b[int64_t(k) * NR + q]) : 0.0;
+      bv[u] = k < e.n0 ? b[int64_t(k) * NR + q] : X(0);
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc += av[u] * bv[u];
+    for (int u = 0; u < U; ++u) acc += av[u] * double(bv[u]);
   }
 #pragma unroll
   for (int o = kWave / 2; o >= NR; o >>= 1) acc += __shfl_down(acc, o, kWave);
@@ -1627,14 +1632,10 @@ __global__ __launch_bounds__(kThreads) void k_bmgs_step(BSegs g, double* __restr
   __shared__ double hq[64];
   const SegPos sp = seg_pos(g);
   if (!sp.on) return;                      // uniform over the block
-  seg_sums(pin, sp, g.NR, lds, hq);
-  if (sp.lb == 0 && int(threadIdx.x) < g.NR) H[int64_t(sp.p * g.NR + threadIdx.x) * hstride] = hq[threadIdx.x];
-  const double h = hq[threadIdx.x % g.NR];
   constexpr int U = 4;
-  double t = 0.0;
   const int64_t stride = int64_t(sp.nb) * blockDim.x;
-  for (int64_t i0 = int64_t(sp.lb) * blockDim.x + threadIdx.x; i0 < sp.len; i0 += stride * U) {
-    double wv[U], vv[U], nv[U];
+  double wv[U], vv[U], nv[U];
+  auto load = [&](int64_t i0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = i0 + u * stride;
@@ -1643,6 +1644,15 @@ __global__ __launch_bounds__(kThreads) void k_bmgs_step(BSegs g, double* __restr
       vv[u] = ok ? vi[sp.off + i] : 0.0;
       nv[u] = (ok && vnext) ? vnext[sp.off + i] : 0.0;
     }
+  };
+  const int64_t first = int64_t(sp.lb) * blockDim.x + threadIdx.x;
+  load(first);                             // independent of h: overlaps the partial sums
+  seg_sums(pin, sp, g.NR, lds, hq);
+  if (sp.lb == 0 && int(threadIdx.x) < g.NR) H[int64_t(sp.p * g.NR + threadIdx.x) * hstride] = hq[threadIdx.x];
+  const double h = hq[threadIdx.x % g.NR];
+  double t = 0.0;
+  for (int64_t i0 = first; i0 < sp.len; i0 += stride * U) {
+    if (i0 != first) load(i0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = i0 + u * stride;
@@ -1662,28 +1672,30 @@ __global__ __launch_bounds__(kThreads) void k_bmgs_normalize(BSegs g, double* __
   __shared__ double hq[64];
   const SegPos sp = seg_pos(g);
   if (!sp.on) return;                      // uniform over the block
+  constexpr int U = 4;
+  const int64_t stride = int64_t(sp.nb) * blockDim.x;
+  double wv[U];
+  auto load = [&](int64_t i0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      wv[u] = i < sp.len ? w[sp.off + i] : 0.0;
+    }
+  };
+  const int64_t first = int64_t(sp.lb) * blockDim.x + threadIdx.x;
+  load(first);                             // independent of the norm (latency overlap)
   seg_sums(pin, sp, g.NR, lds, hq);
   if (int(threadIdx.x) < g.NR) hq[threadIdx.x] = sqrt(hq[threadIdx.x]);
   __syncthreads();
   if (sp.lb == 0 && int(threadIdx.x) < g.NR) H[int64_t(sp.p * g.NR + threadIdx.x) * hstride] = hq[threadIdx.x];
   const double nrm = hq[threadIdx.x % g.NR];
   if (nrm == 0.0) {
-    if (wc) {
-      const int64_t stride = int64_t(sp.nb) * blockDim.x;
-      for (int64_t i = int64_t(sp.lb) * blockDim.x + threadIdx.x; i < sp.len; i += stride)
-        wc[sp.off + i] = float(w[sp.off + i]);
-    }
+    if (wc)
+      for (int64_t i = first; i < sp.len; i += stride) wc[sp.off + i] = float(w[sp.off + i]);
     return;
   }
-  constexpr int U = 4;
-  const int64_t stride = int64_t(sp.nb) * blockDim.x;
-  for (int64_t i0 = int64_t(sp.lb) * blockDim.x + threadIdx.x; i0 < sp.len; i0 += stride * U) {
-    double wv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = i0 + u * stride;
-      wv[u] = i < sp.len ? w[sp.off + i] : 0.0;
-    }
+  for (int64_t i0 = first; i0 < sp.len; i0 += stride * U) {
+    if (i0 != first) load(i0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = i0 + u * stride;
