@@ -77,19 +77,22 @@ def time_solves(torch, h, b, x, steps, warmup):
 def counter_traffic(workload_name):
     """HBM bytes per launch of the finest-level FP64 sweep from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy), or None when
-    the kernel source has changed since the counters were taken."""
+    the kernel or runtime source (which decides the data layout) has changed since the
+    counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_sweep_fp64_counters.json")
-    src = os.path.join(ROOT, "paper_2405_05047_amd", "csrc", "mgq1_kernels.hip")
+    h = hashlib.sha256()
     try:
         with open(path) as f:
             table = json.load(f)
-        with open(src, "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
+        for name in ("mgq1_kernels.hip", "mgq1_runtime.hip"):
+            with open(os.path.join(ROOT, "paper_2405_05047_amd", "csrc", name), "rb") as f:
+                h.update(f.read())
     except OSError:
         return None
+    digest = h.hexdigest()
     entry = table.get(workload_name)
-    if not entry or entry.get("kernels_sha256") != digest:
+    if not entry or entry.get("sources_sha256") != digest:
         return None
     return entry["traffic_bytes_per_launch"]
 

@@ -180,17 +180,19 @@ struct HostSell {
   std::vector<int8_t> rexp;                         // nslices * W
 };
 
-// Uniform slice width (plain ELL) when padding every slice to the widest one costs little:
-// at most 2% more slots, or at most 12.5% on levels of up to 2^18 scalar rows, whose kernels
-// wait on memory latency rather than bandwidth; the kernels then compute a slice's slot
-// range instead of loading it.  Padding slots contribute exact zeros, so the results are
-// those of the variable widths (MGQ1_NO_ELL=1 keeps those, for tests).
+// Uniform slice width (plain ELL) on levels of up to 2^18 scalar rows, whose kernels wait
+// on memory latency rather than bandwidth, when padding every slice to the widest one
+// adds at most 12.5% slots (on larger levels only when it adds none: there the extra
+// bytes cost more than the saved slice-pointer load, measured +2% on the 3D sweeps); the
+// kernels then compute a slice's slot range instead of loading it.  Padding slots
+// contribute exact zeros, so the results are those of the variable widths (MGQ1_NO_ELL=1
+// keeps those, for tests).
 bool want_ell(int64_t slots, int64_t nslices, int32_t maxw, int64_t rows) {
   const char* off = std::getenv("MGQ1_NO_ELL");
   if (off && std::atoi(off) != 0) return false;
   const int64_t ell = nslices * int64_t(maxw);
   if (maxw <= 0 || ell >= (int64_t(1) << 31)) return false;
-  return ell * 50 <= slots * 51 || (rows <= (int64_t(1) << 18) && ell * 8 <= slots * 9);
+  return ell == slots || (rows <= (int64_t(1) << 18) && ell * 8 <= slots * 9);
 }
 
 // slice pointers of uniform width w
@@ -211,7 +213,7 @@ int32_t max_width(const std::vector<int32_t>& sptr, int32_t nslices) {
 // its slot order, so its sum is unchanged; only the lane that computes it moves.  One
 // component per node is left in node order (the fused two-sweep kernel relies on it).
 // MGQ1_NO_SORT=1 keeps the node order everywhere (tests).
-constexpr int kSortSlices = 16;
+constexpr int kSortSlices = 64;
 
 std::vector<int32_t> sorted_positions(const HostLevel& L, int R) {
   std::vector<int32_t> perm;
