@@ -14,7 +14,7 @@ enum VecKind { X_F64 = 0, X_F32 = 1 };
 
 constexpr int kWave = 64;             // wavefront width on CDNA
 constexpr int kSliceWaves = 4;        // slices (one per wave) per 256-thread workgroup
-constexpr int kRedThreads = 256;
+constexpr int kRedThreads = 1024;
 constexpr int kMaxRedBlocks = 2048;   // grid (= partial count) of the vector reductions
 
 // Sliced ELL of a block matrix: one slice = 64 lanes = R = 64/B nodes x B components;
