@@ -39,6 +39,7 @@ struct SellDev {
                                     // (some slot spans 2^16 or more); NULL: no such slice
   const int32_t* perm = nullptr;    // node at row position slice*R + r (NULL: the position
                                     // itself); rows sorted by length inside windows of slices
+  int nt = 1;                       // 1: values and indices read with non-temporal loads
 };
 
 // the two slot-batch sizes the slice kernels are built for (default, alternative)
@@ -62,6 +63,7 @@ struct CsrDev {
 struct TSellDev {
   int32_t nrows = 0, ncols = 0, R = 64, nslices = 0;
   int32_t ell = 0;                  // > 0: uniform slice width, as in SellDev
+  int nt = 1;                       // 1: indices and weights read with non-temporal loads
   const int32_t* sptr = nullptr;
   const int32_t* col = nullptr;
   const void* w = nullptr;

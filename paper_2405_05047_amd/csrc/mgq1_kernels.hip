@@ -59,36 +59,49 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   return x * q + (x < r ? x : r) + k;
 }
 
-// stored matrix values: load() fetches the raw stored word (nontemporal: A is streamed
-// once per sweep), dec() widens it to FP32/FP64.  FP16/BF16 values are a_ij / s_i with the
+// Loads of the operator streams (values, column indices, transfer weights): non-temporal
+// (NT) on levels too large to stay in the memory-side cache between kernels, where they
+// would only evict the gathered vectors; ordinary loads on the smaller levels, whose
+// operators the next kernels read again from that cache.
+template <bool NT, class P>
+__device__ __forceinline__ P stream_load(const P* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+// stored matrix values: load() fetches the raw stored word, dec() widens it to FP32/FP64.  FP16/BF16 values are a_ij / s_i with the
 // power-of-two row scale s_i applied once to the finished row sum (exact: scaling by 2^e
 // commutes with rounding away from overflow and underflow).
 template <int K> struct Val;
 template <> struct Val<VK_F64> {
   using raw = double;
+  template <bool NT>
   __device__ __forceinline__ static raw load(const void* p, int64_t i) {
-    return __builtin_nontemporal_load(static_cast<const double*>(p) + i);
+    return stream_load<NT>(static_cast<const double*>(p) + i);
   }
   __device__ __forceinline__ static double dec(raw u) { return u; }
 };
 template <> struct Val<VK_F32> {
   using raw = float;
+  template <bool NT>
   __device__ __forceinline__ static raw load(const void* p, int64_t i) {
-    return __builtin_nontemporal_load(static_cast<const float*>(p) + i);
+    return stream_load<NT>(static_cast<const float*>(p) + i);
   }
   __device__ __forceinline__ static float dec(raw u) { return u; }
 };
 template <> struct Val<VK_F16> {
   using raw = unsigned short;
+  template <bool NT>
   __device__ __forceinline__ static raw load(const void* p, int64_t i) {
-    return __builtin_nontemporal_load(static_cast<const unsigned short*>(p) + i);
+    return stream_load<NT>(static_cast<const unsigned short*>(p) + i);
   }
   __device__ __forceinline__ static float dec(raw u) { return __half2float(__ushort_as_half(u)); }
 };
 template <> struct Val<VK_BF16> {
   using raw = unsigned short;
+  template <bool NT>
   __device__ __forceinline__ static raw load(const void* p, int64_t i) {
-    return __builtin_nontemporal_load(static_cast<const unsigned short*>(p) + i);
+    return stream_load<NT>(static_cast<const unsigned short*>(p) + i);
   }
   __device__ __forceinline__ static float dec(raw u) { return __uint_as_float(static_cast<uint32_t>(u) << 16); }
 };
@@ -99,10 +112,10 @@ template <> struct Val<VK_BF16> {
 // result is widened inside the block would force a wait per slot).
 // C16: column indices are stored as 16-bit offsets from a per-slot base (the smallest
 // column of that slot in the slice, wave-uniform, so a scalar load).
-template <bool C16>
+template <bool C16, bool NT>
 __device__ __forceinline__ unsigned slot_col(const SellDev& A, int k, int64_t idx) {
-  if constexpr (C16) return unsigned(A.colbase[k]) + unsigned(__builtin_nontemporal_load(A.col16 + idx));
-  else return unsigned(__builtin_nontemporal_load(A.col + idx));
+  if constexpr (C16) return unsigned(A.colbase[k]) + unsigned(stream_load<NT>(A.col16 + idx));
+  else return unsigned(stream_load<NT>(A.col + idx));
 }
 
 // slot range [k, k1) of slice su (wave-uniform): computed for uniform-width slices, else
@@ -123,7 +136,7 @@ __device__ __forceinline__ bool is_wide(const SellDev& A, int su) {
   return A.wide != nullptr && ((A.wide[su >> 5] >> (su & 31)) & 1u);
 }
 
-template <int NB, int B, int NR, int K, class XI, class T, bool C16>
+template <int NB, int B, int NR, int K, class XI, class T, bool C16, bool NT>
 __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int node, int rl, int q,
                                            const XI* __restrict__ x, T& acc) {
   constexpr int R = kWave / (B * NR);
@@ -136,12 +149,12 @@ __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int n
   VR av[NB][B];
   XI xv[NB][B];
 #pragma unroll
-  for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16>(A, k + qq, int64_t(k + qq) * R + r);
+  for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16, NT>(A, k + qq, int64_t(k + qq) * R + r);
 #pragma unroll
   for (int qq = 0; qq < NB; ++qq) {
     const int64_t vb = int64_t(k + qq) * B * W + rl;
 #pragma unroll
-    for (int cc = 0; cc < B; ++cc) av[qq][cc] = Val<K>::load(A.val, vb + cc * W);
+    for (int cc = 0; cc < B; ++cc) av[qq][cc] = Val<K>::template load<NT>(A.val, vb + cc * W);
   }
   __builtin_amdgcn_sched_barrier(0);
   if constexpr (B > 1 && NR == 1) {
@@ -176,7 +189,7 @@ __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int n
 // first sweep, x1_j = omega * (S_j * b_j), is formed on the fly from S and b instead of being
 // read (S of node j sits at S[j] for one component and one right-hand side), with the
 // rounding of the stored value, so the result is bitwise that of the two separate sweeps.
-template <int NB, int K, class X, class T, bool C16>
+template <int NB, int K, class X, class T, bool C16, bool NT>
 __device__ __forceinline__ void sell_batch_z(const SellDev& A, int k, int rl, int node, const X* __restrict__ S,
                                              const X* __restrict__ b, T omega, T& acc) {
   using VR = typename Val<K>::raw;
@@ -184,9 +197,9 @@ __device__ __forceinline__ void sell_batch_z(const SellDev& A, int k, int rl, in
   VR av[NB];
   X sv[NB], bv[NB];
 #pragma unroll
-  for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16>(A, k + qq, int64_t(k + qq) * kWave + rl);
+  for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16, NT>(A, k + qq, int64_t(k + qq) * kWave + rl);
 #pragma unroll
-  for (int qq = 0; qq < NB; ++qq) av[qq] = Val<K>::load(A.val, int64_t(k + qq) * kWave + rl);
+  for (int qq = 0; qq < NB; ++qq) av[qq] = Val<K>::template load<NT>(A.val, int64_t(k + qq) * kWave + rl);
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int qq = 0; qq < NB; ++qq) {
@@ -201,23 +214,39 @@ __device__ __forceinline__ void sell_batch_z(const SellDev& A, int k, int rl, in
   }
 }
 
-template <int N, int K, class X, class T, bool C16>
+template <int N, int K, class X, class T, bool C16, bool NT>
 __device__ __forceinline__ void sell_rest_z(int rem, const SellDev& A, int k, int rl, int node,
                                             const X* __restrict__ S, const X* __restrict__ b, T omega, T& acc) {
   if constexpr (N >= 1) {
-    if (rem == N) sell_batch_z<N, K, X, T, C16>(A, k, rl, node, S, b, omega, acc);
-    else sell_rest_z<N - 1, K, X, T, C16>(rem, A, k, rl, node, S, b, omega, acc);
+    if (rem == N) sell_batch_z<N, K, X, T, C16, NT>(A, k, rl, node, S, b, omega, acc);
+    else sell_rest_z<N - 1, K, X, T, C16, NT>(rem, A, k, rl, node, S, b, omega, acc);
   }
 }
 
+// the slots [k, k1) of one slice for the second of two sweeps from 0
+template <int KB, int K, class X, class T, bool C16, bool NT>
+__device__ __forceinline__ void sell_loop_z(int k, int k1, const SellDev& A, int rl, int node,
+                                            const X* __restrict__ S, const X* __restrict__ b, T omega, T& acc) {
+  for (; k + KB <= k1; k += KB) sell_batch_z<KB, K, X, T, C16, NT>(A, k, rl, node, S, b, omega, acc);
+  sell_rest_z<KB - 1, K, X, T, C16, NT>(k1 - k, A, k, rl, node, S, b, omega, acc);
+}
+
 // the remaining rem < KB slots of a slice as one batch of exactly rem slots
-template <int N, int B, int NR, int K, class XI, class T, bool C16>
+template <int N, int B, int NR, int K, class XI, class T, bool C16, bool NT>
 __device__ __forceinline__ void sell_rest(int rem, const SellDev& A, int k, int r, int node, int rl, int q,
                                           const XI* __restrict__ x, T& acc) {
   if constexpr (N >= 1) {
-    if (rem == N) sell_batch<N, B, NR, K, XI, T, C16>(A, k, r, node, rl, q, x, acc);
-    else sell_rest<N - 1, B, NR, K, XI, T, C16>(rem, A, k, r, node, rl, q, x, acc);
+    if (rem == N) sell_batch<N, B, NR, K, XI, T, C16, NT>(A, k, r, node, rl, q, x, acc);
+    else sell_rest<N - 1, B, NR, K, XI, T, C16, NT>(rem, A, k, r, node, rl, q, x, acc);
   }
+}
+
+// the slots [k, k1) of one slice: batches of KB, then the remainder as one batch
+template <int KB, int B, int NR, int K, class XI, class T, bool C16, bool NT>
+__device__ __forceinline__ void sell_loop(int k, int k1, const SellDev& A, int r, int node, int rl, int q,
+                                          const XI* __restrict__ x, T& acc) {
+  for (; k + KB <= k1; k += KB) sell_batch<KB, B, NR, K, XI, T, C16, NT>(A, k, r, node, rl, q, x, acc);
+  sell_rest<KB - 1, B, NR, K, XI, T, C16, NT>(k1 - k, A, k, r, node, rl, q, x, acc);
 }
 
 template <int B> constexpr int kb_default() { return B <= 2 ? 8 : 4; }
@@ -245,12 +274,13 @@ __device__ __forceinline__ T sell_dot(const SellDev& A, int slice, int lane, boo
   const int node = slice * R + r;
   int k, k1;
   slot_range(A, slice, k, k1);
-  if (C16 && is_wide(A, slice)) {
-    for (; k + KB <= k1; k += KB) sell_batch<KB, B, NR, K, XI, T, false>(A, k, r, node, rl, q, x, acc);
-    sell_rest<KB - 1, B, NR, K, XI, T, false>(k1 - k, A, k, r, node, rl, q, x, acc);
+  const bool wide = C16 && is_wide(A, slice);
+  if (A.nt) {
+    if (wide) sell_loop<KB, B, NR, K, XI, T, false, true>(k, k1, A, r, node, rl, q, x, acc);
+    else sell_loop<KB, B, NR, K, XI, T, C16, true>(k, k1, A, r, node, rl, q, x, acc);
   } else {
-    for (; k + KB <= k1; k += KB) sell_batch<KB, B, NR, K, XI, T, C16>(A, k, r, node, rl, q, x, acc);
-    sell_rest<KB - 1, B, NR, K, XI, T, C16>(k1 - k, A, k, r, node, rl, q, x, acc);
+    if (wide) sell_loop<KB, B, NR, K, XI, T, false, false>(k, k1, A, r, node, rl, q, x, acc);
+    else sell_loop<KB, B, NR, K, XI, T, C16, false>(k, k1, A, r, node, rl, q, x, acc);
   }
   if (K == VK_F16 || K == VK_BF16) acc *= T(ldexpf(1.0f, A.rexp[int64_t(slice) * W + rl]));
   return acc;
@@ -427,7 +457,7 @@ __device__ __forceinline__ void prolong_dof(const CsrDev& P, const X* __restrict
 // ---- sliced transfers: NB slots of one node row, loads first (straight-line), then the
 // weighted sum in slot order.  MC: apply the column mask (entries whose column DoF is
 // masked contribute 0).
-template <int NB, int B, int NR, class X, class T, class WT, bool MC>
+template <int NB, int B, int NR, class X, class T, class WT, bool MC, bool NT>
 __device__ __forceinline__ void tsell_batch(const TSellDev& M, int k, int r, int c, int q,
                                             const X* __restrict__ in, const uint8_t* __restrict__ mcol,
                                             T& acc) {
@@ -438,8 +468,8 @@ __device__ __forceinline__ void tsell_batch(const TSellDev& M, int k, int r, int
   uint8_t ms[NB];
 #pragma unroll
   for (int qq = 0; qq < NB; ++qq) {
-    js[qq] = unsigned(__builtin_nontemporal_load(M.col + int64_t(k + qq) * R + r));
-    ws[qq] = __builtin_nontemporal_load(static_cast<const WT*>(M.w) + int64_t(k + qq) * R + r);
+    js[qq] = unsigned(stream_load<NT>(M.col + int64_t(k + qq) * R + r));
+    ws[qq] = stream_load<NT>(static_cast<const WT*>(M.w) + int64_t(k + qq) * R + r);
   }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -453,12 +483,12 @@ __device__ __forceinline__ void tsell_batch(const TSellDev& M, int k, int r, int
   for (int qq = 0; qq < NB; ++qq) acc += T(ws[qq]) * (ms[qq] ? T(0) : T(vs[qq]));
 }
 
-template <int N, int B, int NR, class X, class T, class WT, bool MC>
+template <int N, int B, int NR, class X, class T, class WT, bool MC, bool NT>
 __device__ __forceinline__ void tsell_rest(int rem, const TSellDev& M, int k, int r, int c, int q,
                                            const X* __restrict__ in, const uint8_t* __restrict__ mcol, T& acc) {
   if constexpr (N >= 1) {
-    if (rem == N) tsell_batch<N, B, NR, X, T, WT, MC>(M, k, r, c, q, in, mcol, acc);
-    else tsell_rest<N - 1, B, NR, X, T, WT, MC>(rem, M, k, r, c, q, in, mcol, acc);
+    if (rem == N) tsell_batch<N, B, NR, X, T, WT, MC, NT>(M, k, r, c, q, in, mcol, acc);
+    else tsell_rest<N - 1, B, NR, X, T, WT, MC, NT>(rem, M, k, r, c, q, in, mcol, acc);
   }
 }
 
@@ -485,8 +515,13 @@ __device__ __forceinline__ void tsell_lane(const TSellDev& M, int slice, int lan
   int k, k1;
   slot_range(M, su, k, k1);
   T acc = T(0);
-  for (; k + KB <= k1; k += KB) tsell_batch<KB, B, NR, X, T, WT, MC>(M, k, r, c, q, in, mcol, acc);
-  tsell_rest<KB - 1, B, NR, X, T, WT, MC>(k1 - k, M, k, r, c, q, in, mcol, acc);
+  if (M.nt) {
+    for (; k + KB <= k1; k += KB) tsell_batch<KB, B, NR, X, T, WT, MC, true>(M, k, r, c, q, in, mcol, acc);
+    tsell_rest<KB - 1, B, NR, X, T, WT, MC, true>(k1 - k, M, k, r, c, q, in, mcol, acc);
+  } else {
+    for (; k + KB <= k1; k += KB) tsell_batch<KB, B, NR, X, T, WT, MC, false>(M, k, r, c, q, in, mcol, acc);
+    tsell_rest<KB - 1, B, NR, X, T, WT, MC, false>(k1 - k, M, k, r, c, q, in, mcol, acc);
+  }
   if (MODE == 0) out[t] = masked ? X(0) : X(acc);
   else if (!masked) out[t] = X(T(old) + acc);
 }
@@ -540,12 +575,13 @@ __global__ __launch_bounds__(kThreads) void k_sweep2z(SellDev A, const X* __rest
   slot_range(A, su, k, k1);
   T acc = T(0);
   const int node = int(i);
-  if (C16 && is_wide(A, su)) {
-    for (; k + KB <= k1; k += KB) sell_batch_z<KB, K, X, T, false>(A, k, lane, node, S, b, omega, acc);
-    sell_rest_z<KB - 1, K, X, T, false>(k1 - k, A, k, lane, node, S, b, omega, acc);
+  const bool wide = C16 && is_wide(A, su);
+  if (A.nt) {
+    if (wide) sell_loop_z<KB, K, X, T, false, true>(k, k1, A, lane, node, S, b, omega, acc);
+    else sell_loop_z<KB, K, X, T, C16, true>(k, k1, A, lane, node, S, b, omega, acc);
   } else {
-    for (; k + KB <= k1; k += KB) sell_batch_z<KB, K, X, T, C16>(A, k, lane, node, S, b, omega, acc);
-    sell_rest_z<KB - 1, K, X, T, C16>(k1 - k, A, k, lane, node, S, b, omega, acc);
+    if (wide) sell_loop_z<KB, K, X, T, false, false>(k, k1, A, lane, node, S, b, omega, acc);
+    else sell_loop_z<KB, K, X, T, C16, false>(k, k1, A, lane, node, S, b, omega, acc);
   }
   if (K == VK_F16 || K == VK_BF16) acc *= T(ldexpf(1.0f, A.rexp[int64_t(slice) * kWave + lane]));
   const X x1 = X(omega * (T(0) + T(si) * T(bi)));

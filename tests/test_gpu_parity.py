@@ -396,3 +396,20 @@ def test_mixed_column_format_bitwise_equal(name, prec, monkeypatch):
         st = h.solve(dev(o.b), x)
         outs.append((host(x), st["iters"]))
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+
+
+@pytest.mark.parametrize("name", ["td_band", "elast17"])
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_load_kinds_bitwise_equal(name, prec, monkeypatch):
+    """Operator streams read with non-temporal or ordinary loads (chosen per level by its
+    size) give bitwise the same solve."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    outs = []
+    for kind in ("nt", "t"):
+        monkeypatch.setenv("MGQ1_LOADS", kind)
+        h = mg.Hierarchy(p.levels, mg.config_from(wl, precision=prec))
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        st = h.solve(dev(o.b), x)
+        outs.append((host(x), st["iters"]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
