@@ -77,17 +77,19 @@ def time_solves(torch, h, b, x, steps, warmup):
 def counter_traffic(workload_name):
     """HBM bytes per launch of the finest-level FP64 sweep from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy), or None when
-    the kernel or runtime source (which decides the data layout) has changed since the
-    counters were taken."""
+    any HIP source of the library (kernels, or the runtime that decides the data layout) has
+    changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_sweep_fp64_counters.json")
     h = hashlib.sha256()
     try:
         with open(path) as f:
             table = json.load(f)
-        for name in ("mgq1_kernels.hip", "mgq1_runtime.hip"):
-            with open(os.path.join(ROOT, "paper_2405_05047_amd", "csrc", name), "rb") as f:
-                h.update(f.read())
+        csrc = os.path.join(ROOT, "paper_2405_05047_amd", "csrc")
+        for name in sorted(os.listdir(csrc)):
+            if name.endswith((".hip", ".h")):
+                with open(os.path.join(csrc, name), "rb") as f:
+                    h.update(f.read())
     except OSError:
         return None
     digest = h.hexdigest()

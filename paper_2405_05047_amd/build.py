@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_GEN = os.path.join(HERE, "libmggen.so")
 LIB_MG = os.path.join(HERE, "libmgq1.so")
 
-HIP_SOURCES = ["mgq1_kernels.hip", "mgq1_runtime.hip"]
+HIP_SOURCES = ["mgq1_kernels.hip", "mgq1_batch.hip", "mgq1_runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
@@ -35,12 +35,23 @@ def build_gen():
 
 
 def build_hip():
-    srcs = [os.path.join(CSRC, s) for s in HIP_SOURCES]
-    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-ffp-contract=on", "-Wall",
-           "-I", INCLUDE] + srcs + ["-o", LIB_MG + ".tmp"]
-    _run(cmd)
+    """Compile the HIP translation units in parallel (the kernel units dominate), then link."""
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    flags = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-ffp-contract=on", "-Wall", "-I", INCLUDE]
+    procs, objs = [], []
+    for src in HIP_SOURCES:
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
+        print("+", " ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd))
+        objs.append(obj)
+    failed = [p.args for p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", LIB_MG + ".tmp"])
     os.replace(LIB_MG + ".tmp", LIB_MG)
 
 

@@ -1577,7 +1577,8 @@ int setup_batch(mg_batch* h, const std::vector<std::vector<HostLevel>>& HH, hipS
   for (const auto& pr : h->pr)
     for (const LevelDev& D : pr.lv) h->c16 = h->c16 && D.Ac.col16 && D.A64.col16;
   // one launch streams the operators of every problem: they stay in the memory-side cache
-  // only if the whole batch's do, so the load kind follows the batch total
+  // only if the whole batch's do, so the load kind of the transfers follows the batch
+  // total (the batched slice kernels always read their operators non-temporally)
   {
     auto sbytes = [](const SellDev& A) {
       const int vb = A.kind == VK_F64 ? 8 : A.kind == VK_F32 ? 4 : 2;
