@@ -119,6 +119,34 @@ def forcing_field(fields, x):
     return out
 
 
+def elasticity_mms_displacement(x):
+    """Manufactured displacement u = sin(pi x) sin(pi y) sin(pi z) c, c = ELAST_MMS_DIR,
+    at points x (n, 3); zero on the boundary of the unit cube."""
+    s = np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1]) * np.sin(np.pi * x[:, 2])
+    return s[:, None] * np.asarray(W.ELAST_MMS_DIR)[None, :]
+
+
+def elasticity_mms_load(wl, x):
+    """Body load f = -div sigma(u) of the manufactured displacement, with
+    sigma = 2 mu eps(u) + lambda div(u) I (Sec. 5.2), i.e. f = -mu lap u - (lambda + mu)
+    grad div u.  For u = s c with s = sin(pi x) sin(pi y) sin(pi z): lap u = -3 pi^2 s c
+    and grad div u = Hess(s) c, Hess(s)_ii = -pi^2 s, Hess(s)_ij = pi^2 cos cos sin."""
+    c = np.asarray(W.ELAST_MMS_DIR)
+    sn = np.sin(np.pi * x)
+    cs = np.cos(np.pi * x)
+    s = sn[:, 0] * sn[:, 1] * sn[:, 2]
+    hess = np.empty((len(x), 3, 3))
+    for i in range(3):
+        for j in range(3):
+            if i == j:
+                hess[:, i, j] = -np.pi ** 2 * s
+            else:
+                k = 3 - i - j
+                hess[:, i, j] = np.pi ** 2 * cs[:, i] * cs[:, j] * sn[:, k]
+    lap = -3.0 * np.pi ** 2 * s[:, None] * c[None, :]
+    return -wl.mu * lap - (wl.lam + wl.mu) * np.einsum("nij,j->ni", hess, c)
+
+
 # ------------------------------------------------------------------ element matrices
 def element_matrices(wl, s, x0):
     """Element matrices Ke (ne, nb, nb, b, b) for boxes of side s (ne,) with lower
@@ -209,6 +237,10 @@ def element_loads(wl, s, x0, xi=None, node_ids=None):
         fv = forcing_field(fields, xq.reshape(-1, 3)).reshape(ne, len(qp), 3)
         for k in range(3):
             Fe[..., 1 + k] = np.einsum("eq,eq,qa->ea", wq, fv[..., k], phi)
+    elif wl.rhs == W.RHS_ELAST_MMS:
+        fv = elasticity_mms_load(wl, xq.reshape(-1, 3)).reshape(ne, len(qp), 3)
+        for k in range(3):
+            Fe[..., k] = np.einsum("eq,eq,qa->ea", wq, fv[..., k], phi)
     elif wl.rhs in (W.RHS_NOISE, W.RHS_NONE):
         pass
     else:

@@ -211,13 +211,14 @@ class Multigrid:
         return self.mg_iteration(b, x0, **kw)
 
 
-def l2_error(hier, x, exact: Callable) -> float:
-    """L2 norm of u_h - u on the finest mesh, 3-point tensor Gauss per direction,
-    u_h = H x (hanging values interpolated) evaluated per leaf from its corner values."""
+def l2_error(hier, x, exact: Callable, comp: int = 0) -> float:
+    """L2 norm of u_h - u for component `comp` on the finest mesh, 3-point tensor Gauss
+    per direction, u_h = H x (hanging values interpolated) evaluated per leaf from its
+    corner values; exact(points) returns that component's values."""
     from . import fem
     top = hier.finest
     mesh = top.mesh
-    xf = mesh.H @ x.reshape(mesh.n, -1)[:, 0]
+    xf = mesh.H @ x.reshape(mesh.n, -1)[:, comp]
     s, x0, nodes = fem.leaf_table(mesh)
     qp, qw = fem.tensor_rule(mesh.dim, 3)
     phi, _ = fem.ref_basis(mesh.dim, qp)

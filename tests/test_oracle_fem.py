@@ -231,3 +231,159 @@ def test_load_closed_form():
     f = fem.assemble_load(m, wl)
     # int 2 pi^2 sin(pi x) sin(pi y) over the unit square = 8
     assert f.sum() == pytest.approx(8.0, rel=1e-6)
+
+
+# ---------------------------------------------------------------- elasticity form (Sec. 5.2)
+def _linear_field(m, comp, axis):
+    """Nodal vector (n * 3) of the displacement u = x_axis e_comp (exact in Q1)."""
+    u = np.zeros((m.n, 3))
+    u[:, comp] = m.coords[:, axis]
+    return u.ravel()
+
+
+def test_elasticity_energy_closed_forms():
+    """a(u, v) = 2 mu (eps(u), eps(v)) + lambda (div u, div v) on linear fields, which Q1
+    reproduces and 2-point Gauss integrates exactly, over the unit cube (|Omega| = 1):
+    uniaxial stretch u = (x, 0, 0): 2 mu + lambda; pure shear u = (y, 0, 0): mu;
+    a((x,0,0), (0,y,0)) = lambda (only the div-div term couples them).  lambda != mu, so
+    exchanging the two coefficients anywhere in the form fails these."""
+    wl = W.c3_elasticity(1).with_(lam=1.0, mu=0.5)
+    m, A = _full_matrix(wl)
+    ux = _linear_field(m, 0, 0)
+    uy = _linear_field(m, 1, 1)
+    sh = _linear_field(m, 0, 1)
+    assert ux @ A @ ux == pytest.approx(2 * wl.mu + wl.lam, abs=1e-13)
+    assert sh @ A @ sh == pytest.approx(wl.mu, abs=1e-13)
+    assert ux @ A @ uy == pytest.approx(wl.lam, abs=1e-13)
+    # a rotation-free symmetric shear u = (y, x, 0): eps_xy = 1, energy 2 mu * 2 = 4 mu
+    ss = _linear_field(m, 0, 1) + _linear_field(m, 1, 0)
+    assert ss @ A @ ss == pytest.approx(4 * wl.mu, abs=1e-13)
+    # dilatation u = x: eps = I, div u = 3 -> 6 mu + 9 lambda
+    dl = _linear_field(m, 0, 0) + _linear_field(m, 1, 1) + _linear_field(m, 2, 2)
+    assert dl @ A @ dl == pytest.approx(6 * wl.mu + 9 * wl.lam, abs=1e-12)
+
+
+def test_elasticity_manufactured_O_h2():
+    """Manufactured displacement u = sin(pi x) sin(pi y) sin(pi z) c (clamped cube), load
+    f = -mu lap u - (lambda + mu) grad div u: the L2 error of the discrete solution falls
+    by ~4 per refinement in every component (a swapped lambda/mu, a sign error in the
+    load or in the form would leave an O(1) error)."""
+    from scipy.sparse.linalg import cg
+    from oracle import multigrid as MG
+    errs = []
+    for r in (2, 3, 4):
+        h = Hh.build(W.elasticity_mms(r).with_(coarse_level=99))     # finest level only
+        x, info = cg(h.finest.A, h.b, rtol=1e-12, maxiter=5000)      # SPD; far below the O(h^2) error
+        assert info == 0
+        errs.append([MG.l2_error(h, x, lambda p, c=c: fem.elasticity_mms_displacement(p)[:, c], comp=c)
+                     for c in range(3)])
+    errs = np.array(errs)
+    ratios = errs[:-1] / errs[1:]
+    assert np.all(ratios[-1] > 3.7) and np.all(ratios[-1] < 4.3), ratios
+    assert errs[-1].max() < 2e-2 * np.abs(W.ELAST_MMS_DIR).max()
+
+
+def test_elasticity_mms_load_matches_finite_differences():
+    """The closed-form load equals -div sigma(u) formed by central differences of the
+    manufactured displacement (independent of the Hessian formula)."""
+    wl = W.elasticity_mms(2)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0.1, 0.9, (20, 3))
+    d = 1e-3
+    u = fem.elasticity_mms_displacement
+
+    def grad(p):                       # (n, 3 comps, 3 dirs)
+        g = np.zeros((len(p), 3, 3))
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = d
+            g[:, :, k] = (u(p + e) - u(p - e)) / (2 * d)
+        return g
+
+    def sigma(p):
+        g = grad(p)
+        eps = 0.5 * (g + g.transpose(0, 2, 1))
+        tr = np.trace(eps, axis1=1, axis2=2)
+        return 2 * wl.mu * eps + wl.lam * tr[:, None, None] * np.eye(3)[None]
+
+    div = np.zeros((len(x), 3))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = d
+        div += (sigma(x + e)[:, :, k] - sigma(x - e)[:, :, k]) / (2 * d)
+    assert np.allclose(fem.elasticity_mms_load(wl, x), -div, rtol=0, atol=1e-4)
+
+
+# ---------------------------------------------------------------- flow step (Oseen) blocks
+def test_oseen_coupling_and_mass_blocks():
+    """Signs and placement of the velocity-pressure coupling and of the mass term:
+      * (div u, q) row p, columns u_k (block B) and -(p, div v) row v_k, column p
+        (block C) satisfy C = -B^T entry by entry;
+      * B (x e_1) = lumped masses (int phi_i, since div(x e_1) = 1) at every node;
+      * C (p = x) at interior velocity rows of component 1 = +int phi_i (integration by
+        parts: -(x, d_x phi_i) = (1, phi_i)), 0 for the other components;
+      * 1^T A_{u_k u_k} 1 = |Omega| / dt (grad and beta.grad of a constant vanish)."""
+    wl = W.c4_oseen(1)
+    m, A = _full_matrix(wl)
+    n = m.n
+    B = np.stack([A[0::4, 1 + k::4] for k in range(3)])          # (3, n, n): row p, col u_k
+    C = np.stack([A[1 + k::4, 0::4] for k in range(3)])          # row u_k, col p
+    for k in range(3):
+        assert np.array_equal(C[k], -B[k].T)
+    lumped = fem.assemble_load(m, wl.with_(rhs=W.RHS_NOISE, block=1), np.ones((n, 1)))[:, 0]
+    X = m.coords
+    assert np.allclose(B[0] @ X[:, 0], lumped, rtol=0, atol=1e-15)
+    assert np.allclose(B[1] @ X[:, 1], lumped, rtol=0, atol=1e-15)
+    interior = ~m.boundary_mask(0b111111)
+    Cp = C[0] @ X[:, 0]
+    assert np.allclose(Cp[interior], lumped[interior], rtol=0, atol=1e-15)
+    assert np.abs(C[1] @ X[:, 0])[interior].max() < 1e-15
+    for k in range(3):
+        Auu = A[1 + k::4, 1 + k::4]
+        assert np.ones(n) @ Auu @ np.ones(n) == pytest.approx(1.0 / wl.dt, rel=1e-13)
+
+
+def test_beta_divergence_free_and_curl():
+    """beta = curl(psi) for psi = sum_k a_k sin(2 pi kappa_k.x + phi_k) e_{j_k} (scaled):
+    compared with the curl of psi by central differences, and its divergence by central
+    differences vanishes; the analytic bound keeps max |beta| <= 1."""
+    fields = W.oseen_fields(0)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0.0, 1.0, (50, 3))
+    d = 1e-5
+
+    def psi(p):
+        out = np.zeros((len(p), 3))
+        for k in range(8):
+            out[:, fields["j"][k]] += fields["a"][k] * np.sin(2 * np.pi * p @ fields["kappa"][k] + fields["phi"][k])
+        return out * fields["scale"]
+
+    J = np.zeros((len(x), 3, 3))           # J[:, i, k] = d psi_i / d x_k
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = d
+        J[:, :, k] = (psi(x + e) - psi(x - e)) / (2 * d)
+    curl = np.stack([J[:, 2, 1] - J[:, 1, 2], J[:, 0, 2] - J[:, 2, 0], J[:, 1, 0] - J[:, 0, 1]], axis=1)
+    beta = fem.beta_field(fields, x)
+    assert np.allclose(beta, curl, rtol=0, atol=1e-8)
+    div = np.zeros(len(x))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = d
+        div += (fem.beta_field(fields, x + e)[:, k] - fem.beta_field(fields, x - e)[:, k]) / (2 * d)
+    assert np.abs(div).max() < 1e-8
+    g = rng.uniform(0.0, 1.0, (20000, 3))
+    assert np.sqrt((fem.beta_field(fields, g) ** 2).sum(axis=1)).max() <= 1.0
+
+
+@pytest.mark.parametrize("wl", [W.c2_td(band_rounds=3, uniform_rounds=1), W.c3_adaptive("edge", 3)])
+def test_lumped_mass(wl):
+    """Lumped masses m_i = sum_j (phi_j, phi_i) = int phi_i (mass lumping by row sums):
+    the load of nodal ones equals the Gauss-integrated load of f = 1 at every node
+    (hanging ones included), and they sum to |Omega|."""
+    m = M.Mesh(M.build_forest(wl))
+    wl1 = wl.with_(block=1, pde=W.PDE_POISSON)
+    lumped = fem.assemble_load(m, wl1.with_(rhs=W.RHS_NOISE), np.ones((m.n, 1)))[:, 0]
+    ref = fem.assemble_load(m, wl1.with_(rhs=W.RHS_CONST, rhs_const=(1.0,)))[:, 0]
+    assert np.allclose(lumped, ref, rtol=1e-14, atol=0)
+    assert lumped.sum() == pytest.approx(float(np.prod(np.array(wl.coarse) * wl.h0)), rel=1e-14)

@@ -31,7 +31,7 @@ import numpy as np
 # ---------------------------------------------------------------------------
 
 PDE_POISSON, PDE_TD, PDE_ELASTICITY, PDE_OSEEN = 0, 1, 2, 3
-RHS_SINSIN, RHS_DISK, RHS_CONST, RHS_FIELD, RHS_NOISE, RHS_NONE = 0, 1, 2, 3, 4, 5
+RHS_SINSIN, RHS_DISK, RHS_CONST, RHS_FIELD, RHS_NOISE, RHS_NONE, RHS_ELAST_MMS = 0, 1, 2, 3, 4, 5, 6
 OUTER_IR, OUTER_FGMRES = 0, 1
 COARSE_EXACT, COARSE_SMOOTH = 0, 1
 PREC_FP64, PREC_FP32, PREC_FP32_F16VAL, PREC_FP32_BF16VAL = 0, 1, 2, 3
@@ -123,6 +123,20 @@ def c3_elasticity(rounds: int = 6) -> Workload:
                     lam=1.0, mu=0.5, dir_faces=0b000001, dir_comps=0b111,
                     rhs=RHS_CONST, rhs_const=(0.0, -1.0, 0.0),
                     omega=0.6, nu1=2, nu2=2, outer=OUTER_FGMRES, rtol=1e-8)
+
+
+def elasticity_mms(rounds: int = 3) -> Workload:
+    """3D linear elasticity (lambda = 1, mu = 0.5) on the unit cube, clamped on every face,
+    with the body load of the manufactured displacement
+    u(x) = sin(pi x) sin(pi y) sin(pi z) * ELAST_MMS_DIR (used for the O(h^2) error check)."""
+    return Workload(name=f"elast3d_mms_u{rounds}", dim=3, coarse=(2, 2, 2), h0=0.5,
+                    rounds=(("uniform",),) * rounds, pde=PDE_ELASTICITY, block=3,
+                    lam=1.0, mu=0.5, dir_faces=ALL_FACES_3D, dir_comps=0b111,
+                    rhs=RHS_ELAST_MMS, omega=0.6, nu1=2, nu2=2, outer=OUTER_FGMRES, rtol=1e-10)
+
+
+# direction of the manufactured elasticity displacement
+ELAST_MMS_DIR = (1.0, -0.5, 0.75)
 
 
 def c3_adaptive(kind: str, level: int) -> Workload:
