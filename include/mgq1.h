@@ -65,6 +65,11 @@ typedef struct {
   const double* P_val;        /* p_nnz weights (without the masks) */
   const uint8_t* dof_mask;    /* n_nodes * b; 1 = constrained DoF: its row and column of A
                                  must be the identity row / column */
+  const double* smoother_blocks; /* optional fixed smoother S (Sec. 4.1: x <- x + omega S
+                                 (b - A x) with S a fixed matrix): n_nodes b x b blocks,
+                                 row-major, node i's block applied to node i's defect;
+                                 NULL = the inverses of A's nodal diagonal blocks, computed
+                                 on the device.  Values must be finite. */
 } mg_level_in;
 
 typedef struct {
@@ -98,14 +103,23 @@ typedef struct {
 typedef struct mg_handle mg_handle;
 
 /* Copy a hierarchy to the device and prepare smoother blocks, R = P~^T, the coarse
- * inverse and reduced-precision copies.  `lv[0]` is the coarsest level.
- * inputs_on_device: 0 = host pointers, 1 = device pointers.  stream: hipStream_t or NULL. */
+ * inverse and reduced-precision copies.  `lv[0]` is the coarsest level.  The hierarchy is
+ * that of Sec. 2.2 (global coarsening of the adaptive mesh, one Q1 space per level, the
+ * constrained operator A_l of each level), with the transfers of Sec. 4.1 ("Geometric
+ * Multigrid CUDA": prolongation matrices assembled once, restriction as their transpose).
+ * inputs_on_device: 0 = host pointers, 1 = device pointers.  stream: hipStream_t or NULL.
+ * Every level is validated as by mg_validate_level; on any error nothing is kept and *out
+ * is NULL. */
 int mg_setup_hierarchy(const mg_level_in* lv, int32_t n_levels, const mg_config* cfg,
                        int32_t inputs_on_device, void* stream, mg_handle** out);
 
-/* x = GMG(L, 0, b): one V-cycle on the finest level from the initial value 0
- * (Algorithm "Geometric multigrid solver").  b, x: device FP64, n_L * b each. */
-int mg_vcycle(mg_handle* h, const double* b, double* x, void* stream);
+/* One V-cycle on the finest level (Algorithm "Geometric multigrid solver"):
+ * x_is_zero != 0: x = GMG(L, 0, b) (the input value of x is not read);
+ * x_is_zero == 0: x = GMG(L, x, b) with the input x as the initial iterate (nu1 full
+ * pre-sweeps from it).  b, x: device FP64, n_L * b each; x must not alias b (MG_EINVAL).
+ * On a mixed-precision handle b and x are rounded to FP32 for the cycle and x is
+ * returned in FP64. */
+int mg_vcycle(mg_handle* h, const double* b, double* x, int32_t x_is_zero, void* stream);
 
 /* Solve A_L x = b to rtol (x is the initial guess on entry, the result on exit).
  * MG_OUTER_IR: x <- x + V(b - A x) (the MG iteration of Algorithm "Geometric multigrid
@@ -118,25 +132,43 @@ int mg_solve(mg_handle* h, const double* b, double* x, mg_solve_stats* stats, vo
 int mg_solve_fixed(mg_handle* h, const double* b, double* x, int32_t iters,
                    mg_solve_stats* stats, void* stream);
 
-/* The hot-path steps one at a time on level `level` (FP64 handles only; device FP64):
+/* The outer defect of the finest level in FP64 for every precision (the first step of
+ * the MG iteration and of each GMRES restart, Sec. 4.2): r = b - A_L x and
+ * *norm = ||r||_2.  b, x, r: device FP64 (n_L * b), r must not alias b or x;
+ * norm: one device double.  Enqueued on `stream`, nothing is synchronised; uses the
+ * handle's partial-sum buffer, so calls on one handle must not overlap. */
+int mg_outer_defect(mg_handle* h, const double* b, const double* x, double* r, double* norm, void* stream);
+
+/* The V-cycle steps one at a time on level `level`, with the operator and vectors of the
+ * cycle precision: device FP64 vectors on MG_PREC_FP64 handles, device FP32 vectors (and
+ * FP32 / FP16 x 2^e / BF16 x 2^e stored values, FP32 arithmetic) on the others:
  *   mg_level_defect   r = b - A_l x            (masked = 1: r = 0 on constrained DoFs)
  *   mg_level_spmv     y = A_l x
  *   mg_level_sweep    x_out = x + omega S_l (b - A_l x)      (Sec. 4.1 smoother)
  *   mg_level_sweep0   x_out = omega S_l b                    (first sweep from 0)
- *   mg_level_restrict d_{l-1} = R_{l-1} r = M_{l-1} P~^T M_l r
+ *   mg_level_restrict d_{l-1} = R_{l-1} r = M_{l-1} P~^T M_l r  (Sec. 4.1 transfers)
  *   mg_level_prolong  x_l += M_l P~ M_{l-1} y_{l-1}
- *   mg_coarse_solve   x_0 = A_0^{-1} b_0 (or coarse_sweeps sweeps from 0)          */
-int mg_level_defect(mg_handle* h, int32_t level, const double* b, const double* x, double* r,
+ *   mg_coarse_solve   x_0 = A_0^{-1} b_0 (FP64 inverse; or coarse_sweeps sweeps from 0)
+ * Outputs must not alias inputs (MG_EINVAL); prolongation updates x_fine in place. */
+int mg_level_defect(mg_handle* h, int32_t level, const void* b, const void* x, void* r,
                     int32_t masked, void* stream);
-int mg_level_spmv(mg_handle* h, int32_t level, const double* x, double* y, void* stream);
-int mg_level_sweep(mg_handle* h, int32_t level, const double* b, const double* x, double* x_out,
+int mg_level_spmv(mg_handle* h, int32_t level, const void* x, void* y, void* stream);
+int mg_level_sweep(mg_handle* h, int32_t level, const void* b, const void* x, void* x_out,
                    void* stream);
-int mg_level_sweep0(mg_handle* h, int32_t level, const double* b, double* x_out, void* stream);
-int mg_level_restrict(mg_handle* h, int32_t level, const double* r_fine, double* d_coarse,
+int mg_level_sweep0(mg_handle* h, int32_t level, const void* b, void* x_out, void* stream);
+int mg_level_restrict(mg_handle* h, int32_t level, const void* r_fine, void* d_coarse,
                       void* stream);
-int mg_level_prolong(mg_handle* h, int32_t level, const double* y_coarse, double* x_fine,
+int mg_level_prolong(mg_handle* h, int32_t level, const void* y_coarse, void* x_fine,
                      void* stream);
-int mg_coarse_solve(mg_handle* h, const double* b, double* x, void* stream);
+int mg_coarse_solve(mg_handle* h, const void* b, void* x, void* stream);
+
+/* The stored cycle operator of level `level` in the input's BSR order (the encoding of
+ * the reduced-precision form: values rounded to FP32, or a_ij / 2^e_i rounded to FP16 /
+ * BF16 with e_i the smallest integer with max_j |a_ij| <= 2^e_i per scalar row).
+ * values: host buffer of nnzb * b * b entries of the storage type (double, float or
+ * uint16 codes), block row-major; row_exp: host buffer of n_nodes * b exponents e_i,
+ * required for FP16 / BF16 handles, ignored (may be NULL) otherwise.  Synchronous. */
+int mg_level_export(const mg_handle* h, int32_t level, void* values, int8_t* row_exp);
 
 /* Sizes of level `level`: nodes, block size, stored blocks. */
 int mg_level_info(const mg_handle* h, int32_t level, int32_t* n_nodes, int32_t* block,

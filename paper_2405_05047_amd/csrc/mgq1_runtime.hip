@@ -44,6 +44,7 @@ struct HostLevel {
   std::vector<int32_t> prow, pcol;
   std::vector<double> pval;
   std::vector<uint8_t> mask;
+  std::vector<double> sblk;         // caller's smoother blocks (empty: derived on the device)
 };
 
 template <class T>
@@ -86,6 +87,8 @@ int validate_host(const HostLevel& L, const HostLevel* C, int level) {
     }
     if (!diag) return fail(MG_EINVAL, at + "missing diagonal block");
   }
+  for (double v : L.sblk)
+    if (!std::isfinite(v)) return fail(MG_EINVAL, at + "non-finite smoother block value");
   if (C) {
     if (C->B != B) return fail(MG_EINVAL, at + "block size differs between levels");
     if (L.pc != C->n) return fail(MG_EINVAL, at + "p_cols != n_nodes of the coarser level");
@@ -113,6 +116,7 @@ int load_level(const mg_level_in& in, bool on_dev, bool want_p, HostLevel& L) {
   if ((rc = fetch(L.col, in.A_col, size_t(L.nnzb), on_dev))) return rc;
   if ((rc = fetch(L.val, in.A_val, size_t(L.nnzb) * L.B * L.B, on_dev))) return rc;
   if ((rc = fetch(L.mask, in.dof_mask, size_t(L.n) * L.B, on_dev))) return rc;
+  if (in.smoother_blocks && (rc = fetch(L.sblk, in.smoother_blocks, size_t(L.n) * L.B * L.B, on_dev))) return rc;
   if (want_p) {
     L.pc = in.p_cols;
     if (!in.P_rowptr) return fail(MG_EINVAL, "missing P on a level above 0");
@@ -416,6 +420,9 @@ struct LevelDev {
   TSellDev Ps, Rs;        // the same transfers, sliced (grid kernels)
   void *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;   // cycle vectors
   double us_def = 0.0, us_alt = 0.0;  // measured sweep time of the two slot batches (tuning)
+  // host copies of the operator's geometry (single-problem handles): BSR row pointers,
+  // slice pointers and row positions of the sliced layout, to map stored values back
+  std::vector<int32_t> hrow, hsptr, hperm;
 };
 
 struct mg_handle : DevOwner {
@@ -652,10 +659,11 @@ int smooth_level(mg_handle* h, int l, const void* b, void*& cur, void*& other, i
   return MG_OK;
 }
 
-// x = GMG(L, 0, b) with b, x in cycle precision; x must not alias b.
+// x = GMG(L, 0, b) (xinit = false) or GMG(L, x, b) with the initial iterate in xL (xinit =
+// true), b and x in cycle precision; x must not alias b.
 // Levels above tail_top use grid-wide kernels; levels 0..tail_top run in one
 // single-workgroup launch (same steps, same order of ping-pong buffers).
-int vcycle_cycle(mg_handle* h, const void* bL, void* xL, hipStream_t s) {
+int vcycle_cycle(mg_handle* h, const void* bL, void* xL, hipStream_t s, bool xinit = false) {
   const int L = h->L;
   const mg_config& c = h->cfg;
   const int top = h->tail_top;
@@ -673,6 +681,21 @@ int vcycle_cycle(mg_handle* h, const void* bL, void* xL, hipStream_t s) {
   };
   for (int l = L; l > top; --l) {
     LevelDev& Lv = h->lv[l];
+    if (l == L && xinit) {
+      // nu1 + nu2 full sweeps from the given iterate: start in xL when their number is
+      // even, else in a copy of it, so that the last post-sweep writes xL
+      if ((c.nu1 + c.nu2) % 2 == 0) { cur[l] = xL; oth[l] = Lv.t; }
+      else {
+        MG_HIP(launch_convert(Lv.N, xL, h->xk, Lv.t, h->xk, s));
+        cur[l] = Lv.t;
+        oth[l] = xL;
+      }
+      int rc = smooth_level(h, l, bb[l], cur[l], oth[l], c.nu1, s);
+      if (rc) return rc;
+      MG_HIP(launch_spmv(Lv.Ac, bb[l], cur[l], Lv.r, Lv.mask, h->xk, h->xk, 2, nullptr, s));
+      MG_HIP(launch_restrict_s(Lv.Rs, Lv.B, Lv.r, h->lv[l - 1].b, h->lv[l - 1].mask, nullptr, h->xk, s));
+      continue;
+    }
     first_buffers(l, pre_pp + c.nu2);
     if (c.nu1 >= 2 && Lv.B == 1 && h->fuse2z) {
       // the first two sweeps from 0 in one pass; leaves the iterate where the second
@@ -906,7 +929,6 @@ int solve_impl(mg_handle* h, const double* b, double* x, mg_solve_stats* st, voi
 int check_level(const mg_handle* h, int level) {
   if (!h) return fail(MG_EINVAL, "null handle");
   if (level < 0 || level > h->L) return fail(MG_EINVAL, "level out of range");
-  if (h->xk != X_F64) return fail(MG_EUNSUPPORTED, "step-wise entry points need an FP64 handle");
   return MG_OK;
 }
 
@@ -949,7 +971,7 @@ int load_hierarchy(const mg_level_in* lv, int n_levels, bool on_dev, std::vector
 // one level on the device: FP64 and cycle operators (sliced ELL for NR right-hand sides),
 // smoother blocks, mask, P~ and R = P~^T; with vectors = true also x, b, r, t
 int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, int xk, bool vectors, int* flag,
-                hipStream_t s, LevelDev& D) {
+                hipStream_t s, LevelDev& D, bool keep_host = false) {
   int rc;
   D.n = L.n;
   D.B = L.B;
@@ -961,8 +983,36 @@ int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, 
   else if ((rc = upload_sell(h, S, vkind, D.Ac, s))) return rc;
   const size_t sblk = size_t(S.nslices) * L.B * S.W;
   if ((rc = dalloc(h, reinterpret_cast<char**>(&D.S), sblk * xsize(xk)))) return rc;
-  MG_HIP(launch_fill(int64_t(sblk), D.S, xk, 0.0, s));
-  MG_HIP(launch_block_invert(D.A64, D.S, xk, flag, NR, s));
+  if (L.sblk.empty()) {
+    MG_HIP(launch_fill(int64_t(sblk), D.S, xk, 0.0, s));
+    MG_HIP(launch_block_invert(D.A64, D.S, xk, flag, NR, s));
+  } else {
+    // the caller's fixed smoother matrix S (Sec. 4.1) in the lane layout of the sweeps:
+    // lane r * B + c of a slice holds row c of its node's block, column cc at
+    // S[(slice * B + cc) * W + r * B + c]
+    std::vector<double> lane(sblk, 0.0);
+    const int B = L.B;
+    for (int64_t pos = 0; pos < L.n; ++pos) {
+      const int64_t node = S.perm.empty() ? pos : S.perm[size_t(pos)];
+      const int64_t slice = pos / S.R, r = pos % S.R;
+      for (int c = 0; c < B; ++c)
+        for (int cc = 0; cc < B; ++cc)
+          lane[size_t((slice * B + cc) * S.W + r * B + c)] = L.sblk[size_t(node * B * B + c * B + cc)];
+    }
+    if (xk == X_F64) {
+      MG_HIP(hipMemcpyAsync(D.S, lane.data(), sblk * sizeof(double), hipMemcpyHostToDevice, s));
+      MG_HIP(hipStreamSynchronize(s));
+    } else {
+      std::vector<float> lf(lane.begin(), lane.end());
+      MG_HIP(hipMemcpyAsync(D.S, lf.data(), sblk * sizeof(float), hipMemcpyHostToDevice, s));
+      MG_HIP(hipStreamSynchronize(s));
+    }
+  }
+  if (keep_host) {
+    D.hrow = L.rowptr;
+    D.hsptr = S.sptr;
+    D.hperm = S.perm;
+  }
   if ((rc = upload(h, &D.mask, L.mask, s))) return rc;
   if (has_p) {
     CsrHost P;
@@ -1113,7 +1163,7 @@ int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
   MG_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
   const int vkind = value_kind(c.precision);
   for (int l = 0; l < n_levels; ++l)
-    if ((rc = setup_level(h, H[l], l > 0, 1, vkind, h->xk, true, flag, s, h->lv[l]))) return rc;
+    if ((rc = setup_level(h, H[l], l > 0, 1, vkind, h->xk, true, flag, s, h->lv[l], true))) return rc;
   if ((rc = setup_coarse_inverse(h, H[0], flag, s, &h->Ainv, &h->n0))) return rc;
   if ((rc = check_flag(flag, s))) return rc;
   // outer-loop storage
@@ -1580,16 +1630,18 @@ int setup_batch(mg_batch* h, const std::vector<std::vector<HostLevel>>& HH, hipS
   // only if the whole batch's do, so the load kind of the transfers follows the batch
   // total (the batched slice kernels always read their operators non-temporally)
   {
-    auto sbytes = [](const SellDev& A) {
+    // value lanes per slot: B * W with the row-lane stride W = kWave / NR of the batch
+    const int64_t W = kWave / NR;
+    auto sbytes = [W](const SellDev& A) {
       const int vb = A.kind == VK_F64 ? 8 : A.kind == VK_F32 ? 4 : 2;
-      return A.slots * (int64_t(A.B) * kWave * vb + int64_t(A.R) * (A.col16 ? 2 : 4));
+      return A.slots * (int64_t(A.B) * W * vb + int64_t(A.R) * (A.col16 ? 2 : 4));
     };
     int64_t tot = 0;
     for (const auto& pr : h->pr)
       for (const LevelDev& D : pr.lv) tot += sbytes(D.Ac) + (D.A64.val != D.Ac.val ? sbytes(D.A64) : 0);
     const int nt = stream_nt(tot);
     for (auto& pr : h->pr)
-      for (LevelDev& D : pr.lv) D.Ac.nt = D.A64.nt = D.Ps.nt = D.Rs.nt = nt;
+      for (LevelDev& D : pr.lv) D.Ps.nt = D.Rs.nt = nt;
   }
   const int64_t N = h->Ntot = h->off[P];
   const int m = c.gmres_m;
@@ -1868,13 +1920,20 @@ int mg_setup_hierarchy(const mg_level_in* lv, int32_t n_levels, const mg_config*
   return MG_OK;
 }
 
-int mg_vcycle(mg_handle* h, const double* b, double* x, void* stream) {
+int mg_vcycle(mg_handle* h, const double* b, double* x, int32_t x_is_zero, void* stream) {
   if (!h || !b || !x) return fail(MG_EINVAL, "null argument");
+  if (static_cast<const void*>(b) == static_cast<const void*>(x)) return fail(MG_EINVAL, "x must not alias b");
+  const bool xinit = x_is_zero == 0;
+  if (xinit && h->L > 0 && h->tail_top == h->L)
+    return fail(MG_EUNSUPPORTED, "an initial iterate needs the finest level outside the single-workgroup tail");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (h->xk == X_F64) return vcycle_cycle(h, b, x, s);
-  int rc = precond(h, b, h->e, s);
+  if (h->xk == X_F64) return vcycle_cycle(h, b, x, s, xinit);
+  const int64_t N = h->lv[h->L].N;
+  MG_HIP(launch_convert(N, b, X_F64, h->bcyc, h->xk, s));
+  if (xinit) MG_HIP(launch_convert(N, x, X_F64, h->e, h->xk, s));
+  int rc = vcycle_cycle(h, h->bcyc, h->e, s, xinit);
   if (rc) return rc;
-  MG_HIP(launch_convert(h->lv[h->L].N, h->e, h->xk, x, X_F64, s));
+  MG_HIP(launch_convert(N, h->e, h->xk, x, X_F64, s));
   return MG_OK;
 }
 
@@ -1888,74 +1947,124 @@ int mg_solve_fixed(mg_handle* h, const double* b, double* x, int32_t iters, mg_s
   return solve_impl(h, b, x, st, stream, iters);
 }
 
-int mg_level_defect(mg_handle* h, int32_t level, const double* b, const double* x, double* r, int32_t masked,
+int mg_outer_defect(mg_handle* h, const double* b, const double* x, double* r, double* norm, void* stream) {
+  if (!h || !b || !x || !r || !norm) return fail(MG_EINVAL, "null argument");
+  if (static_cast<const void*>(r) == static_cast<const void*>(x) || static_cast<const void*>(r) == static_cast<const void*>(b))
+    return fail(MG_EINVAL, "r must not alias b or x");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LevelDev& T = h->lv[h->L];
+  MG_HIP(launch_spmv(T.A64, b, x, r, nullptr, X_F64, X_F64, 1, h->pbig, s));
+  MG_HIP(launch_finish(h->pbig, spmv_grid(T.A64), norm, 1, s));
+  return MG_OK;
+}
+
+int mg_level_defect(mg_handle* h, int32_t level, const void* b, const void* x, void* r, int32_t masked,
                     void* stream) {
   int rc = check_level(h, level);
   if (rc) return rc;
+  if (r == x || r == b) return fail(MG_EINVAL, "defect output must not alias its inputs");
   LevelDev& L = h->lv[level];
-  MG_HIP(launch_spmv(L.A64, b, x, r, L.mask, X_F64, X_F64, masked ? 2 : 1, nullptr, static_cast<hipStream_t>(stream)));
+  MG_HIP(launch_spmv(L.Ac, b, x, r, L.mask, h->xk, h->xk, masked ? 2 : 1, nullptr, static_cast<hipStream_t>(stream)));
   return MG_OK;
 }
 
-int mg_level_spmv(mg_handle* h, int32_t level, const double* x, double* y, void* stream) {
+int mg_level_spmv(mg_handle* h, int32_t level, const void* x, void* y, void* stream) {
   int rc = check_level(h, level);
   if (rc) return rc;
+  if (x == y) return fail(MG_EINVAL, "product output must not alias its input");
   LevelDev& L = h->lv[level];
-  MG_HIP(launch_spmv(L.A64, nullptr, x, y, nullptr, X_F64, X_F64, 0, nullptr, static_cast<hipStream_t>(stream)));
+  MG_HIP(launch_spmv(L.Ac, nullptr, x, y, nullptr, h->xk, h->xk, 0, nullptr, static_cast<hipStream_t>(stream)));
   return MG_OK;
 }
 
-int mg_level_sweep(mg_handle* h, int32_t level, const double* b, const double* x, double* x_out, void* stream) {
+int mg_level_sweep(mg_handle* h, int32_t level, const void* b, const void* x, void* x_out, void* stream) {
   int rc = check_level(h, level);
   if (rc) return rc;
-  if (x == x_out) return fail(MG_EINVAL, "sweep output must not alias its input");
+  if (x == x_out || b == x_out) return fail(MG_EINVAL, "sweep output must not alias its inputs");
   LevelDev& L = h->lv[level];
-  MG_HIP(launch_sweep(L.Ac, L.S, b, x, x_out, h->cfg.omega, X_F64, static_cast<hipStream_t>(stream)));
+  MG_HIP(launch_sweep(L.Ac, L.S, b, x, x_out, h->cfg.omega, h->xk, static_cast<hipStream_t>(stream)));
   return MG_OK;
 }
 
-int mg_level_sweep0(mg_handle* h, int32_t level, const double* b, double* x_out, void* stream) {
+int mg_level_sweep0(mg_handle* h, int32_t level, const void* b, void* x_out, void* stream) {
   int rc = check_level(h, level);
   if (rc) return rc;
+  if (b == x_out) return fail(MG_EINVAL, "sweep output must not alias its input");
   LevelDev& L = h->lv[level];
-  MG_HIP(launch_sweep0(L.Ac, L.S, b, x_out, h->cfg.omega, X_F64, static_cast<hipStream_t>(stream)));
+  MG_HIP(launch_sweep0(L.Ac, L.S, b, x_out, h->cfg.omega, h->xk, static_cast<hipStream_t>(stream)));
   return MG_OK;
 }
 
-int mg_level_restrict(mg_handle* h, int32_t level, const double* r_fine, double* d_coarse, void* stream) {
+int mg_level_restrict(mg_handle* h, int32_t level, const void* r_fine, void* d_coarse, void* stream) {
   int rc = check_level(h, level);
   if (rc) return rc;
   if (level < 1) return fail(MG_EINVAL, "restriction needs level >= 1");
   LevelDev& L = h->lv[level];
-  MG_HIP(launch_restrict_s(L.Rs, L.B, r_fine, d_coarse, h->lv[level - 1].mask, L.mask, X_F64,
-                         static_cast<hipStream_t>(stream)));
+  MG_HIP(launch_restrict_s(L.Rs, L.B, r_fine, d_coarse, h->lv[level - 1].mask, L.mask, h->xk,
+                           static_cast<hipStream_t>(stream)));
   return MG_OK;
 }
 
-int mg_level_prolong(mg_handle* h, int32_t level, const double* y_coarse, double* x_fine, void* stream) {
+int mg_level_prolong(mg_handle* h, int32_t level, const void* y_coarse, void* x_fine, void* stream) {
   int rc = check_level(h, level);
   if (rc) return rc;
   if (level < 1) return fail(MG_EINVAL, "prolongation needs level >= 1");
   LevelDev& L = h->lv[level];
-  MG_HIP(launch_prolong_s(L.Ps, L.B, y_coarse, x_fine, L.mask, h->lv[level - 1].mask, X_F64,
-                        static_cast<hipStream_t>(stream)));
+  MG_HIP(launch_prolong_s(L.Ps, L.B, y_coarse, x_fine, L.mask, h->lv[level - 1].mask, h->xk,
+                          static_cast<hipStream_t>(stream)));
   return MG_OK;
 }
 
-int mg_coarse_solve(mg_handle* h, const double* b, double* x, void* stream) {
+int mg_coarse_solve(mg_handle* h, const void* b, void* x, void* stream) {
   int rc = check_level(h, 0);
   if (rc) return rc;
+  if (b == x) return fail(MG_EINVAL, "coarse solution must not alias its right-hand side");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (h->cfg.coarse_mode == MG_COARSE_EXACT) {
-    MG_HIP(launch_coarse_gemv(h->n0, h->Ainv, b, x, X_F64, s));
+    MG_HIP(launch_coarse_gemv(h->n0, h->Ainv, b, x, h->xk, s));
     return MG_OK;
   }
   LevelDev& C0 = h->lv[0];
   const int k = std::max(1, h->cfg.coarse_sweeps);
-  void* cu = ((k - 1) % 2 == 0) ? static_cast<void*>(x) : C0.t;
-  void* ot = ((k - 1) % 2 == 0) ? C0.t : static_cast<void*>(x);
-  MG_HIP(launch_sweep0(C0.Ac, C0.S, b, cu, h->cfg.omega, X_F64, s));
+  void* cu = ((k - 1) % 2 == 0) ? x : C0.t;
+  void* ot = ((k - 1) % 2 == 0) ? C0.t : x;
+  MG_HIP(launch_sweep0(C0.Ac, C0.S, b, cu, h->cfg.omega, h->xk, s));
   return smooth_level(h, 0, b, cu, ot, k - 1, s);
+}
+
+int mg_level_export(const mg_handle* h, int32_t level, void* values, int8_t* row_exp) {
+  if (!h || !values || level < 0 || level > h->L) return fail(MG_EINVAL, "bad handle, level or output");
+  const LevelDev& L = h->lv[level];
+  const SellDev& A = L.Ac;
+  if (L.hrow.empty()) return fail(MG_EUNSUPPORTED, "no host geometry kept for this level");
+  if ((A.kind == VK_F16 || A.kind == VK_BF16) && !row_exp) return fail(MG_EINVAL, "row_exp is required for 16-bit values");
+  const int B = L.B, W = kWave, R = A.R;
+  const int vb = A.kind == VK_F64 ? 8 : A.kind == VK_F32 ? 4 : 2;
+  const int64_t slots = L.hsptr.back();
+  std::vector<char> dv(size_t(slots) * B * W * vb);
+  MG_HIP(hipMemcpy(dv.data(), A.val, dv.size(), hipMemcpyDeviceToHost));
+  std::vector<int8_t> de;
+  if (A.rexp) {
+    de.resize(size_t(A.nslices) * W);
+    MG_HIP(hipMemcpy(de.data(), A.rexp, de.size(), hipMemcpyDeviceToHost));
+  }
+  char* out = static_cast<char*>(values);
+  for (int64_t pos = 0; pos < L.n; ++pos) {
+    const int64_t node = L.hperm.empty() ? pos : L.hperm[size_t(pos)];
+    const int64_t slice = pos / R, r = pos % R;
+    const int32_t len = L.hrow[size_t(node) + 1] - L.hrow[size_t(node)];
+    for (int32_t k = 0; k < len; ++k) {
+      const int64_t slot = int64_t(L.hsptr[size_t(slice)]) + k;
+      const int64_t blk = int64_t(L.hrow[size_t(node)]) + k;
+      for (int c = 0; c < B; ++c)
+        for (int cc = 0; cc < B; ++cc)
+          std::memcpy(out + (size_t(blk) * B * B + c * B + cc) * vb,
+                      dv.data() + (size_t(slot * B + cc) * W + r * B + c) * vb, vb);
+    }
+    if (A.rexp)
+      for (int c = 0; c < B; ++c) row_exp[size_t(node) * B + c] = de[size_t(slice) * W + r * B + c];
+  }
+  return MG_OK;
 }
 
 int mg_level_info(const mg_handle* h, int32_t level, int32_t* n_nodes, int32_t* block, int64_t* nnzb) {

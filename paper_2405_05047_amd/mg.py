@@ -25,7 +25,7 @@ class LevelIn(C.Structure):
                 ("A_rowptr", C.c_void_p), ("A_col", C.c_void_p), ("A_val", C.c_void_p),
                 ("p_cols", C.c_int32), ("p_nnz", C.c_int64),
                 ("P_rowptr", C.c_void_p), ("P_col", C.c_void_p), ("P_val", C.c_void_p),
-                ("dof_mask", C.c_void_p)]
+                ("dof_mask", C.c_void_p), ("smoother_blocks", C.c_void_p)]
 
 
 class Config(C.Structure):
@@ -50,7 +50,7 @@ SYMBOLS = ["mg_setup_hierarchy", "mg_vcycle", "mg_solve", "mg_solve_fixed", "mg_
            "mg_level_prolong", "mg_coarse_solve", "mg_level_info", "mg_num_levels",
            "mg_validate_level", "mg_destroy", "mg_status_string", "mg_last_error",
            "mg_setup_batch", "mg_batch_offsets", "mg_solve_batch", "mg_destroy_batch",
-           "mg_level_tuning"]
+           "mg_level_tuning", "mg_outer_defect", "mg_level_export"]
 
 
 def lib():
@@ -59,7 +59,9 @@ def lib():
         L = load("libmgq1.so")
         vp, i32 = C.c_void_p, C.c_int32
         L.mg_setup_hierarchy.argtypes = [C.POINTER(LevelIn), i32, C.POINTER(Config), i32, vp, C.POINTER(vp)]
-        L.mg_vcycle.argtypes = [vp, vp, vp, vp]
+        L.mg_vcycle.argtypes = [vp, vp, vp, i32, vp]
+        L.mg_outer_defect.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.mg_level_export.argtypes = [vp, i32, vp, vp]
         L.mg_solve.argtypes = [vp, vp, vp, C.POINTER(Stats), vp]
         L.mg_solve_fixed.argtypes = [vp, vp, vp, i32, C.POINTER(Stats), vp]
         L.mg_level_defect.argtypes = [vp, i32, vp, vp, vp, i32, vp]
@@ -124,8 +126,9 @@ def _stream(stream):
     return torch.cuda.current_stream().cuda_stream
 
 
-def level_structs(levels):
-    """mg_level_in array from host levels (objects with rowptr, col, val, p_*, mask)."""
+def level_structs(levels, smoother_blocks=None):
+    """mg_level_in array from host levels (objects with rowptr, col, val, p_*, mask);
+    smoother_blocks: None or one (n, b, b) array (or None) per level."""
     keep = []
     arr = (LevelIn * len(levels))()
     for l, lv in enumerate(levels):
@@ -135,6 +138,11 @@ def level_structs(levels):
         s = arr[l]
         s.n_nodes, s.block, s.nnzb = lv.n, lv.block, len(parts[1])
         s.A_rowptr, s.A_col, s.A_val, s.dof_mask = (p.ctypes.data for p in parts)
+        if smoother_blocks is not None and smoother_blocks[l] is not None:
+            sb = np.ascontiguousarray(smoother_blocks[l], np.float64)
+            assert sb.size == lv.n * lv.block * lv.block
+            keep.append(sb)
+            s.smoother_blocks = sb.ctypes.data
         if l > 0 and lv.p_rowptr is not None:
             pp = [np.ascontiguousarray(lv.p_rowptr, np.int32), np.ascontiguousarray(lv.p_col, np.int32),
                   np.ascontiguousarray(lv.p_val, np.float64)]
@@ -164,9 +172,9 @@ def config_from(wl: W.Workload, precision="fp64", **over) -> Config:
 class Hierarchy:
     """A device-resident multigrid hierarchy (library handle)."""
 
-    def __init__(self, levels, cfg: Config, stream=None):
+    def __init__(self, levels, cfg: Config, stream=None, smoother_blocks=None):
         L = lib()
-        arr, keep = level_structs(levels)
+        arr, keep = level_structs(levels, smoother_blocks)
         h = C.c_void_p()
         self.cfg = cfg
         _check(L.mg_setup_hierarchy(arr, len(levels), C.byref(cfg), 0, _stream(stream), C.byref(h)))
@@ -206,9 +214,29 @@ class Hierarchy:
         n, b, _ = self.sizes[l]
         return n * b
 
+    @property
+    def cycle_fp64(self):
+        """True when the V-cycle (and the step-wise entry points) work on FP64 vectors."""
+        return self.cfg.precision == PREC["fp64"]
+
     # -- whole-path entry points
-    def vcycle(self, b, x, stream=None):
-        _check(lib().mg_vcycle(self.h, _ptr(b), _ptr(x), _stream(stream)))
+    def vcycle(self, b, x, x_is_zero=True, stream=None):
+        _check(lib().mg_vcycle(self.h, _ptr(b), _ptr(x), int(bool(x_is_zero)), _stream(stream)))
+
+    def outer_defect(self, b, x, r, norm, stream=None):
+        """r = b - A_L x and norm[0] = ||r|| in FP64 (device tensors)."""
+        _check(lib().mg_outer_defect(self.h, _ptr(b), _ptr(x), _ptr(r), _ptr(norm), _stream(stream)))
+
+    def export(self, l):
+        """Stored cycle operator of level l in BSR order: (values (nnzb, b, b) of the storage
+        dtype: float64, float32 or uint16 codes; row exponents (n * b,) int8 or None)."""
+        n, b, nnzb = self.sizes[l]
+        prec = self.cfg.precision
+        dt = {0: np.float64, 1: np.float32, 2: np.uint16, 3: np.uint16}[prec]
+        vals = np.zeros((nnzb, b, b), dt)
+        ex = np.zeros(n * b, np.int8) if prec >= 2 else None
+        _check(lib().mg_level_export(self.h, l, vals.ctypes.data, None if ex is None else ex.ctypes.data))
+        return vals, ex
 
     def solve(self, b, x, stream=None, fixed=None):
         st = Stats()

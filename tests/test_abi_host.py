@@ -64,12 +64,19 @@ def test_malformed_rejected(levels, breakage):
         k = lv.rowptr[i]
         lv.val[k, 0, 0] = 2.0
     elif breakage == "mask_col":
+        # a free row that references a constrained node with a nonzero entry: insert the
+        # block (i, j) in sorted position (the generator's pattern drops such columns)
         j = int(np.nonzero(lv.mask[:, 0])[0][0])
-        rows = np.repeat(np.arange(lv.n), np.diff(lv.rowptr))
-        ks = np.nonzero((lv.col == j) & (rows != j))[0]
-        if len(ks) == 0:
-            pytest.skip("no off-diagonal reference to a constrained node")
-        lv.val[ks[0], 0, 0] = 0.5
+        i = int(np.nonzero(lv.mask[:, 0] == 0)[0][0])
+        row = lv.col[lv.rowptr[i]:lv.rowptr[i + 1]]
+        assert j not in row
+        k = int(lv.rowptr[i] + np.searchsorted(row, j))
+        blk = np.zeros((1,) + lv.val.shape[1:])
+        blk[0, 0, 0] = 0.5
+        lv.col = np.insert(lv.col, k, j)
+        lv.val = np.insert(lv.val, k, blk, axis=0)
+        lv.rowptr = lv.rowptr.copy()
+        lv.rowptr[i + 1:] += 1
     elif breakage == "nan":
         lv.val[7, 0, 0] = np.nan
     elif breakage == "p_col":
@@ -78,6 +85,18 @@ def test_malformed_rejected(levels, breakage):
         lv.p_cols = co.n + 1
     assert mg.validate_level(lv, co) == -1
     assert mg.last_error()
+
+
+def test_smoother_blocks_validated(levels):
+    """Caller smoother blocks must be finite (host validation, no device)."""
+    lv = levels[-1]
+    S = np.ones((lv.n, 1, 1))
+    arr, keep = mg.level_structs([lv], [S])
+    assert mg.lib().mg_validate_level(arr, None) == 0
+    S[3] = np.inf
+    arr, keep = mg.level_structs([lv], [S])
+    assert mg.lib().mg_validate_level(arr, None) == -1
+    assert "smoother" in mg.last_error()
 
 
 @pytest.mark.parametrize("bad", ["nrhs3", "outer_ir", "coarse_smooth", "nrhs8_block3", "block_mismatch"])

@@ -413,3 +413,134 @@ def test_load_kinds_bitwise_equal(name, prec, monkeypatch):
         st = h.solve(dev(o.b), x)
         outs.append((host(x), st["iters"]))
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+
+
+@pytest.mark.parametrize("name", ["poisson33", "td_band", "elast17", "oseen17", "edge4"])
+def test_vcycle_from_initial_iterate(name):
+    """GMG(L, x, b) with a nonzero initial iterate (mg_vcycle, x_is_zero = 0) against the
+    oracle's recursion from the same x, for V(2,2) and for an odd sweep count V(1,2)."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h = _pair(name)
+    x0 = _rand(950, o.finest.ndof)
+    x0[o.finest.mask.ravel()] = 0.0
+    ref = mgo.gmg(o.L, x0.copy(), o.b)
+    x = dev(x0)
+    h.vcycle(dev(o.b), x, x_is_zero=False)
+    assert np.abs(host(x) - ref).max() <= 1e-12 * np.abs(ref).max()
+    h12 = mg.Hierarchy(p.levels, mg.config_from(wl, nu1=1, nu2=2))
+    mg12 = MG.Multigrid(o, nu1=1, nu2=2)
+    ref = mg12.gmg(o.L, x0.copy(), o.b)
+    x = dev(x0)
+    h12.vcycle(dev(o.b), x, x_is_zero=False)
+    assert np.abs(host(x) - ref).max() <= 1e-12 * np.abs(ref).max()
+    # from zero the two forms agree bitwise
+    xa = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+    xb = torch.zeros_like(xa)
+    h.vcycle(dev(o.b), xa)
+    h.vcycle(dev(o.b), xb, x_is_zero=False)
+    ref0 = mgo.vcycle(o.b)
+    assert np.abs(host(xb) - ref0).max() <= 1e-12 * np.abs(ref0).max()
+    assert np.abs(host(xa) - host(xb)).max() <= 1e-12 * np.abs(ref0).max()
+
+
+@pytest.mark.parametrize("name", ["td_band", "elast17", "oseen17"])
+def test_mixed_vcycle_from_initial_iterate(name):
+    """The mixed form's GMG(L, x, b) stays within FP32 accuracy of the FP64 recursion."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h = _pair(name)
+    hm = mg.Hierarchy(p.levels, mg.config_from(wl, precision="fp32"))
+    x0 = _rand(951, o.finest.ndof)
+    x0[o.finest.mask.ravel()] = 0.0
+    ref = mgo.gmg(o.L, x0.copy(), o.b)
+    x = dev(x0)
+    hm.vcycle(dev(o.b), x, x_is_zero=False)
+    assert np.linalg.norm(host(x) - ref) <= 1e-4 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name", ["td_band", "elast17", "oseen17"])
+def test_caller_smoother_blocks(name):
+    """mg_level_in.smoother_blocks: the oracle's block inverses reproduce the derived
+    smoother; a different fixed S (0.5 times them) is the one the sweeps then apply."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h = _pair(name)
+    S = [MG.smoother_blocks(lv) for lv in o.levels]
+    h1 = mg.Hierarchy(p.levels, mg.config_from(wl), smoother_blocks=S)
+    h2 = mg.Hierarchy(p.levels, mg.config_from(wl), smoother_blocks=[0.5 * s for s in S])
+    for l, lv in enumerate(o.levels):
+        x = _rand(960 + l, lv.ndof)
+        b = _rand(970 + l, lv.ndof)
+        ref = mgo.smooth(l, x, b)
+        scale = np.abs(ref).max() + np.abs(abs(lv.A) @ np.abs(x)).max()
+        xo = torch.zeros(lv.ndof, dtype=torch.float64, device="cuda")
+        h1.sweep(l, dev(b), dev(x), xo)
+        assert np.abs(host(xo) - ref).max() <= 1e-12 * scale
+        h2.sweep(l, dev(b), dev(x), xo)
+        ref2 = x + wl.omega * 0.5 * mgo.apply_S(l, b - lv.A @ x)
+        assert np.abs(host(xo) - ref2).max() <= 1e-12 * scale
+    # the V-cycle with the oracle's blocks is the default V-cycle
+    xa = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+    h1.vcycle(dev(o.b), xa)
+    ref = mgo.vcycle(o.b)
+    assert np.abs(host(xa) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", ["td_band", "elast17", "oseen17"])
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_outer_defect(name, prec):
+    """mg_outer_defect: r = b - A_L x and ||r|| in FP64 on the finest FP64 operator,
+    whatever the cycle precision."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h = _pair(name)
+    hh = h if prec == "fp64" else mg.Hierarchy(p.levels, mg.config_from(wl, precision=prec))
+    x = _rand(980, o.finest.ndof)
+    ref = o.b - o.finest.A @ x
+    r = torch.zeros(len(x), dtype=torch.float64, device="cuda")
+    nrm = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hh.outer_defect(dev(o.b), dev(x), r, nrm)
+    scale = np.abs(o.b).max() + np.abs(abs(o.finest.A) @ np.abs(x)).max()
+    assert np.abs(host(r) - ref).max() <= 1e-12 * scale
+    assert abs(float(host(nrm)[0]) - np.linalg.norm(ref)) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name", ["poisson33", "td_band", "elast17"])
+def test_coarse_smooth_mode(name):
+    """MG_COARSE_SMOOTH (the paper's GPU coarse variant: a few smoothing sweeps from 0 on
+    the coarse level): coarse step, V-cycle and a converged solve against the oracle."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, _ = _pair(name)
+    wl = wl.with_(coarse_mode=W.COARSE_SMOOTH, coarse_sweeps=7)
+    o = Hh.build(wl)
+    mgo = MG.Multigrid(o)
+    h = mg.Hierarchy(p.levels, mg.config_from(wl))
+    b0 = _rand(990, o.levels[0].ndof)
+    b0[o.levels[0].mask.ravel()] = 0.0
+    x0 = torch.zeros(len(b0), dtype=torch.float64, device="cuda")
+    h.coarse_solve(dev(b0), x0)
+    ref = mgo.coarse_solve(b0)
+    assert np.abs(host(x0) - ref).max() <= 1e-12 * np.abs(ref).max()
+    x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+    h.vcycle(dev(o.b), x)
+    ref = mgo.vcycle(o.b)
+    assert np.abs(host(x) - ref).max() <= 1e-12 * np.abs(ref).max()
+    x.zero_()
+    st = h.solve(dev(o.b), x)
+    xr, st_ref = mgo.solve(o.b)
+    assert st["converged"] == 1 and st_ref.converged and st["iters"] == st_ref.iters
+    assert np.linalg.norm(host(x) - xr) <= 1e-10 * np.linalg.norm(xr)
+
+
+def test_aliasing_rejected():
+    """Outputs that alias inputs are refused with MG_EINVAL before any device work."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h = _pair("td_band")
+    v = dev(o.b)
+    w = torch.zeros_like(v)
+    nrm = torch.zeros(1, dtype=torch.float64, device="cuda")
+    L = o.L
+    calls = [lambda: h.vcycle(v, v), lambda: h.vcycle(v, v, x_is_zero=False),
+             lambda: h.sweep(L, v, w, w), lambda: h.sweep(L, w, v, w), lambda: h.sweep0(L, v, v),
+             lambda: h.spmv(L, v, v), lambda: h.defect(L, v, w, w), lambda: h.outer_defect(v, w, w, nrm)]
+    for call in calls:
+        with pytest.raises(mg.MGError) as e:
+            call()
+        assert e.value.code == -1
