@@ -70,6 +70,11 @@ typedef struct {
   int32_t j[8];
   double fk[4][3], fc[4], fphi[4];
   int32_t fi[4];
+  int32_t no_supg;             /* 1: no streamline stabilisation in the TD operator */
+  double mass_coef;            /* c of a lumped mass term c M_l added to every level's
+                                  operator (eq. mass_lumping: m_i = int phi_i); 0 = none */
+  int32_t time_ops;            /* 1: also build the right-hand-side operators of a
+                                  time-stepping run on the finest level (mggen_time_ops) */
 } mggen_config;
 
 typedef struct {
@@ -102,6 +107,30 @@ const double* mggen_rhs(const mggen_problem* p);
 /* b = Z H^T (m (*) xi) for nodal noise xi (n_nodes * nrhs, node-major), m the lumped mass
  * (block must be 1); out: n_nodes * nrhs, node-major */
 int mggen_rhs_noise(const mggen_problem* p, const double* xi, int32_t nrhs, double* out);
+/* Operators of a backward-Euler run with the lumped mass (Algorithm "Nonstationary Linear
+ * Problem", Sec. 4; eq. mass_lumping), finest level, DoF = node * block + component:
+ *   R (n_dofs x (n_dofs + n_g)) = [Z H^T M_l | -Z H^T A_full E_g], so that the right-hand
+ *     side of a step is b = R [theta_old / dt + f ; g] (f nodal source values, g the
+ *     Dirichlet values of the step); A_full is the unconstrained operator with its mass
+ *     term, E_g injects the n_g Dirichlet DoFs g_idx;
+ *   H (n_dofs x n_dofs): theta = H x (hanging DoFs interpolated; identity rows else);
+ *   coords: n_nodes * dim node coordinates.
+ * Available when the problem was built with time_ops = 1; views stay valid until
+ * mggen_free(). */
+typedef struct {
+  int32_t n_dofs;
+  int32_t n_g;
+  int64_t r_nnz, h_nnz;
+  const int32_t* R_rowptr;
+  const int32_t* R_col;
+  const double* R_val;
+  const int32_t* H_rowptr;
+  const int32_t* H_col;
+  const double* H_val;
+  const int32_t* g_idx;
+  const double* coords;
+} mggen_time_view;
+int mggen_time_ops(const mggen_problem* p, mggen_time_view* out);
 void mggen_free(mggen_problem* p);
 const char* mggen_last_error(void);
 

@@ -17,6 +17,9 @@ Readings (the paper gives no formulas for these):
     left and tau_K (f, b.grad v)_K on the right, tau_K = h_K/(2|b|) (coth Pe - 1/Pe),
     Pe = |b| h_K / (2 eps), h_K = s |b| / max_k |b_k| (chord through the centre of a
     square of side s along b).
+  * Lumped mass term (time-dependent problems, eq. mass_lumping): c * M_l with
+    M_l = diag(m_i), m_i = sum_j (phi_j, phi_i) = int phi_i, added element by element as
+    c |K| / 2^dim on the diagonal of each cell's corners (before the constraints).
   * Flow step (4 components p, u, v, w): (1/dt)(u,v) + nu (grad u, grad v)
     + (beta.grad u, v) - (p, div v) + (div u, q) + sum_K delta_K (grad p, grad q)_K,
     delta_K = alpha0 / (nu / s^2 + |beta(x_K)| / s + 1/dt), beta at the 2-point
@@ -87,10 +90,11 @@ def langevin(pe):
 
 
 def supg_tau(wl, s):
-    """Stabilisation parameter tau_K for square cells of side s (see module docstring)."""
+    """Stabilisation parameter tau_K for square cells of side s (see module docstring);
+    zero when the workload switches the stabilisation off."""
     b = np.asarray(wl.bvec, dtype=np.float64)
     nb = math.sqrt(float(b @ b))
-    if nb == 0.0:
+    if nb == 0.0 or not wl.supg:
         return np.zeros_like(np.asarray(s, dtype=np.float64))
     hk = np.asarray(s, dtype=np.float64) * nb / float(np.max(np.abs(b)))
     pe = nb * hk / (2.0 * wl.eps)
@@ -202,6 +206,11 @@ def element_matrices(wl, s, x0):
             Ke[:, :, :, 1 + k, 1 + k] = mass / wl.dt + wl.nu * grad_grad + conv
     else:
         raise ValueError(wl.pde)
+    if wl.mass_coef != 0.0:
+        lumped = wl.mass_coef * jac / nb                # c |K| / 2^dim per corner
+        for a in range(nb):
+            for ci in range(b):
+                Ke[:, a, a, ci, ci] += lumped
     return Ke
 
 
@@ -260,6 +269,15 @@ def leaf_table(mesh):
     nodes = mesh.node_of_lin[lin]
     assert np.all(nodes >= 0)
     return size * f.hf, anc * f.hf, nodes
+
+
+def lumped_mass(mesh) -> np.ndarray:
+    """m_i = sum_j (phi_j, phi_i) = int phi_i per node (all nodes, hanging included): each
+    cell gives |K| / 2^dim to each of its corners (eq. mass_lumping)."""
+    s, x0, nodes = leaf_table(mesh)
+    dim = mesh.dim
+    return np.bincount(nodes.ravel(), weights=np.repeat(s ** dim / (1 << dim), nodes.shape[1]),
+                       minlength=mesh.n)
 
 
 def dof_mask(mesh, wl) -> np.ndarray:

@@ -352,7 +352,7 @@ double langevin(double pe) {
 double supg_tau(const mggen_config& c, double s) {
   const double bx = c.bvec[0], by = c.bvec[1];
   const double nb = std::sqrt(bx * bx + by * by);
-  if (nb == 0.0) return 0.0;
+  if (nb == 0.0 || c.no_supg) return 0.0;
   const double hk = s * nb / std::max(std::fabs(bx), std::fabs(by));
   const double pe = nb * hk / (2.0 * c.eps);
   return hk / (2.0 * nb) * langevin(pe);
@@ -410,8 +410,9 @@ Gauss gauss(int n) {
   return g;
 }
 
-// row `a` of the element matrix of a box (lower corner x0, side s): out[b][ci][cj]
-void element_row(const mggen_config& c, int a, double s, const double x0[3], double* out) {
+// row `a` of the element matrix of the PDE's bilinear form on a box (lower corner x0,
+// side s): out[b][ci][cj]
+void element_row_pde(const mggen_config& c, int a, double s, const double x0[3], double* out) {
   const int dim = c.dim, nb = 1 << dim, B = c.block;
   std::fill(out, out + nb * B * B, 0.0);
   if (c.pde == MGGEN_PDE_POISSON || c.pde == MGGEN_PDE_TD) {
@@ -486,6 +487,18 @@ void element_row(const mggen_config& c, int a, double s, const double x0[3], dou
     return;
   }
   throw Fail(MGGEN_EINVAL, "unknown pde");
+}
+
+// row `a` of the element matrix: the PDE's form plus, for time-dependent problems, the
+// lumped mass term c M_l (eq. mass_lumping: m_i = int phi_i, each cell giving |K| / 2^dim
+// to each corner), c = mass_coef
+void element_row(const mggen_config& c, int a, double s, const double x0[3], double* out) {
+  element_row_pde(c, a, s, x0, out);
+  if (c.mass_coef != 0.0) {
+    const int nb = 1 << c.dim, B = c.block;
+    const double vol = c.dim == 3 ? s * s * s : s * s;
+    for (int ci = 0; ci < B; ++ci) out[(a * B + ci) * B + ci] += c.mass_coef * vol / double(nb);
+  }
 }
 
 // load entries of corner `a` (3-point Gauss per direction): out[ci]
@@ -773,10 +786,124 @@ void prolongation(const Tree& tf, const MeshLevel& mf, const Tree& tc, const Mes
 
 }  // namespace
 
+// right-hand-side operators of a time-stepping run on the finest level
+struct TimeOps {
+  int32_t n_dofs = 0, n_g = 0;
+  std::vector<int32_t> rrow, rcol, hrow, hcol, gidx;
+  std::vector<double> rval, hval, coords;
+};
+
+namespace {
+
+// R = [Z H^T M_l | -Z H^T A_full E_g], H at DoF level, Dirichlet DoF list, coordinates
+void time_operators(const mggen_config& c, const Tree& t, const MeshLevel& m, const LevelOut& L,
+                    const std::vector<double>& lumped, TimeOps& T) {
+  const int dim = c.dim, nb = 1 << dim, B = c.block;
+  const int32_t n = m.n;
+  const int64_t N = int64_t(n) * B;
+  if (N >= (int64_t(1) << 31)) throw Fail(MGGEN_EINVAL, "too many DoFs for int32 indices");
+  T.n_dofs = int32_t(N);
+  // Dirichlet DoFs: listed components of nodes on the Dirichlet faces (hanging ones too)
+  std::vector<int32_t> gpos(size_t(N), -1);
+  for (int32_t i = 0; i < n; ++i) {
+    bool on = false;
+    for (int a = 0; a < dim; ++a) {
+      const int64_t top = t.nc[a] << t.D;
+      if ((c.dir_faces >> (2 * a) & 1) && m.lat[3 * i + a] == 0) on = true;
+      if ((c.dir_faces >> (2 * a + 1) & 1) && m.lat[3 * i + a] == top) on = true;
+    }
+    if (!on) continue;
+    for (int ci = 0; ci < B; ++ci)
+      if (c.dir_comps >> ci & 1) {
+        gpos[size_t(i) * B + ci] = int32_t(T.gidx.size());
+        T.gidx.push_back(i * B + ci);
+      }
+  }
+  T.n_g = int32_t(T.gidx.size());
+  std::vector<std::vector<std::pair<int32_t, double>>> rows;
+  rows.resize(size_t(N));
+  auto add = [&](int64_t r, int32_t col, double v) {
+    for (auto& e : rows[size_t(r)])
+      if (e.first == col) { e.second += v; return; }
+    rows[size_t(r)].push_back({col, v});
+  };
+  // Q = Z H^T M_l: node k's mass goes to k, or to the masters of a hanging k
+  for (int32_t k = 0; k < n; ++k) {
+    const Expand ek = expand(m, k);
+    for (int q = 0; q < ek.cnt; ++q)
+      for (int ci = 0; ci < B; ++ci) {
+        const int64_t r = int64_t(ek.node[q]) * B + ci;
+        if (!L.mask[size_t(r)]) add(r, int32_t(int64_t(k) * B + ci), ek.w[q] * lumped[k]);
+      }
+  }
+  // -G = -Z H^T A_full E_g: element couplings of free (expanded) rows with Dirichlet corners
+  const double hf = t.hf();
+  std::vector<double> krow(size_t(nb) * B * B);
+  for (size_t e = 0; e < m.leaves.size(); ++e) {
+    bool touches = false;
+    for (int b = 0; b < nb && !touches; ++b)
+      for (int cj = 0; cj < B; ++cj) touches |= gpos[size_t(m.corner[e * nb + b]) * B + cj] >= 0;
+    if (!touches) continue;
+    const Leaf& Lf = m.leaves[e];
+    const double s = hf * double(Lf.s);
+    const double x0[3] = {double(Lf.a[0]) * hf, double(Lf.a[1]) * hf, double(Lf.a[2]) * hf};
+    for (int a = 0; a < nb; ++a) {
+      const Expand ea = expand(m, m.corner[e * nb + a]);
+      element_row(c, a, s, x0, krow.data());
+      for (int b = 0; b < nb; ++b) {
+        const int32_t jb = m.corner[e * nb + b];
+        for (int cj = 0; cj < B; ++cj) {
+          const int32_t g = gpos[size_t(jb) * B + cj];
+          if (g < 0) continue;
+          for (int q = 0; q < ea.cnt; ++q)
+            for (int ci = 0; ci < B; ++ci) {
+              const int64_t r = int64_t(ea.node[q]) * B + ci;
+              if (L.mask[size_t(r)]) continue;
+              const double v = ea.w[q] * krow[(size_t(b) * B + ci) * B + cj];
+              if (v != 0.0) add(r, int32_t(N + g), -v);
+            }
+        }
+      }
+    }
+  }
+  T.rrow.assign(size_t(N) + 1, 0);
+  for (int64_t r = 0; r < N; ++r) {
+    std::sort(rows[size_t(r)].begin(), rows[size_t(r)].end());
+    T.rrow[size_t(r) + 1] = T.rrow[size_t(r)] + int32_t(rows[size_t(r)].size());
+  }
+  for (auto& rw : rows)
+    for (auto& e : rw) {
+      T.rcol.push_back(e.first);
+      T.rval.push_back(e.second);
+    }
+  // H at DoF level
+  T.hrow.assign(size_t(N) + 1, 0);
+  for (int32_t k = 0; k < n; ++k) {
+    Expand ek = expand(m, k);
+    std::vector<std::pair<int32_t, double>> ent;
+    for (int q = 0; q < ek.cnt; ++q) ent.push_back({ek.node[q], ek.w[q]});
+    std::sort(ent.begin(), ent.end());
+    for (int ci = 0; ci < B; ++ci) {
+      for (auto& pr : ent) {
+        T.hcol.push_back(pr.first * B + ci);
+        T.hval.push_back(pr.second);
+      }
+      T.hrow[size_t(k) * B + ci + 1] = int32_t(T.hcol.size());
+    }
+  }
+  T.coords.resize(size_t(n) * dim);
+  for (int32_t i = 0; i < n; ++i)
+    for (int a = 0; a < dim; ++a) T.coords[size_t(i) * dim + a] = double(m.lat[3 * i + a]) * hf;
+}
+
+}  // namespace
+
 struct mggen_problem {
   mggen_config cfg;
   std::vector<LevelOut> levels;
   std::vector<double> rhs;
+  TimeOps time;
+  bool has_time = false;
   // finest mesh data kept for the noise right-hand side
   std::vector<double> lumped;               // lumped mass per finest node
   std::vector<int32_t> hang_node, hang_master;
@@ -825,6 +952,10 @@ int mggen_build(const mggen_config* cfg, mggen_problem** out) {
       const double s = hf * double(mf.leaves[e].s);
       const double vol = cfg->dim == 3 ? s * s * s : s * s;
       for (int a = 0; a < nb; ++a) P->lumped[mf.corner[e * nb + a]] += vol / double(nb);
+    }
+    if (cfg->time_ops) {
+      time_operators(P->cfg, trees[nl - 1], mf, P->levels[nl - 1], P->lumped, P->time);
+      P->has_time = true;
     }
     P->mask = P->levels[nl - 1].mask;
     P->hang_node = P->levels[nl - 1].hang_node;
@@ -900,6 +1031,28 @@ int mggen_rhs_noise(const mggen_problem* p, const double* xi, int32_t nrhs, doub
   for (int32_t i = 0; i < n; ++i)
     if (p->mask[i])
       for (int32_t r = 0; r < nrhs; ++r) out[size_t(i) * nrhs + r] = 0.0;
+  return MGGEN_OK;
+}
+
+int mggen_time_ops(const mggen_problem* p, mggen_time_view* o) {
+  if (!p || !o || !p->has_time) {
+    g_err = "no time-stepping operators (build with time_ops = 1)";
+    return MGGEN_EINVAL;
+  }
+  const TimeOps& T = p->time;
+  std::memset(o, 0, sizeof(*o));
+  o->n_dofs = T.n_dofs;
+  o->n_g = T.n_g;
+  o->r_nnz = int64_t(T.rcol.size());
+  o->h_nnz = int64_t(T.hcol.size());
+  o->R_rowptr = T.rrow.data();
+  o->R_col = T.rcol.data();
+  o->R_val = T.rval.data();
+  o->H_rowptr = T.hrow.data();
+  o->H_col = T.hcol.data();
+  o->H_val = T.hval.data();
+  o->g_idx = T.gidx.data();
+  o->coords = T.coords.data();
   return MGGEN_OK;
 }
 

@@ -33,7 +33,16 @@ class Config(C.Structure):
                 ("kappa", (C.c_double * 3) * 8), ("a", C.c_double * 8), ("phi", C.c_double * 8),
                 ("scale", C.c_double), ("j", C.c_int32 * 8),
                 ("fk", (C.c_double * 3) * 4), ("fc", C.c_double * 4), ("fphi", C.c_double * 4),
-                ("fi", C.c_int32 * 4)]
+                ("fi", C.c_int32 * 4), ("no_supg", C.c_int32), ("mass_coef", C.c_double),
+                ("time_ops", C.c_int32)]
+
+
+class TimeView(C.Structure):
+    _fields_ = [("n_dofs", C.c_int32), ("n_g", C.c_int32), ("r_nnz", C.c_int64), ("h_nnz", C.c_int64),
+                ("R_rowptr", C.POINTER(C.c_int32)), ("R_col", C.POINTER(C.c_int32)),
+                ("R_val", C.POINTER(C.c_double)), ("H_rowptr", C.POINTER(C.c_int32)),
+                ("H_col", C.POINTER(C.c_int32)), ("H_val", C.POINTER(C.c_double)),
+                ("g_idx", C.POINTER(C.c_int32)), ("coords", C.POINTER(C.c_double))]
 
 
 class LevelView(C.Structure):
@@ -61,6 +70,8 @@ def lib():
         L.mggen_rhs.restype = C.POINTER(C.c_double)
         L.mggen_rhs_noise.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double)]
         L.mggen_rhs_noise.restype = C.c_int
+        L.mggen_time_ops.argtypes = [C.c_void_p, C.POINTER(TimeView)]
+        L.mggen_time_ops.restype = C.c_int
         L.mggen_free.argtypes = [C.c_void_p]
         L.mggen_free.restype = None
         L.mggen_last_error.argtypes = []
@@ -99,11 +110,30 @@ class GenLevel:
 
 
 @dataclasses.dataclass
+class TimeOps:
+    """Right-hand-side operators of a time-stepping run on the finest level (CSR)."""
+    n_dofs: int
+    R_rowptr: np.ndarray         # n_dofs + 1; R is n_dofs x (n_dofs + n_g)
+    R_col: np.ndarray
+    R_val: np.ndarray
+    H_rowptr: np.ndarray         # n_dofs + 1; H is n_dofs x n_dofs
+    H_col: np.ndarray
+    H_val: np.ndarray
+    g_idx: np.ndarray            # n_g Dirichlet DoFs
+    coords: np.ndarray           # (n_nodes, dim)
+
+    @property
+    def n_g(self):
+        return len(self.g_idx)
+
+
+@dataclasses.dataclass
 class Problem:
     wl: W.Workload
     levels: List[GenLevel]
     b: Optional[np.ndarray]      # finest rhs (n*b,), None for noise problems
     _handle: Optional[int] = None
+    time: Optional[TimeOps] = None
 
     @property
     def finest(self):
@@ -139,6 +169,8 @@ def config_of(wl: W.Workload):
         cfg.bvec[a] = wl.bvec[a]
     cfg.lam, cfg.mu, cfg.nu, cfg.dt, cfg.pspg_alpha = wl.lam, wl.mu, wl.nu, wl.dt, wl.pspg_alpha
     cfg.dir_faces, cfg.dir_comps, cfg.rhs = wl.dir_faces, wl.dir_comps, wl.rhs
+    cfg.no_supg = 0 if wl.supg else 1
+    cfg.mass_coef = wl.mass_coef
     for a in range(len(wl.rhs_const)):
         cfg.rhs_const[a] = wl.rhs_const[a]
     if wl.pde == W.PDE_OSEEN or wl.rhs == W.RHS_FIELD:
@@ -155,9 +187,10 @@ def config_of(wl: W.Workload):
     return cfg, rounds
 
 
-def build(wl: W.Workload, nrhs: int = 1) -> Problem:
+def build(wl: W.Workload, nrhs: int = 1, time_ops: bool = False) -> Problem:
     L = lib()
     cfg, keep = config_of(wl)
+    cfg.time_ops = 1 if time_ops else 0
     h = C.c_void_p()
     rc = L.mggen_build(C.byref(cfg), C.byref(h))
     if rc != 0:
@@ -200,6 +233,18 @@ def build(wl: W.Workload, nrhs: int = 1) -> Problem:
             b = out[:, 0].copy() if nrhs == 1 else out
         else:
             b = _arr(L.mggen_rhs(h), top.n * top.block, np.float64)
-        return Problem(wl, levels, b)
+        tops = None
+        if time_ops:
+            v = TimeView()
+            if L.mggen_time_ops(h, C.byref(v)) != 0:
+                raise RuntimeError(L.mggen_last_error().decode())
+            N = v.n_dofs
+            tops = TimeOps(n_dofs=N, R_rowptr=_arr(v.R_rowptr, N + 1, np.int32),
+                           R_col=_arr(v.R_col, v.r_nnz, np.int32), R_val=_arr(v.R_val, v.r_nnz, np.float64),
+                           H_rowptr=_arr(v.H_rowptr, N + 1, np.int32),
+                           H_col=_arr(v.H_col, v.h_nnz, np.int32), H_val=_arr(v.H_val, v.h_nnz, np.float64),
+                           g_idx=_arr(v.g_idx, v.n_g, np.int32),
+                           coords=_arr(v.coords, top.n * wl.dim, np.float64).reshape(top.n, wl.dim))
+        return Problem(wl, levels, b, time=tops)
     finally:
         L.mggen_free(h)

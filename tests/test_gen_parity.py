@@ -12,7 +12,12 @@ from paper_2405_05047_amd import gen
 
 CASES = [W.c1_poisson(4), W.c2_td(band_rounds=3, uniform_rounds=1), W.c2_td(band_rounds=4),
          W.c3_elasticity(3), W.c3_adaptive("edge", 4), W.c3_adaptive("vertex", 4),
-         W.c3_adaptive("face", 3), W.c4_oseen(3), W.c4_oseen(2, tall=True)] + W.batch_problems(3, max_levels=6)
+         W.c3_adaptive("face", 3), W.c4_oseen(3), W.c4_oseen(2, tall=True), W.td_time(5)] + W.batch_problems(3, max_levels=6)
+
+# time-dependent problems: a uniform mesh, and an adaptive one with hanging nodes (band
+# refinement reaching close to the Dirichlet boundary)
+TIME_CASES = [W.td_time(5), W.td_time(4).with_(coarse=(8, 8), h0=0.125, rounds=(
+    ("uniform",), ("band", 0.5, 0.5, 0.3, 0.05), ("band", 0.5, 0.5, 0.45, 0.06)))]
 
 
 @pytest.mark.parametrize("wl", CASES, ids=[w.name for w in CASES])
@@ -39,6 +44,32 @@ def test_generator_matches_oracle(wl):
             assert np.array_equal(g.p_col, o.Pt.indices)
             assert np.array_equal(g.p_val, o.Pt.data)            # dyadic: bit-exact
     assert np.abs(p.b - h.b).max() <= 1e-14 * max(np.abs(h.b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("wl", TIME_CASES, ids=["uniform", "adaptive"])
+def test_time_operators_match_oracle(wl):
+    """R = [Z H^T M_l | -Z H^T A_full E_g], H and the Dirichlet DoF list of a
+    time-stepping run: patterns and the dyadic / lumped-mass entries bit-exact, the
+    lifting entries to rounding; the operators with their lumped mass term likewise."""
+    from oracle import timestep as TS
+    p = gen.build(wl, time_ops=True)
+    h = Hh.build(wl)
+    ops = TS.operators(h)
+    t = p.time
+    assert np.array_equal(t.g_idx, ops.g_idx)
+    assert np.array_equal(t.R_rowptr, ops.R.indptr) and np.array_equal(t.R_col, ops.R.indices)
+    scale = np.abs(ops.R.data).max()
+    assert np.abs(t.R_val - ops.R.data).max() <= 1e-14 * scale
+    H = ops.H.tocsr()
+    H.sort_indices()
+    assert np.array_equal(t.H_rowptr, H.indptr) and np.array_equal(t.H_col, H.indices)
+    assert np.array_equal(t.H_val, H.data)
+    assert np.array_equal(t.coords, ops.coords)
+    if wl.rounds[-1][0] == "band":
+        assert h.finest.mesh.is_hanging.any()
+    for g, o in zip(p.levels, h.levels):
+        assert np.array_equal(g.col, o.col)
+        assert np.abs(g.val - o.val).max() <= 1e-14 * np.abs(o.val).max()
 
 
 def test_noise_rhs_multi():

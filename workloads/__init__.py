@@ -54,6 +54,9 @@ class Workload:
     nu: float = 0.0                  # viscosity (Oseen)
     dt: float = 1.0                  # time step (Oseen mass term 1/dt)
     pspg_alpha: float = 1.0          # pressure-stabilisation constant (Oseen)
+    supg: bool = True                # streamline stabilisation of the TD operator
+    mass_coef: float = 0.0           # coefficient c of a lumped mass term c * M_l in the operator
+    t_end: float = 0.0               # time-dependent problems: end of the interval (0, t_end]
     # Dirichlet part: bitmask of faces (bit 2a = face x_a = 0, bit 2a+1 = face x_a = max)
     # and bitmask of constrained components on those faces
     dir_faces: int = 0
@@ -137,6 +140,44 @@ def elasticity_mms(rounds: int = 3) -> Workload:
 
 # direction of the manufactured elasticity displacement
 ELAST_MMS_DIR = (1.0, -0.5, 0.75)
+
+
+def td_time(n: int = 10, dt: float = 0.02, t_end: float = 2.0, coarse_level: int = 0) -> Workload:
+    """The nonstationary transport-diffusion problem of Sec. 5.1: unit square, uniform mesh
+    of width h = 2^-n ((2^n + 1)^2 nodes; 2x2 coarse cells and n - 1 uniform rounds),
+    diffusion 0.01, convection b = (0, -1), backward Euler with step dt on (0, t_end]
+    (100 steps by default), Dirichlet data of the exact solution td_exact on all sides.
+    The operator of every level is M_l / dt + 0.01 K + C (lumped mass, Galerkin
+    convection: the cell Peclet number |b| h / (2 * 0.01) is below 0.4 from n = 7 on)."""
+    return Workload(name=f"tdtime_n{n}", dim=2, coarse=(2, 2), h0=0.5,
+                    rounds=(("uniform",),) * (n - 1), pde=PDE_TD, block=1, eps=0.01,
+                    bvec=(0.0, -1.0), supg=False, mass_coef=1.0 / dt, dt=dt, t_end=t_end,
+                    dir_faces=ALL_FACES_2D, dir_comps=1, rhs=RHS_NONE,
+                    omega=0.8, nu1=2, nu2=2, outer=OUTER_FGMRES, gmres_m=10, rtol=1e-8,
+                    coarse_level=coarse_level)
+
+
+def td_exact(t, x, y):
+    """Exact solution of the Sec. 5.1 problem:
+    theta = exp(-(m(t, x)^2 + m(t, y)^2) / 4), m(t, z) = 1/2 + cos(pi t / 2) / 4 - z."""
+    c = 0.5 + 0.25 * np.cos(0.5 * np.pi * t)
+    mx, my = c - x, c - y
+    return np.exp(-0.25 * (mx * mx + my * my))
+
+
+def td_source(t, x, y, diff=0.01, bvec=(0.0, -1.0)):
+    """f = d_t theta - diff * lap theta + b . grad theta for theta = td_exact.
+    With m_x = c - x, m_y = c - y, c(t) = 1/2 + cos(pi t / 2) / 4, theta = exp(-(m_x^2 +
+    m_y^2) / 4): d_t theta = -theta (m_x + m_y) c' / 2 with c' = -pi sin(pi t / 2) / 8;
+    d_x theta = theta m_x / 2, d_y theta = theta m_y / 2;
+    lap theta = theta ((m_x^2 + m_y^2) / 4 - 1)."""
+    c = 0.5 + 0.25 * np.cos(0.5 * np.pi * t)
+    dc = -0.125 * np.pi * np.sin(0.5 * np.pi * t)
+    mx, my = c - x, c - y
+    th = np.exp(-0.25 * (mx * mx + my * my))
+    dt_th = -0.5 * th * (mx + my) * dc
+    lap = th * (0.25 * (mx * mx + my * my) - 1.0)
+    return dt_th - diff * lap + bvec[0] * 0.5 * th * mx + bvec[1] * 0.5 * th * my
 
 
 def c3_adaptive(kind: str, level: int) -> Workload:
