@@ -212,6 +212,43 @@ int mg_batch_offsets(const mg_batch* h, int64_t* offsets);
  * instance converged, else MG_ENOCONV / MG_ENUMERIC (stats still filled). */
 int mg_solve_batch(mg_batch* h, const double* b, double* x, mg_solve_stats* stats, void* stream);
 void mg_destroy_batch(mg_batch* h);
+/* ---- time stepping: Algorithm "Nonstationary Linear Problem" (Sec. 4) -------------
+ * The operators of a handle are reused for every step; each step forms its right-hand
+ * side on the device, solves with mg_solve from the previous solution, and maps the
+ * solution back to nodal values.  For backward Euler with the lumped mass of eq.
+ * mass_lumping (m_i = integral of phi_i) on the finest level,
+ *   b_n = R [theta_{n-1} / dt + f_n ; g_n],  R = [Z H^T M_l | -Z H^T A_full E_g],
+ *   A_L x_n = b_n (the handle's operator, which must hold the M_l / dt term),
+ *   theta_n = H x_n, and theta_n = g_n on the Dirichlet DoFs,
+ * with f_n the nodal source values, g_n the Dirichlet values of step n, H the
+ * hanging-node interpolation, Z the mask of constrained DoFs, A_full the unconstrained
+ * operator (mass term included) and E_g the injection of the Dirichlet DoFs.
+ * mg_time_setup: n = n_L * b rows; R is scalar CSR with n rows over n + n_g columns
+ * (columns < n address theta / dt + f, column n + k the k-th Dirichlet value), H is
+ * scalar CSR n x n, g_idx the n_g Dirichlet DoFs (distinct, ascending not required).
+ * Host arrays, deep-copied; the handle must outlive the time object and is used
+ * by it (do not run other work on the handle concurrently).  MG_EINVAL for malformed
+ * CSR, out-of-range indices, duplicate Dirichlet DoFs or dt <= 0. */
+typedef struct mg_time mg_time;
+int mg_time_setup(mg_handle* h, int32_t n_g, const int32_t* R_rowptr, const int32_t* R_col,
+                  const double* R_val, const int32_t* H_rowptr, const int32_t* H_col,
+                  const double* H_val, const int32_t* g_idx, double dt, void* stream, mg_time** out);
+/* b = R [theta / dt + f ; g] (device FP64: theta, f, b of n entries, g of n_g; b must not
+ * alias the inputs). */
+int mg_time_rhs(mg_time* t, const double* theta, const double* f, const double* g, double* b, void* stream);
+/* theta = H x, then theta[g_idx[k]] = g[k] (device FP64; theta must not alias x or g). */
+int mg_time_theta(mg_time* t, const double* x, const double* g, double* theta, void* stream);
+/* `steps` backward-Euler steps: F holds f_1 .. f_steps (steps * n, device), G holds
+ * g_1 .. g_steps (steps * n_g, device); theta (n, device) is theta_0 on entry and
+ * theta_steps on exit; x (n, device) is the initial guess of the first solve on entry
+ * (each later solve starts from the previous solution) and x_steps on exit.  history:
+ * NULL or steps * n device doubles receiving theta_1 .. theta_steps.  stats: NULL or
+ * `steps` entries.  Stops at the first step whose solve fails (its code is returned,
+ * the stats of that step are filled). */
+int mg_time_run(mg_time* t, int32_t steps, double* theta, const double* F, const double* G, double* x,
+                double* history, mg_solve_stats* stats, void* stream);
+void mg_time_destroy(mg_time* t);
+
 const char* mg_status_string(int status);
 const char* mg_last_error(void);
 

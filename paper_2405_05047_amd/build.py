@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_GEN = os.path.join(HERE, "libmggen.so")
 LIB_MG = os.path.join(HERE, "libmgq1.so")
 
-HIP_SOURCES = ["mgq1_kernels.hip", "mgq1_batch.hip", "mgq1_runtime.hip"]
+HIP_SOURCES = ["mgq1_kernels.hip", "mgq1_batch.hip", "mgq1_runtime.hip", "mgq1_time.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

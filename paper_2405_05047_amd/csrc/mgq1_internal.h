@@ -157,6 +157,17 @@ hipError_t launch_backsolve(int k, int m, const double* H, const double* g, doub
 // g = (beta, 0, ..., 0), beta read from the device
 hipError_t launch_init_g(int m, double* g, const double* beta, hipStream_t s);
 
+// ------------------------------------------------------------------ time stepping
+// b = R [theta / dt + f ; g] (R: n rows of a scalar CSR over n + n_g columns; columns
+// below n address theta / dt + f, the others g)
+hipError_t launch_time_rhs(int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                           const double* theta, const double* f, const double* g, double dt, double* b,
+                           hipStream_t s);
+// theta = H x (scalar CSR, n x n), then theta_i = g[gpos[i]] where gpos[i] >= 0
+hipError_t launch_time_theta(int32_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                             const int32_t* gpos, const double* x, const double* g, double* theta,
+                             hipStream_t s);
+
 // ------------------------------------------------------------------ batched form
 // Many independent problems (same block size) with NR right-hand sides each.  Vectors
 // of one problem are stored [node][component][rhs]; the problems' vectors are

@@ -1875,6 +1875,72 @@ int solve_batch_impl(mg_batch* h, const double* b, double* x, mg_solve_stats* st
   return MG_OK;
 }
 
+// ---------------------------------------------------------------- time stepping
+// Right-hand-side operator R, interpolation H and Dirichlet positions of a
+// backward-Euler run (Algorithm "Nonstationary Linear Problem"), on the device.
+struct TimeDev : DevOwner {
+  mg_handle* h = nullptr;
+  int32_t n = 0, n_g = 0;
+  double dt = 1.0;
+  const int32_t *rrow = nullptr, *rcol = nullptr, *hrow = nullptr, *hcol = nullptr, *gpos = nullptr;
+  const double *rval = nullptr, *hval = nullptr;
+  double* b = nullptr;   // right-hand side of the current step
+};
+
+// CSR with `rows` rows over `cols` columns: monotone row pointers from 0, indices in range
+int check_csr(const int32_t* rowptr, const int32_t* col, const double* val, int32_t rows, int64_t cols,
+              const char* what) {
+  if (!rowptr || (rowptr[rows] > 0 && (!col || !val))) return fail(MG_EINVAL, std::string(what) + ": null array");
+  if (rowptr[0] != 0) return fail(MG_EINVAL, std::string(what) + ": row pointers must start at 0");
+  for (int32_t i = 0; i < rows; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return fail(MG_EINVAL, std::string(what) + ": decreasing row pointers");
+  for (int32_t k = 0; k < rowptr[rows]; ++k) {
+    if (col[k] < 0 || col[k] >= cols) return fail(MG_EINVAL, std::string(what) + ": column out of range");
+    if (!std::isfinite(val[k])) return fail(MG_EINVAL, std::string(what) + ": non-finite value");
+  }
+  return MG_OK;
+}
+
+int time_setup(TimeDev* t, const int32_t* R_rowptr, const int32_t* R_col, const double* R_val,
+               const int32_t* H_rowptr, const int32_t* H_col, const double* H_val, const int32_t* g_idx,
+               hipStream_t s) {
+  const int32_t n = t->n, ng = t->n_g;
+  int rc;
+  if ((rc = check_csr(R_rowptr, R_col, R_val, n, int64_t(n) + ng, "R"))) return rc;
+  if ((rc = check_csr(H_rowptr, H_col, H_val, n, n, "H"))) return rc;
+  std::vector<int32_t> gpos(size_t(n), -1);
+  for (int32_t k = 0; k < ng; ++k) {
+    const int32_t d = g_idx[k];
+    if (d < 0 || d >= n) return fail(MG_EINVAL, "Dirichlet DoF out of range");
+    if (gpos[size_t(d)] >= 0) return fail(MG_EINVAL, "duplicate Dirichlet DoF");
+    gpos[size_t(d)] = k;
+  }
+  const size_t rnnz = size_t(R_rowptr[n]), hnnz = size_t(H_rowptr[n]);
+  std::vector<int32_t> rr(R_rowptr, R_rowptr + n + 1), rc_(R_col, R_col + rnnz);
+  std::vector<double> rv(R_val, R_val + rnnz);
+  std::vector<int32_t> hr(H_rowptr, H_rowptr + n + 1), hc(H_col, H_col + hnnz);
+  std::vector<double> hv(H_val, H_val + hnnz);
+  int32_t *p32;
+  double* p64;
+  if ((rc = upload(t, &p32, rr, s))) return rc;
+  t->rrow = p32;
+  if ((rc = upload(t, &p32, rc_, s))) return rc;
+  t->rcol = p32;
+  if ((rc = upload(t, &p64, rv, s))) return rc;
+  t->rval = p64;
+  if ((rc = upload(t, &p32, hr, s))) return rc;
+  t->hrow = p32;
+  if ((rc = upload(t, &p32, hc, s))) return rc;
+  t->hcol = p32;
+  if ((rc = upload(t, &p64, hv, s))) return rc;
+  t->hval = p64;
+  if ((rc = upload(t, &p32, gpos, s))) return rc;
+  t->gpos = p32;
+  if ((rc = dalloc(t, &t->b, size_t(n)))) return rc;
+  MG_HIP(hipStreamSynchronize(s));   // the host vectors above are freed on return
+  return MG_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- C ABI
@@ -2166,5 +2232,71 @@ int mg_solve_batch(mg_batch* h, const double* b, double* x, mg_solve_stats* stat
 
 void mg_destroy_batch(mg_batch* h) { delete h; }
 
+
+struct mg_time : TimeDev {};
+
+int mg_time_setup(mg_handle* h, int32_t n_g, const int32_t* R_rowptr, const int32_t* R_col, const double* R_val,
+                  const int32_t* H_rowptr, const int32_t* H_col, const double* H_val, const int32_t* g_idx,
+                  double dt, void* stream, mg_time** out) {
+  if (!h || !out || (n_g > 0 && !g_idx) || n_g < 0) return fail(MG_EINVAL, "null argument or negative n_g");
+  *out = nullptr;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(MG_EINVAL, "dt must be positive and finite");
+  const int64_t N = h->lv[h->L].N;
+  if (N + n_g > INT32_MAX) return fail(MG_EUNSUPPORTED, "more than 2^31 - 1 columns in R");
+  mg_time* t = new (std::nothrow) mg_time();
+  if (!t) return fail(MG_ENOMEM, "host allocation failed");
+  t->h = h;
+  t->n = int32_t(N);
+  t->n_g = n_g;
+  t->dt = dt;
+  int rc;
+  try {
+    rc = time_setup(t, R_rowptr, R_col, R_val, H_rowptr, H_col, H_val, g_idx, static_cast<hipStream_t>(stream));
+  } catch (const std::bad_alloc&) {
+    rc = fail(MG_ENOMEM, "host allocation failed");
+  }
+  if (rc) {
+    delete t;
+    return rc;
+  }
+  *out = t;
+  return MG_OK;
+}
+
+int mg_time_rhs(mg_time* t, const double* theta, const double* f, const double* g, double* b, void* stream) {
+  if (!t || !theta || !f || !b || (t->n_g > 0 && !g)) return fail(MG_EINVAL, "null argument");
+  if (b == theta || b == f || b == g) return fail(MG_EINVAL, "b must not alias the inputs");
+  MG_HIP(launch_time_rhs(t->n, t->rrow, t->rcol, t->rval, theta, f, g, t->dt, b, static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
+int mg_time_theta(mg_time* t, const double* x, const double* g, double* theta, void* stream) {
+  if (!t || !x || !theta || (t->n_g > 0 && !g)) return fail(MG_EINVAL, "null argument");
+  if (theta == x || theta == g) return fail(MG_EINVAL, "theta must not alias the inputs");
+  MG_HIP(launch_time_theta(t->n, t->hrow, t->hcol, t->hval, t->gpos, x, g, theta, static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
+int mg_time_run(mg_time* t, int32_t steps, double* theta, const double* F, const double* G, double* x,
+                double* history, mg_solve_stats* stats, void* stream) {
+  if (!t || !theta || !x || steps < 0 || (steps > 0 && !F) || (steps > 0 && t->n_g > 0 && !G))
+    return fail(MG_EINVAL, "null argument or negative step count");
+  if (theta == x) return fail(MG_EINVAL, "theta must not alias x");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = t->n, ng = t->n_g;
+  for (int32_t k = 0; k < steps; ++k) {
+    const double* f = F + k * n;
+    const double* g = ng > 0 ? G + k * ng : nullptr;
+    MG_HIP(launch_time_rhs(t->n, t->rrow, t->rcol, t->rval, theta, f, g, t->dt, t->b, s));
+    int rc = solve_impl(t->h, t->b, x, stats ? stats + k : nullptr, s, 0);
+    if (rc) return rc;
+    MG_HIP(launch_time_theta(t->n, t->hrow, t->hcol, t->hval, t->gpos, x, g, theta, s));
+    if (history)
+      MG_HIP(hipMemcpyAsync(history + k * n, theta, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  return MG_OK;
+}
+
+void mg_time_destroy(mg_time* t) { delete t; }
 
 }  // extern "C"

@@ -50,7 +50,8 @@ SYMBOLS = ["mg_setup_hierarchy", "mg_vcycle", "mg_solve", "mg_solve_fixed", "mg_
            "mg_level_prolong", "mg_coarse_solve", "mg_level_info", "mg_num_levels",
            "mg_validate_level", "mg_destroy", "mg_status_string", "mg_last_error",
            "mg_setup_batch", "mg_batch_offsets", "mg_solve_batch", "mg_destroy_batch",
-           "mg_level_tuning", "mg_outer_defect", "mg_level_export"]
+           "mg_level_tuning", "mg_outer_defect", "mg_level_export", "mg_time_setup", "mg_time_rhs",
+           "mg_time_theta", "mg_time_run", "mg_time_destroy"]
 
 
 def lib():
@@ -89,9 +90,15 @@ def lib():
         L.mg_solve_batch.argtypes = [vp, vp, vp, C.POINTER(Stats), vp]
         L.mg_destroy_batch.argtypes = [vp]
         L.mg_destroy_batch.restype = None
+        L.mg_time_setup.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, C.c_double, vp, C.POINTER(vp)]
+        L.mg_time_rhs.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.mg_time_theta.argtypes = [vp, vp, vp, vp, vp]
+        L.mg_time_run.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.mg_time_destroy.argtypes = [vp]
+        L.mg_time_destroy.restype = None
         for name in SYMBOLS:
             if name not in ("mg_destroy", "mg_status_string", "mg_last_error", "mg_num_levels",
-                            "mg_destroy_batch"):
+                            "mg_destroy_batch", "mg_time_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -317,6 +324,50 @@ class Batch:
         if rc not in (0, -5):
             _check(rc)
         return rc, [st[i].as_dict() for i in range(n)]
+
+
+class TimeStepper:
+    """Backward-Euler time stepping on a hierarchy whose operator holds the M_l / dt term
+    (library object mg_time): every step forms b = R [theta / dt + f ; g] on the device,
+    solves with the hierarchy from the previous solution and sets theta = H x (Dirichlet
+    values on the Dirichlet DoFs).  `ops` carries R, H and g_idx as host CSR arrays."""
+
+    def __init__(self, hier: Hierarchy, ops, dt: float, stream=None):
+        L = lib()
+        a = [np.ascontiguousarray(ops.R_rowptr, np.int32), np.ascontiguousarray(ops.R_col, np.int32),
+             np.ascontiguousarray(ops.R_val, np.float64), np.ascontiguousarray(ops.H_rowptr, np.int32),
+             np.ascontiguousarray(ops.H_col, np.int32), np.ascontiguousarray(ops.H_val, np.float64),
+             np.ascontiguousarray(ops.g_idx, np.int32)]
+        t = C.c_void_p()
+        _check(L.mg_time_setup(hier.h, len(a[6]), *(_ptr(v) for v in a), float(dt), _stream(stream),
+                               C.byref(t)))
+        self.t, self.hier, self.n_g = t, hier, len(a[6])
+
+    def close(self):
+        if getattr(self, "t", None):
+            lib().mg_time_destroy(self.t)
+            self.t = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rhs(self, theta, f, g, b, stream=None):
+        _check(lib().mg_time_rhs(self.t, _ptr(theta), _ptr(f), _ptr(g), _ptr(b), _stream(stream)))
+
+    def theta(self, x, g, theta, stream=None):
+        _check(lib().mg_time_theta(self.t, _ptr(x), _ptr(g), _ptr(theta), _stream(stream)))
+
+    def run(self, theta, F, G, x, history=None, stream=None):
+        """len(F) steps (F: steps x n, G: steps x n_g device tensors); theta and x are
+        updated in place; returns the per-step stats dicts."""
+        steps = int(F.shape[0])
+        st = (Stats * max(steps, 1))()
+        _check(lib().mg_time_run(self.t, steps, _ptr(theta), _ptr(F), _ptr(G) if self.n_g else None, _ptr(x),
+                                 _ptr(history), st, _stream(stream)))
+        return [st[i].as_dict() for i in range(steps)]
 
 
 def validate_level(level, coarser=None) -> int:

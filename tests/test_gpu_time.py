@@ -1,0 +1,160 @@
+"""GPU parity of the time-stepping driver (Algorithm "Nonstationary Linear Problem",
+Sec. 4; backward Euler with the lumped mass of eq. mass_lumping) against the oracle's
+time loop, step by step, and the Sec. 5.1 error against the exact solution.
+
+Both sides build the operators M_l / dt + A of every level and the right-hand-side
+operators R = [Z H^T M_l | -Z H^T A E_g] and H independently (generator / oracle); the
+nodal source and Dirichlet values come from the shared seeded recipes.  Tolerances:
+  * one right-hand-side or interpolation pass: 1e-14 of the vector scale (a sum of a
+    handful of FP64 products in the same order on both sides);
+  * every step's nodal solution: 1e-10 relative (converged solves whose iteration counts
+    are asserted equal, starting from the previous step's solution on both sides).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hierarchy as Hh, multigrid as MG, timestep as TS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _log(*a):
+    print("[gpu-time]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+ADAPTIVE = W.td_time(4).with_(coarse=(8, 8), h0=0.125, rounds=(
+    ("uniform",), ("band", 0.5, 0.5, 0.3, 0.05), ("band", 0.5, 0.5, 0.3, 0.05)))
+
+
+def _data(coords, g_idx, dt, steps, exact, source):
+    X = coords
+    theta0 = exact(0.0, X[:, 0], X[:, 1])
+    F = np.stack([source(k * dt, X[:, 0], X[:, 1]) for k in range(1, steps + 1)])
+    G = np.stack([exact(k * dt, X[:, 0], X[:, 1])[g_idx] for k in range(1, steps + 1)])
+    return theta0, F, G
+
+
+def _setup(wl):
+    from paper_2405_05047_amd import gen, mg
+    p = gen.build(wl, time_ops=True)
+    h = mg.Hierarchy(p.levels, mg.config_from(wl))
+    ts = mg.TimeStepper(h, p.time, wl.dt)
+    return p, h, ts
+
+
+def _oracle(wl):
+    o = Hh.build(wl)
+    return o, MG.Multigrid(o), TS.operators(o)
+
+
+@pytest.mark.parametrize("wl", [W.td_time(5), ADAPTIVE], ids=["uniform33", "band_hanging"])
+def test_rhs_and_theta_passes(wl):
+    """b = R [theta / dt + f ; g] and theta = H x (Dirichlet values written) against the
+    oracle's sparse products on seeded vectors."""
+    p, h, ts = _setup(wl)
+    o, mgo, ops = _oracle(wl)
+    N = o.finest.ndof
+    assert p.time.n_dofs == N and np.array_equal(p.time.g_idx, ops.g_idx)
+    ng = len(ops.g_idx)
+    th, f, g, x = (W.rand_vec(s, n) for s, n in ((1, N), (2, N), (3, ng), (4, N)))
+    b = torch.empty(N, dtype=torch.float64, device="cuda")
+    ts.rhs(dev(th), dev(f), dev(g), b)
+    ref = ops.R @ np.concatenate([th / wl.dt + f, g])
+    scale = np.abs(ops.R) @ np.abs(np.concatenate([th / wl.dt + f, g]))
+    assert np.all(np.abs(host(b) - ref) <= 1e-14 * scale.max())
+    t = torch.empty(N, dtype=torch.float64, device="cuda")
+    ts.theta(dev(x), dev(g), t)
+    ref = ops.H @ x
+    ref[ops.g_idx] = g
+    assert np.abs(host(t) - ref).max() <= 1e-14 * np.abs(x).max()
+    _log(wl.name, "rhs/theta ok")
+
+
+def _compare_run(wl, steps, exact, source, rtol_step=1e-10):
+    p, h, ts = _setup(wl)
+    o, mgo, ops = _oracle(wl)
+    theta0, F, G = _data(ops.coords, ops.g_idx, wl.dt, steps, exact, source)
+    ref = TS.run(o, mgo, ops, theta0, F, G, wl.dt)
+    th = dev(theta0)
+    x = dev(np.where(ops.mask, 0.0, theta0))
+    hist = torch.empty((steps, len(theta0)), dtype=torch.float64, device="cuda")
+    stats = ts.run(th, dev(F), dev(G), x, history=hist)
+    hh = host(hist)
+    worst = 0.0
+    for k, (r, st) in enumerate(zip(ref, stats)):
+        assert st["converged"] == 1, (k, st)
+        assert st["iters"] == r.iters, (k, st["iters"], r.iters)
+        err = np.abs(hh[k] - r.theta).max() / np.abs(r.theta).max()
+        worst = max(worst, err)
+        assert err <= rtol_step, (k, err)
+    assert np.array_equal(host(th), hh[-1])
+    _log(wl.name, f"{steps} steps, worst step error {worst:.2e}, cycles "
+         f"{min(s['iters'] for s in stats)}-{max(s['iters'] for s in stats)}")
+    return o, hh
+
+
+def test_every_step_matches_oracle_and_exact_solution():
+    """Sec. 5.1 on the 129^2-node mesh (Table "tab:td" level 7, 16,641 DoFs), dt = 0.02,
+    100 steps to T = 2: every step's nodal solution equals the oracle's, and the L2 error
+    at T = 2 against the exact solution is below 1e-3 (first order in time, dominated by
+    the dt term)."""
+    wl = W.td_time(7)
+    o, hh = _compare_run(wl, 100, W.td_exact, W.td_source)
+    err = MG.l2_error(o, hh[-1], lambda q: W.td_exact(2.0, q[:, 0], q[:, 1]))
+    _log("L2 error at T=2:", f"{err:.3e}")
+    assert err < 1e-3
+
+
+def test_hanging_mesh_steps_match_oracle():
+    """The same scheme on a band-refined mesh with hanging nodes, 10 steps."""
+    _compare_run(ADAPTIVE, 10, W.td_exact, W.td_source)
+
+
+def test_linear_data_reproduced_on_hanging_mesh():
+    """theta = 0.3 + 0.5 x - 0.7 y with f = b . grad theta = 0.7 is a steady solution in
+    every Q1 space: three steps return it to solver accuracy (lifting, lumped mass, H and
+    the masks all enter)."""
+    from paper_2405_05047_amd import gen, mg
+    wl = ADAPTIVE.with_(rtol=1e-13)
+    p = gen.build(wl, time_ops=True)
+    h = mg.Hierarchy(p.levels, mg.config_from(wl))
+    ts = mg.TimeStepper(h, p.time, wl.dt)
+    lin = lambda t, x, y: 0.3 + 0.5 * x - 0.7 * y
+    src = lambda t, x, y: 0.7 + 0.0 * x
+    theta0, F, G = _data(p.time.coords, p.time.g_idx, wl.dt, 3, lin, src)
+    th = dev(theta0)
+    x = torch.zeros_like(th)
+    ts.run(th, dev(F), dev(G), x)
+    assert np.abs(host(th) - theta0).max() < 1e-11
+
+
+def test_invalid_time_setup_refused():
+    from paper_2405_05047_amd import gen, mg
+    wl = W.td_time(4)
+    p = gen.build(wl, time_ops=True)
+    h = mg.Hierarchy(p.levels, mg.config_from(wl))
+    with pytest.raises(mg.MGError):
+        mg.TimeStepper(h, p.time, 0.0)
+    bad = p.time.__class__(**{**p.time.__dict__, "g_idx": np.concatenate([p.time.g_idx, p.time.g_idx[:1]])})
+    with pytest.raises(mg.MGError):
+        mg.TimeStepper(h, bad, wl.dt)
+    col = p.time.R_col.copy()
+    col[0] = p.time.n_dofs + p.time.n_g
+    bad = p.time.__class__(**{**p.time.__dict__, "R_col": col})
+    with pytest.raises(mg.MGError):
+        mg.TimeStepper(h, bad, wl.dt)
