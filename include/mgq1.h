@@ -139,6 +139,18 @@ int mg_solve_fixed(mg_handle* h, const double* b, double* x, int32_t iters,
  * handle's partial-sum buffer, so calls on one handle must not overlap. */
 int mg_outer_defect(mg_handle* h, const double* b, const double* x, double* r, double* norm, void* stream);
 
+/* mg_outer_defect for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * the same result, but the per-workgroup partial sums of the norm live in a static device
+ * array of the library (65,536 doubles, 512 KiB, held by each GPU the library runs on
+ * until the process ends) instead of the handle's buffer, and the call allocates nothing.
+ * Finest levels whose SpMV needs more partial sums than the array holds (above about
+ * 16.7 million scalar rows) are refused with MG_EUNSUPPORTED before any device work.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (two
+ * streams, two threads) race and must be serialised by the caller. */
+int mg_outer_defect_noalloc(mg_handle* h, const double* b, const double* x, double* r, double* norm,
+                            void* stream);
+
 /* The V-cycle steps one at a time on level `level`, with the operator and vectors of the
  * cycle precision: device FP64 vectors on MG_PREC_FP64 handles, device FP32 vectors (and
  * FP32 / FP16 x 2^e / BF16 x 2^e stored values, FP32 arithmetic) on the others:

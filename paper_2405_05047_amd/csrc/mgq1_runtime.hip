@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -18,6 +19,13 @@
 #include "mgq1_internal.h"
 
 using namespace mgq1;
+
+// Partial sums of the allocation-free outer defect (mg_outer_defect_noalloc): one FP64
+// per workgroup of the finest-level FP64 SpMV.  Each GPU the library runs on holds its
+// own copy of this array until the process ends; host code reaches it only through the
+// per-device address taken with hipGetSymbolAddress at setup.
+constexpr int kScratchDoubles = 1 << 16;   // 512 KiB: finest levels up to ~16.7M scalar rows
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace {
 
@@ -443,6 +451,8 @@ struct mg_handle : DevOwner {
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
   double* dsc = nullptr;  // device scalars: [0] norm, [1] one, [2..3] givens status
   double* pbig = nullptr; // per-block partials of the outer defect norm
+  double* scratch_dev = nullptr;  // this device's copy of `scratch` (device address)
+  int scratch_cap = kScratchDoubles;
   double* pv[2] = {nullptr, nullptr};   // per-block partials of the vector reductions
   int* dflag = nullptr;
   bool fuse2z = true;     // fused first two pre-sweeps for block size 1 (MGQ1_NO_FUSE=1: off)
@@ -1875,6 +1885,26 @@ int solve_batch_impl(mg_batch* h, const double* b, double* x, mg_solve_stats* st
   return MG_OK;
 }
 
+// Device address of `scratch` on the current device, taken once per device.
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+double* g_scratch_addr[kMaxDevices] = {};
+
+int scratch_address(double** out) {
+  int dev = 0;
+  MG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MG_EUNSUPPORTED, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(MG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_addr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return MG_OK;
+}
+
 // ---------------------------------------------------------------- time stepping
 // Right-hand-side operator R, interpolation H and Dirichlet positions of a
 // backward-Euler run (Algorithm "Nonstationary Linear Problem"), on the device.
@@ -1973,6 +2003,11 @@ int mg_setup_hierarchy(const mg_level_in* lv, int32_t n_levels, const mg_config*
   h->L = n_levels - 1;
   h->xk = cfg->precision == MG_PREC_FP64 ? X_F64 : X_F32;
   h->lv.resize(n_levels);
+  if (const char* lim = std::getenv("MGQ1_SCRATCH_LIMIT")) h->scratch_cap = std::min(kScratchDoubles, std::max(0, std::atoi(lim)));
+  if ((rc = scratch_address(&h->scratch_dev))) {
+    delete h;
+    return rc;
+  }
   try {
     rc = setup_handle(h, H, s);
   } catch (const std::bad_alloc&) {
@@ -2021,6 +2056,23 @@ int mg_outer_defect(mg_handle* h, const double* b, const double* x, double* r, d
   LevelDev& T = h->lv[h->L];
   MG_HIP(launch_spmv(T.A64, b, x, r, nullptr, X_F64, X_F64, 1, h->pbig, s));
   MG_HIP(launch_finish(h->pbig, spmv_grid(T.A64), norm, 1, s));
+  return MG_OK;
+}
+
+int mg_outer_defect_noalloc(mg_handle* h, const double* b, const double* x, double* r, double* norm, void* stream) {
+  if (!h || !b || !x || !r || !norm) return fail(MG_EINVAL, "null argument");
+  if (static_cast<const void*>(r) == static_cast<const void*>(x) || static_cast<const void*>(r) == static_cast<const void*>(b))
+    return fail(MG_EINVAL, "r must not alias b or x");
+  LevelDev& T = h->lv[h->L];
+  const int g = spmv_grid(T.A64);
+  if (g > h->scratch_cap)
+    return fail(MG_EUNSUPPORTED, "the finest level needs " + std::to_string(g) + " partial sums; the static scratch array holds " +
+                                     std::to_string(h->scratch_cap));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // every workgroup writes its own partial and the finish kernel reads exactly g of them,
+  // so nothing left in the array by an earlier call is read
+  MG_HIP(launch_spmv(T.A64, b, x, r, nullptr, X_F64, X_F64, 1, h->scratch_dev, s));
+  MG_HIP(launch_finish(h->scratch_dev, g, norm, 1, s));
   return MG_OK;
 }
 

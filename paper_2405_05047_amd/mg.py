@@ -51,7 +51,7 @@ SYMBOLS = ["mg_setup_hierarchy", "mg_vcycle", "mg_solve", "mg_solve_fixed", "mg_
            "mg_validate_level", "mg_destroy", "mg_status_string", "mg_last_error",
            "mg_setup_batch", "mg_batch_offsets", "mg_solve_batch", "mg_destroy_batch",
            "mg_level_tuning", "mg_outer_defect", "mg_level_export", "mg_time_setup", "mg_time_rhs",
-           "mg_time_theta", "mg_time_run", "mg_time_destroy"]
+           "mg_time_theta", "mg_time_run", "mg_time_destroy", "mg_outer_defect_noalloc"]
 
 
 def lib():
@@ -62,6 +62,7 @@ def lib():
         L.mg_setup_hierarchy.argtypes = [C.POINTER(LevelIn), i32, C.POINTER(Config), i32, vp, C.POINTER(vp)]
         L.mg_vcycle.argtypes = [vp, vp, vp, i32, vp]
         L.mg_outer_defect.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.mg_outer_defect_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
         L.mg_level_export.argtypes = [vp, i32, vp, vp]
         L.mg_solve.argtypes = [vp, vp, vp, C.POINTER(Stats), vp]
         L.mg_solve_fixed.argtypes = [vp, vp, vp, i32, C.POINTER(Stats), vp]
@@ -233,6 +234,11 @@ class Hierarchy:
     def outer_defect(self, b, x, r, norm, stream=None):
         """r = b - A_L x and norm[0] = ||r|| in FP64 (device tensors)."""
         _check(lib().mg_outer_defect(self.h, _ptr(b), _ptr(x), _ptr(r), _ptr(norm), _stream(stream)))
+
+    def outer_defect_noalloc(self, b, x, r, norm, stream=None):
+        """outer_defect with the partial sums in the library's static device array (the
+        call allocates nothing; calls overlapping on one GPU race)."""
+        _check(lib().mg_outer_defect_noalloc(self.h, _ptr(b), _ptr(x), _ptr(r), _ptr(norm), _stream(stream)))
 
     def export(self, l):
         """Stored cycle operator of level l in BSR order: (values (nnzb, b, b) of the storage
