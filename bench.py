@@ -301,7 +301,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
-    ap.add_argument("--precisions", default="fp64,fp32,fp16,bf16")
+    ap.add_argument("--precisions", default="fp64,fp32,fp16,bf16",
+                    help="variants; a '+cheb' suffix runs the variant with the Chebyshev smoother")
+    ap.add_argument("--cheb-variants", default="fp64+cheb,fp16+cheb",
+                    help="Chebyshev-smoothed variants added for the elasticity workloads ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cache-served", action="store_true")
     ap.add_argument("--batch-problems", type=int, default=64,
@@ -328,9 +331,14 @@ def main():
     x = torch.zeros_like(b)
     results = {}
     handles = {}
-    for prec in args.precisions.split(","):
+    variants = args.precisions.split(",")
+    if wl.pde == W.PDE_ELASTICITY and args.cheb_variants:
+        variants += [v for v in args.cheb_variants.split(",") if v not in variants]
+    for prec in variants:
         t = time.perf_counter()
-        h = mg.Hierarchy(prob.levels, mg.config_from(wl, precision=prec))
+        base_prec, _, sm = prec.partition("+")
+        over = {"smoother": W.SMOOTH_CHEBYSHEV} if sm == "cheb" else {}
+        h = mg.Hierarchy(prob.levels, mg.config_from(wl, precision=base_prec, **over))
         t_setup = time.perf_counter() - t
         sec, stats = time_solves(torch, h, b, x, args.steps, args.warmup)
         xs = x.cpu().numpy()
@@ -342,7 +350,12 @@ def main():
                          "converged": all(s["converged"] for s in stats), "rel_residual": rel,
                          "setup_s": round(t_setup, 3),
                          "slot_batch_per_level": [h.tuning(l)[0] for l in range(h.n_levels)]}
-        handles[prec] = h
+        if sm == "cheb":
+            results[prec]["smoother"] = (f"Chebyshev on [{wl.cheb_lo}, {wl.cheb_hi}] x lambda(S A), lambda by "
+                                         f"{wl.power_its} power-iteration steps")
+            h.close()
+        else:
+            handles[prec] = h
         _progress(f"{wl.name} {prec}: {sec * 1e3:.2f} ms per solve, {stats[-1]['iters']} cycles")
     base = results["fp64"]
     for prec, r in results.items():

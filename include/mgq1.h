@@ -47,6 +47,8 @@ enum {
 
 enum { MG_COARSE_EXACT = 0, MG_COARSE_SMOOTH = 1 };
 enum { MG_OUTER_IR = 0, MG_OUTER_FGMRES = 1 };
+/* smoother on levels >= 1 (the coarse MG_COARSE_SMOOTH variant always uses damped sweeps) */
+enum { MG_SMOOTH_JACOBI = 0, MG_SMOOTH_CHEBYSHEV = 1 };
 /* precision of the V-cycle; the outer defect, the update and the coarse solve are FP64 */
 enum { MG_PREC_FP64 = 0, MG_PREC_FP32 = 1, MG_PREC_FP32_F16VAL = 2, MG_PREC_FP32_BF16VAL = 3 };
 
@@ -89,6 +91,16 @@ typedef struct {
                                  0 = autotune (setup times both built sizes on every level's
                                  sweep and keeps the faster), or a fixed size: 8 or 16 for
                                  block sizes 1-2, 4 or 8 for 3-4.  Results are identical. */
+  int32_t smoother;           /* MG_SMOOTH_JACOBI: x <- x + omega S (b - A x) (Sec. 4.1).
+                                 MG_SMOOTH_CHEBYSHEV: the nu sweeps of a smoothing phase form
+                                 the Chebyshev polynomial of S A on [cheb_lo, cheb_hi] *
+                                 lambda, lambda estimated per level at setup by power_its
+                                 steps of power iteration from a fixed Weyl-sequence vector;
+                                 a stronger smoother of the fixed-matrix family (Sec. 6 names
+                                 stronger smoothers as the next step).  omega is then unused
+                                 on levels >= 1. */
+  int32_t power_its;          /* power-iteration steps (Chebyshev only), 1..1000 */
+  double cheb_lo, cheb_hi;    /* Chebyshev interval as fractions of lambda, 0 < lo < hi */
 } mg_config;
 
 typedef struct {
@@ -168,6 +180,16 @@ int mg_level_spmv(mg_handle* h, int32_t level, const void* x, void* y, void* str
 int mg_level_sweep(mg_handle* h, int32_t level, const void* b, const void* x, void* x_out,
                    void* stream);
 int mg_level_sweep0(mg_handle* h, int32_t level, const void* b, void* x_out, void* stream);
+/* The level's smoother (Sec. 4.1; with MG_SMOOTH_CHEBYSHEV the three-term Chebyshev
+ * steps) applied `sweeps` times to b from x (x_is_zero = 0) or from 0 (x not read), as a
+ * pre- or post-smoothing phase of the V-cycle does; result in x_out.  Vectors of the cycle
+ * precision; x_out must not alias b or x; uses the level's work buffer, so calls on one
+ * handle must not overlap.  Chebyshev phases may have at most max(nu1, nu2) steps. */
+int mg_level_smooth(mg_handle* h, int32_t level, const void* b, const void* x, void* x_out, int32_t x_is_zero,
+                    int32_t sweeps, void* stream);
+/* The power-iteration estimate of the largest eigenvalue of S_l A_l (Chebyshev handles,
+ * levels >= 1; MG_EUNSUPPORTED otherwise). */
+int mg_level_eigen_estimate(const mg_handle* h, int32_t level, double* lambda_max);
 int mg_level_restrict(mg_handle* h, int32_t level, const void* r_fine, void* d_coarse,
                       void* stream);
 int mg_level_prolong(mg_handle* h, int32_t level, const void* y_coarse, void* x_fine,
@@ -211,7 +233,8 @@ void mg_destroy(mg_handle* h);
  * n_problems * nrhs FGMRES(m) instances run in lockstep, each with its own Hessenberg
  * matrix, Givens rotations and stopping test ||b_i - A x_i|| <= rtol ||b_i||; with
  * use_graph each Krylov step of the whole batch is one captured HIP graph.
- * Requirements: outer = MG_OUTER_FGMRES, coarse_mode = MG_COARSE_EXACT, nrhs in {1, 8}
+ * Requirements: outer = MG_OUTER_FGMRES, coarse_mode = MG_COARSE_EXACT, smoother =
+ * MG_SMOOTH_JACOBI, nrhs in {1, 8}
  * (8 for block size 1 only).  Mathematically every instance is the single-problem solve
  * of mg_solve (Algorithm "Geometric multigrid solver" inside GMRES, Sec. 4.2). */
 typedef struct mg_batch mg_batch;

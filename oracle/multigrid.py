@@ -4,6 +4,10 @@
     fixed matrix S; here S = inverse of the nodal diagonal blocks of A (damped Jacobi for
     one component, nodal block-Jacobi / point-Vanka for systems).  Sweeps are
     simultaneous (Jacobi), every sweep a full update.
+  * Stronger smoother (Sec. 6 names stronger smoothers as the next step): the nu steps of
+    a smoothing phase as the Chebyshev iteration for S A on [lo, hi] * lambda (Saad,
+    Iterative Methods for Sparse Linear Systems, Sec. 12.3, Algorithm "Chebyshev
+    acceleration"), lambda the largest eigenvalue of S A estimated by power iteration.
   * Coarse problem (Algorithm "Geometric multigrid solver", step 0): A_0^{-1} b_0 by a
     dense LU solve; the paper's GPU variant of a few smoothing sweeps is mode SMOOTH.
   * V-cycle: Algorithm "Geometric multigrid solver": pre-smooth nu1 times, restrict the
@@ -61,6 +65,12 @@ class Multigrid:
         self.coarse_mode = wl.coarse_mode if coarse_mode is None else coarse_mode
         self.coarse_sweeps = wl.coarse_sweeps if coarse_sweeps is None else coarse_sweeps
         self.S = [smoother_blocks(lv) for lv in hier.levels]
+        self.smoother = wl.smoother
+        self.cheb_lo, self.cheb_hi = wl.cheb_lo, wl.cheb_hi
+        self.lam = [None] * len(hier.levels)
+        if self.smoother == W.SMOOTH_CHEBYSHEV:
+            for l in range(1, len(hier.levels)):
+                self.lam[l] = self.power_estimate(l, wl.power_its)
         A0 = hier.levels[0].A.toarray()
         self.A0 = A0
         self.lu0 = sla.lu_factor(A0)
@@ -76,6 +86,49 @@ class Multigrid:
         A = self.h.levels[l].A
         return x + self.omega * self.apply_S(l, b - A @ x)
 
+    def power_estimate(self, l: int, its: int) -> float:
+        """Largest eigenvalue of S A by power iteration: v = Weyl vector / its norm, then
+        `its` times w = S A v, lambda = ||w||, v = w / lambda; the last lambda."""
+        A = self.h.levels[l].A
+        v = W.weyl_vec(A.shape[0])
+        v = v / np.linalg.norm(v)
+        lam = 0.0
+        for _ in range(its):
+            w = self.apply_S(l, A @ v)
+            lam = float(np.linalg.norm(w))
+            v = w / lam
+        return lam
+
+    def chebyshev(self, l: int, x: np.ndarray, b: np.ndarray, k: int) -> np.ndarray:
+        """k steps of the Chebyshev iteration for A x = b preconditioned by S, for a
+        spectrum of S A in [a, c] = [lo, hi] * lambda: theta = (c + a)/2, delta = (c - a)/2,
+        sigma = theta/delta; d_0 = S r_0 / theta; x_{j+1} = x_j + d_j;
+        rho_0 = 1/sigma, rho_{j+1} = 1/(2 sigma - rho_j),
+        d_{j+1} = rho_{j+1} rho_j d_j + (2 rho_{j+1}/delta) S r_{j+1}."""
+        A = self.h.levels[l].A
+        a, c = self.cheb_lo * self.lam[l], self.cheb_hi * self.lam[l]
+        theta, delta = (c + a) / 2, (c - a) / 2
+        sigma = theta / delta
+        rho = 1.0 / sigma
+        d = self.apply_S(l, b - A @ x) / theta
+        for j in range(k):
+            x = x + d
+            if j + 1 < k:
+                rho_next = 1.0 / (2.0 * sigma - rho)
+                d = rho_next * rho * d + (2.0 * rho_next / delta) * self.apply_S(l, b - A @ x)
+                rho = rho_next
+        return x
+
+    def smooth_phase(self, l: int, x: np.ndarray, b: np.ndarray, k: int) -> np.ndarray:
+        """A pre- or post-smoothing phase of k steps on level l >= 1."""
+        if k == 0:
+            return x
+        if self.smoother == W.SMOOTH_CHEBYSHEV:
+            return self.chebyshev(l, x, b, k)
+        for _ in range(k):
+            x = self.smooth(l, x, b)
+        return x
+
     def coarse_solve(self, b: np.ndarray) -> np.ndarray:
         if self.coarse_mode == W.COARSE_EXACT:
             return sla.lu_solve(self.lu0, b)
@@ -89,13 +142,11 @@ class Multigrid:
         if l == 0:
             return self.coarse_solve(b)                         # step 0
         lv = self.h.levels[l]
-        for _ in range(self.nu1):                               # step 1
-            x = self.smooth(l, x, b)
+        x = self.smooth_phase(l, x, b, self.nu1)                # step 1
         d = lv.R @ (b - lv.A @ x)                               # step 2
         y = self.gmg(l - 1, np.zeros(lv.R.shape[0]), d)         # step 3
         x = x + lv.P @ y                                        # step 4
-        for _ in range(self.nu2):                               # step 5
-            x = self.smooth(l, x, b)
+        x = self.smooth_phase(l, x, b, self.nu2)                # step 5
         return x
 
     def vcycle(self, b: np.ndarray) -> np.ndarray:

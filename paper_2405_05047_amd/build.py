@@ -1,6 +1,7 @@
 """Build the native libraries in-tree.
 
-  libmggen.so  host problem generator (g++ -O3 -fopenmp)
+  libmggen.so  host problem generators (g++ -O3 -fopenmp): adaptive Q1 hierarchies and the
+               explicit pressure-correction workload
   libmgq1.so   HIP solver library for gfx950 (hipcc --offload-arch=gfx950)
 
 Run as `python -m paper_2405_05047_amd.build` (or call build_all()).
@@ -18,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_GEN = os.path.join(HERE, "libmggen.so")
 LIB_MG = os.path.join(HERE, "libmgq1.so")
 
-HIP_SOURCES = ["mgq1_kernels.hip", "mgq1_batch.hip", "mgq1_runtime.hip", "mgq1_time.hip"]
+HIP_SOURCES = ["mgq1_kernels.hip", "mgq1_batch.hip", "mgq1_runtime.hip", "mgq1_time.hip", "mgq1_cheb.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
@@ -28,9 +29,9 @@ def _run(cmd):
 
 
 def build_gen():
-    src = os.path.join(CSRC, "gen", "mggen.cpp")
+    srcs = [os.path.join(CSRC, "gen", "mggen.cpp"), os.path.join(CSRC, "gen", "mgns.cpp")]
     _run(["g++", "-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-          "-Wall", "-Wextra", "-I", INCLUDE, src, "-o", LIB_GEN + ".tmp"])
+          "-Wall", "-Wextra", "-I", INCLUDE] + srcs + ["-o", LIB_GEN + ".tmp"])
     os.replace(LIB_GEN + ".tmp", LIB_GEN)
 
 

@@ -346,20 +346,24 @@ __device__ __forceinline__ T spmv_slice(const SellDev& A, const XO* __restrict__
   return out;
 }
 
+// x_out = x + omega S (b - A x), and with pmode != 0 the three-term (Chebyshev) form
+// x_out = x + omega S (b - A x) + beta (x - x_prev): pmode 1 reads x_prev from x_out
+// itself (each lane reads its own entry before it overwrites it), pmode 2 takes x_prev = 0
 template <int B, int NR, int K, class X, class T, int KB = kb_default<B>(), bool C16 = false, int LK = 0>
 __device__ __forceinline__ void sweep_slice(const SellDev& A, const X* __restrict__ S, const X* __restrict__ b,
                                             const X* __restrict__ x, X* __restrict__ xo, T omega,
-                                            const SliceLane& s) {
+                                            const SliceLane& s, T beta = T(0), int pmode = 0) {
   constexpr int W = kWave / NR;
   const int rl = s.lane / NR, q = s.lane % NR;
   // the lane's own b, x and smoother row are loaded before the row sum, so their latency
   // overlaps the slot batches
-  X bv = X(0), xv = X(0), sv[B];
+  X bv = X(0), xv = X(0), pv = X(0), sv[B];
 #pragma unroll
   for (int cc = 0; cc < B; ++cc) sv[cc] = X(0);
   if (s.valid) {
     bv = b[s.dof];
     xv = x[s.dof];
+    if (pmode == 1) pv = xo[s.dof];
 #pragma unroll
     for (int cc = 0; cc < B; ++cc) sv[cc] = S[(int64_t(s.slice) * B + cc) * W + rl];
   }
@@ -372,7 +376,11 @@ __device__ __forceinline__ void sweep_slice(const SellDev& A, const X* __restric
     const T rc = __shfl(res, ((base + cc) * NR + q) & (kWave - 1), kWave);
     if (s.valid) upd += T(sv[cc]) * rc;
   }
-  if (s.valid) xo[s.dof] = X(T(xv) + omega * upd);
+  if (s.valid) {
+    T nx = T(xv) + omega * upd;
+    if (pmode != 0) nx = nx + beta * (T(xv) - T(pv));
+    xo[s.dof] = X(nx);
+  }
 }
 
 template <int B, int NR, class X, class T>

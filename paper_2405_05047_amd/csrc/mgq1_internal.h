@@ -103,9 +103,11 @@ hipError_t launch_spmv(const SellDev& A, const void* b, const void* x, void* y, 
                        int xk, int yk, int mode, double* partials, hipStream_t s,
                        const double* dotv = nullptr);
 int spmv_grid(const SellDev& A);
-// x_out = x + omega S (b - A x); S in lane layout, same kind as the vectors
+// x_out = x + omega S (b - A x); S in lane layout, same kind as the vectors.  pmode 1:
+// also + beta (x - x_prev) with x_prev read from xo before it is overwritten (three-term
+// Chebyshev step); pmode 2: + beta x (x_prev = 0)
 hipError_t launch_sweep(const SellDev& A, const void* S, const void* b, const void* x, void* xo,
-                        double omega, int xk, hipStream_t s);
+                        double omega, int xk, hipStream_t s, double beta = 0.0, int pmode = 0);
 // x_out = omega S b
 // two sweeps from x = 0 in one pass (block size 1): xo = x1 + omega S (b - A x1), x1 = omega S b
 hipError_t launch_sweep2z(const SellDev& A, const void* S, const void* b, void* xo, double omega, int xk,
@@ -156,6 +158,14 @@ hipError_t launch_update_x(int64_t n, double* x, const void* Z, int zk, int64_t 
 hipError_t launch_backsolve(int k, int m, const double* H, const double* g, double* y, hipStream_t s);
 // g = (beta, 0, ..., 0), beta read from the device
 hipError_t launch_init_g(int m, double* g, const double* beta, hipStream_t s);
+
+// ------------------------------------------------------------------ Chebyshev setup
+// v_i = frac(i g) - 1/2, g = (sqrt(5) - 1) / 2 (Weyl sequence), in vector kind xk
+hipError_t launch_weyl(int64_t n, void* v, int xk, hipStream_t s);
+// per-workgroup partial sums of v_i^2 (reduction_grid(n) of them)
+hipError_t launch_sumsq_partials(int64_t n, const void* v, int xk, double* partials, hipStream_t s);
+// v = w / *d
+hipError_t launch_scale_inv(int64_t n, void* v, const void* w, int xk, const double* d, hipStream_t s);
 
 // ------------------------------------------------------------------ time stepping
 // b = R [theta / dt + f ; g] (R: n rows of a scalar CSR over n + n_g columns; columns

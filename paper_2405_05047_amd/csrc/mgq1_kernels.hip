@@ -63,10 +63,11 @@ __global__ __launch_bounds__(kThreads) void k_spmv(SellDev A, const XO* __restri
 
 template <int B, int K, class X, class T, int KB, bool C16>
 __global__ __launch_bounds__(kThreads) void k_sweep(SellDev A, const X* __restrict__ S, const X* __restrict__ b,
-                                                    const X* __restrict__ x, X* __restrict__ xo, T omega) {
+                                                    const X* __restrict__ x, X* __restrict__ xo, T omega,
+                                                    T beta, int pmode) {
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const SliceLane s = slice_lane<B, 1>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
-  sweep_slice<B, 1, K, X, T, KB, C16>(A, S, b, x, xo, omega, s);
+  sweep_slice<B, 1, K, X, T, KB, C16>(A, S, b, x, xo, omega, s, beta, pmode);
 }
 
 // two smoothing sweeps from x = 0 in one pass, one component per node:
@@ -593,7 +594,7 @@ hipError_t spmv_b(const SellDev& A, const void* b, const void* x, void* y, const
 
 template <int B, class X, class T>
 hipError_t sweep_t(const SellDev& A, const void* S, const void* b, const void* x, void* xo, double omega,
-                   hipStream_t s) {
+                   double beta, int pmode, hipStream_t s) {
   const unsigned g = slice_grid(A.nslices);
   if (g == 0) return hipSuccess;
   const X* SS = static_cast<const X*>(S);
@@ -601,7 +602,7 @@ hipError_t sweep_t(const SellDev& A, const void* S, const void* b, const void* x
   const X* xx = static_cast<const X*>(x);
   X* oo = static_cast<X*>(xo);
 #define MGQ1_SWEEP4(KIND, KB, C16) \
-  hipLaunchKernelGGL((k_sweep<B, KIND, X, T, KB, C16>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega))
+  hipLaunchKernelGGL((k_sweep<B, KIND, X, T, KB, C16>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega), T(beta), pmode)
 #define MGQ1_SWEEP(KIND)                                                   \
   if (A.col16) {                                                           \
     if (A.kb == kb_alt<B>()) MGQ1_SWEEP4(KIND, kb_alt<B>(), true);         \
@@ -679,21 +680,21 @@ hipError_t launch_spmv(const SellDev& A, const void* b, const void* x, void* y, 
 }
 
 hipError_t launch_sweep(const SellDev& A, const void* S, const void* b, const void* x, void* xo, double omega,
-                        int xk, hipStream_t s) {
+                        int xk, hipStream_t s, double beta, int pmode) {
   if (xk == X_F64) {
     switch (A.B) {
-      case 1: return sweep_t<1, double, double>(A, S, b, x, xo, omega, s);
-      case 2: return sweep_t<2, double, double>(A, S, b, x, xo, omega, s);
-      case 3: return sweep_t<3, double, double>(A, S, b, x, xo, omega, s);
-      case 4: return sweep_t<4, double, double>(A, S, b, x, xo, omega, s);
+      case 1: return sweep_t<1, double, double>(A, S, b, x, xo, omega, beta, pmode, s);
+      case 2: return sweep_t<2, double, double>(A, S, b, x, xo, omega, beta, pmode, s);
+      case 3: return sweep_t<3, double, double>(A, S, b, x, xo, omega, beta, pmode, s);
+      case 4: return sweep_t<4, double, double>(A, S, b, x, xo, omega, beta, pmode, s);
       default: return hipErrorInvalidValue;
     }
   }
   switch (A.B) {
-    case 1: return sweep_t<1, float, float>(A, S, b, x, xo, omega, s);
-    case 2: return sweep_t<2, float, float>(A, S, b, x, xo, omega, s);
-    case 3: return sweep_t<3, float, float>(A, S, b, x, xo, omega, s);
-    case 4: return sweep_t<4, float, float>(A, S, b, x, xo, omega, s);
+    case 1: return sweep_t<1, float, float>(A, S, b, x, xo, omega, beta, pmode, s);
+    case 2: return sweep_t<2, float, float>(A, S, b, x, xo, omega, beta, pmode, s);
+    case 3: return sweep_t<3, float, float>(A, S, b, x, xo, omega, beta, pmode, s);
+    case 4: return sweep_t<4, float, float>(A, S, b, x, xo, omega, beta, pmode, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -456,6 +456,10 @@ struct mg_handle : DevOwner {
   double* pv[2] = {nullptr, nullptr};   // per-block partials of the vector reductions
   int* dflag = nullptr;
   bool fuse2z = true;     // fused first two pre-sweeps for block size 1 (MGQ1_NO_FUSE=1: off)
+  // Chebyshev smoother (levels >= 1): estimated largest eigenvalue of S A per level and
+  // the step coefficients x_{k+1} = x_k + alpha_k S r_k + beta_k (x_k - x_{k-1})
+  std::vector<double> lam;
+  std::vector<std::vector<double>> cheb_alpha, cheb_beta;
   double* hs = nullptr;   // pinned host scalars
   double* hst = nullptr;  // pinned, device-mapped: Givens output of step j at [2j], [2j+1]
   double* hst_dev = nullptr;             // the same memory as the kernels address it
@@ -660,10 +664,29 @@ int upload_tsell(DevOwner* h, const TSellHost& T, TSellDev& D, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- V-cycle
-int smooth_level(mg_handle* h, int l, const void* b, void*& cur, void*& other, int sweeps, hipStream_t s) {
+bool chebyshev_on(const mg_handle* h, int l) { return h->cfg.smoother == MG_SMOOTH_CHEBYSHEV && l >= 1; }
+
+// damping of the first step of a smoothing phase (the first sweep from x = 0 included)
+double first_omega(const mg_handle* h, int l) { return chebyshev_on(h, l) ? h->cheb_alpha[l][0] : h->cfg.omega; }
+
+// `sweeps` smoothing steps k0, k0 + 1, ... of a phase on level l, ping-pong between cur
+// and other (cur holds x_k on entry, the result on exit).  Damped (block-)Jacobi: every
+// step is x + omega S (b - A x).  Chebyshev (levels >= 1): step k >= 1 also adds
+// beta_k (x_k - x_{k-1}), with x_{k-1} in `other` (or 0 when prev_zero is set for the first
+// step taken here), overwritten in place by x_{k+1}.
+int smooth_level(mg_handle* h, int l, const void* b, void*& cur, void*& other, int sweeps, hipStream_t s,
+                 int k0 = 0, bool prev_zero = false) {
   LevelDev& L = h->lv[l];
+  const bool cheb = chebyshev_on(h, l);
   for (int q = 0; q < sweeps; ++q) {
-    MG_HIP(launch_sweep(L.Ac, L.S, b, cur, other, h->cfg.omega, h->xk, s));
+    const int k = k0 + q;
+    if (!cheb || k == 0) {
+      MG_HIP(launch_sweep(L.Ac, L.S, b, cur, other, cheb ? h->cheb_alpha[l][0] : h->cfg.omega, h->xk, s));
+    } else {
+      const int pmode = (q == 0 && prev_zero) ? 2 : 1;
+      MG_HIP(launch_sweep(L.Ac, L.S, b, cur, other, h->cheb_alpha[l][size_t(k)], h->xk, s,
+                          h->cheb_beta[l][size_t(k)], pmode));
+    }
     std::swap(cur, other);
   }
   return MG_OK;
@@ -715,8 +738,8 @@ int vcycle_cycle(mg_handle* h, const void* bL, void* xL, hipStream_t s, bool xin
       int rc = smooth_level(h, l, bb[l], cur[l], oth[l], c.nu1 - 2, s);
       if (rc) return rc;
     } else if (c.nu1 >= 1) {
-      MG_HIP(launch_sweep0(Lv.Ac, Lv.S, bb[l], cur[l], c.omega, h->xk, s));
-      int rc = smooth_level(h, l, bb[l], cur[l], oth[l], c.nu1 - 1, s);
+      MG_HIP(launch_sweep0(Lv.Ac, Lv.S, bb[l], cur[l], first_omega(h, l), h->xk, s));
+      int rc = smooth_level(h, l, bb[l], cur[l], oth[l], c.nu1 - 1, s, 1, true);
       if (rc) return rc;
     } else {
       MG_HIP(launch_fill(Lv.N, cur[l], h->xk, 0.0, s));
@@ -958,6 +981,57 @@ int check_config(const mg_config& c) {
       (c.outer != MG_OUTER_IR && c.outer != MG_OUTER_FGMRES) ||
       (c.coarse_mode != MG_COARSE_EXACT && c.coarse_mode != MG_COARSE_SMOOTH))
     return fail(MG_EINVAL, "invalid configuration");
+  if (c.smoother != MG_SMOOTH_JACOBI && c.smoother != MG_SMOOTH_CHEBYSHEV) return fail(MG_EINVAL, "unknown smoother");
+  if (c.smoother == MG_SMOOTH_CHEBYSHEV &&
+      (!(c.cheb_lo > 0.0) || !(c.cheb_hi > c.cheb_lo) || !std::isfinite(c.cheb_hi) || c.power_its < 1 || c.power_its > 1000))
+    return fail(MG_EINVAL, "Chebyshev smoother needs 0 < cheb_lo < cheb_hi and 1 <= power_its <= 1000");
+  return MG_OK;
+}
+
+// Largest eigenvalue of S A on every level >= 1 by power iteration from the Weyl vector
+// (v <- S A v / ||S A v||, power_its steps, the last norm is the estimate), then the
+// Chebyshev step coefficients on [cheb_lo, cheb_hi] * lambda (three-term recurrence of
+// the Chebyshev iteration, Saad, Iterative Methods for Sparse Linear Systems, Sec. 12.3).
+int setup_chebyshev(mg_handle* h, hipStream_t s) {
+  const mg_config& c = h->cfg;
+  const int kmax = std::max(std::max(c.nu1, c.nu2), 1);
+  h->lam.assign(size_t(h->L) + 1, 0.0);
+  h->cheb_alpha.assign(size_t(h->L) + 1, {});
+  h->cheb_beta.assign(size_t(h->L) + 1, {});
+  for (int l = 1; l <= h->L; ++l) {
+    LevelDev& Lv = h->lv[l];
+    const int64_t n = Lv.N;
+    MG_HIP(launch_weyl(n, Lv.t, h->xk, s));
+    MG_HIP(launch_sumsq_partials(n, Lv.t, h->xk, h->pv[0], s));
+    MG_HIP(launch_finish(h->pv[0], reduction_grid(n), h->dsc + 6, 1, s));
+    MG_HIP(launch_scale_inv(n, Lv.x, Lv.t, h->xk, h->dsc + 6, s));
+    for (int it = 0; it < c.power_its; ++it) {
+      MG_HIP(launch_spmv(Lv.Ac, nullptr, Lv.x, Lv.r, nullptr, h->xk, h->xk, 0, nullptr, s));
+      MG_HIP(launch_sweep0(Lv.Ac, Lv.S, Lv.r, Lv.t, 1.0, h->xk, s));
+      MG_HIP(launch_sumsq_partials(n, Lv.t, h->xk, h->pv[0], s));
+      MG_HIP(launch_finish(h->pv[0], reduction_grid(n), h->dsc + 6, 1, s));
+      MG_HIP(launch_scale_inv(n, Lv.x, Lv.t, h->xk, h->dsc + 6, s));
+    }
+    double lam = 0.0;
+    MG_HIP(hipMemcpyAsync(&lam, h->dsc + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+    MG_HIP(hipStreamSynchronize(s));
+    if (!(lam > 0.0) || !std::isfinite(lam)) return fail(MG_ENUMERIC, "eigenvalue estimate of S A is not positive and finite");
+    h->lam[size_t(l)] = lam;
+    const double a = c.cheb_lo * lam, bnd = c.cheb_hi * lam;
+    const double theta = 0.5 * (bnd + a), delta = 0.5 * (bnd - a), sigma = theta / delta;
+    std::vector<double>& al = h->cheb_alpha[size_t(l)];
+    std::vector<double>& be = h->cheb_beta[size_t(l)];
+    al.assign(size_t(kmax), 0.0);
+    be.assign(size_t(kmax), 0.0);
+    al[0] = 1.0 / theta;
+    double rho = 1.0 / sigma;
+    for (int k = 1; k < kmax; ++k) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      al[size_t(k)] = 2.0 * rn / delta;
+      be[size_t(k)] = rn * rho;
+      rho = rn;
+    }
+  }
   return MG_OK;
 }
 
@@ -1203,8 +1277,10 @@ int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
   if ((rc = dalloc(h, &h->pbig, size_t(maxgrid)))) return rc;
   for (int q = 0; q < 2; ++q)
     if ((rc = dalloc(h, &h->pv[q], size_t(kMaxRedBlocks)))) return rc;
+  if (c.smoother == MG_SMOOTH_CHEBYSHEV && (rc = setup_chebyshev(h, s))) return rc;
   if ((rc = tune_levels(h, s))) return rc;
   if (const char* e = std::getenv("MGQ1_NO_FUSE")) h->fuse2z = std::atoi(e) == 0;
+  if (c.smoother == MG_SMOOTH_CHEBYSHEV) h->fuse2z = false;   // the fused pair is two Jacobi sweeps
   // tail: every level up to the largest one with at most tail_dofs unknowns.  Default off:
   // on MI355X one workgroup walking several levels was measured slower (dependent-load
   // latency serialises) than separate grid launches per step.
@@ -1213,6 +1289,8 @@ int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
   int top = 0;
   for (int l = 1; l <= h->L; ++l)
     if (h->lv[l].N <= tail_dofs) top = l;
+  if (top >= 1 && c.smoother == MG_SMOOTH_CHEBYSHEV)
+    return fail(MG_EUNSUPPORTED, "the single-workgroup tail runs damped Jacobi sweeps only");
   h->tail_top = top;
   std::vector<TailLevel> tl(top + 1);
   for (int l = 0; l <= top; ++l) {
@@ -2113,6 +2191,37 @@ int mg_level_sweep0(mg_handle* h, int32_t level, const void* b, void* x_out, voi
   return MG_OK;
 }
 
+int mg_level_smooth(mg_handle* h, int32_t level, const void* b, const void* x, void* x_out, int32_t x_is_zero,
+                    int32_t sweeps, void* stream) {
+  int rc = check_level(h, level);
+  if (rc) return rc;
+  if (sweeps < 1) return fail(MG_EINVAL, "sweeps must be at least 1");
+  if (x_out == b || (!x_is_zero && (x == nullptr || x_out == x))) return fail(MG_EINVAL, "smoother output must not alias its inputs");
+  if (chebyshev_on(h, level) && sweeps > int(h->cheb_alpha[size_t(level)].size()))
+    return fail(MG_EUNSUPPORTED, "more Chebyshev steps than the configured nu1 / nu2");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  LevelDev& L = h->lv[level];
+  // the ping-pong between x_out and the level's work buffer t starts where it ends in x_out
+  if (x_is_zero) {
+    const int rest = sweeps - 1;
+    void* cur = (rest % 2 == 0) ? x_out : L.t;
+    void* oth = (cur == x_out) ? L.t : x_out;
+    MG_HIP(launch_sweep0(L.Ac, L.S, b, cur, first_omega(h, level), h->xk, s));
+    return smooth_level(h, level, b, cur, oth, rest, s, 1, true);
+  }
+  void* cur = (sweeps % 2 == 0) ? x_out : L.t;
+  void* oth = (cur == x_out) ? L.t : x_out;
+  MG_HIP(launch_convert(L.N, x, h->xk, cur, h->xk, s));
+  return smooth_level(h, level, b, cur, oth, sweeps, s, 0, false);
+}
+
+int mg_level_eigen_estimate(const mg_handle* h, int32_t level, double* lambda_max) {
+  if (!h || !lambda_max || level < 0 || level > h->L) return fail(MG_EINVAL, "bad handle, level or output");
+  if (h->cfg.smoother != MG_SMOOTH_CHEBYSHEV || level < 1) return fail(MG_EUNSUPPORTED, "no estimate: not a Chebyshev level");
+  *lambda_max = h->lam[size_t(level)];
+  return MG_OK;
+}
+
 int mg_level_restrict(mg_handle* h, int32_t level, const void* r_fine, void* d_coarse, void* stream) {
   int rc = check_level(h, level);
   if (rc) return rc;
@@ -2236,6 +2345,7 @@ int mg_setup_batch(const mg_level_in* const* problems, const int32_t* n_levels, 
   if (rc) return rc;
   if (cfg->outer != MG_OUTER_FGMRES) return fail(MG_EUNSUPPORTED, "batched solves use the FGMRES outer loop");
   if (cfg->coarse_mode != MG_COARSE_EXACT) return fail(MG_EUNSUPPORTED, "batched solves use the exact coarse solve");
+  if (cfg->smoother != MG_SMOOTH_JACOBI) return fail(MG_EUNSUPPORTED, "batched solves use the damped (block-)Jacobi smoother");
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<std::vector<HostLevel>> HH(n_problems);
   for (int p = 0; p < n_problems; ++p) {

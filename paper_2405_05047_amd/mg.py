@@ -33,7 +33,8 @@ class Config(C.Structure):
                 ("coarse_mode", C.c_int32), ("coarse_sweeps", C.c_int32),
                 ("precision", C.c_int32), ("outer", C.c_int32), ("gmres_m", C.c_int32),
                 ("maxit", C.c_int32), ("rtol", C.c_double), ("use_graph", C.c_int32),
-                ("slot_batch", C.c_int32)]
+                ("slot_batch", C.c_int32), ("smoother", C.c_int32), ("power_its", C.c_int32),
+                ("cheb_lo", C.c_double), ("cheb_hi", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -51,7 +52,8 @@ SYMBOLS = ["mg_setup_hierarchy", "mg_vcycle", "mg_solve", "mg_solve_fixed", "mg_
            "mg_validate_level", "mg_destroy", "mg_status_string", "mg_last_error",
            "mg_setup_batch", "mg_batch_offsets", "mg_solve_batch", "mg_destroy_batch",
            "mg_level_tuning", "mg_outer_defect", "mg_level_export", "mg_time_setup", "mg_time_rhs",
-           "mg_time_theta", "mg_time_run", "mg_time_destroy", "mg_outer_defect_noalloc"]
+           "mg_time_theta", "mg_time_run", "mg_time_destroy", "mg_outer_defect_noalloc",
+           "mg_level_smooth", "mg_level_eigen_estimate"]
 
 
 def lib():
@@ -70,6 +72,8 @@ def lib():
         L.mg_level_spmv.argtypes = [vp, i32, vp, vp, vp]
         L.mg_level_sweep.argtypes = [vp, i32, vp, vp, vp, vp]
         L.mg_level_sweep0.argtypes = [vp, i32, vp, vp, vp]
+        L.mg_level_smooth.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp]
+        L.mg_level_eigen_estimate.argtypes = [vp, i32, C.POINTER(C.c_double)]
         L.mg_level_restrict.argtypes = [vp, i32, vp, vp, vp]
         L.mg_level_prolong.argtypes = [vp, i32, vp, vp, vp]
         L.mg_coarse_solve.argtypes = [vp, vp, vp, vp]
@@ -174,6 +178,10 @@ def config_from(wl: W.Workload, precision="fp64", **over) -> Config:
     c.rtol = over.get("rtol", wl.rtol)
     c.use_graph = over.get("use_graph", 1)
     c.slot_batch = over.get("slot_batch", 0)
+    c.smoother = over.get("smoother", wl.smoother)
+    c.power_its = over.get("power_its", wl.power_its)
+    c.cheb_lo = over.get("cheb_lo", wl.cheb_lo)
+    c.cheb_hi = over.get("cheb_hi", wl.cheb_hi)
     return c
 
 
@@ -273,6 +281,17 @@ class Hierarchy:
 
     def sweep0(self, l, b, xo, stream=None):
         _check(lib().mg_level_sweep0(self.h, l, _ptr(b), _ptr(xo), _stream(stream)))
+
+    def smooth(self, l, b, x, xo, sweeps, stream=None):
+        """The level's smoothing phase of `sweeps` steps from x (None: from 0) into xo."""
+        _check(lib().mg_level_smooth(self.h, l, _ptr(b), _ptr(x), _ptr(xo), int(x is None), int(sweeps),
+                                     _stream(stream)))
+
+    def eigen_estimate(self, l):
+        """Power-iteration estimate of the largest eigenvalue of S_l A_l (Chebyshev handles)."""
+        v = C.c_double()
+        _check(lib().mg_level_eigen_estimate(self.h, l, C.byref(v)))
+        return v.value
 
     def restrict(self, l, r, d, stream=None):
         _check(lib().mg_level_restrict(self.h, l, _ptr(r), _ptr(d), _stream(stream)))

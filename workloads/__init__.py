@@ -34,6 +34,7 @@ PDE_POISSON, PDE_TD, PDE_ELASTICITY, PDE_OSEEN = 0, 1, 2, 3
 RHS_SINSIN, RHS_DISK, RHS_CONST, RHS_FIELD, RHS_NOISE, RHS_NONE, RHS_ELAST_MMS = 0, 1, 2, 3, 4, 5, 6
 OUTER_IR, OUTER_FGMRES = 0, 1
 COARSE_EXACT, COARSE_SMOOTH = 0, 1
+SMOOTH_JACOBI, SMOOTH_CHEBYSHEV = 0, 1
 PREC_FP64, PREC_FP32, PREC_FP32_F16VAL, PREC_FP32_BF16VAL = 0, 1, 2, 3
 
 
@@ -75,6 +76,12 @@ class Workload:
     maxit: int = 200
     coarse_mode: int = COARSE_EXACT
     coarse_sweeps: int = 20
+    # smoother of levels >= 1: damped (block-)Jacobi, or its Chebyshev acceleration on
+    # [cheb_lo, cheb_hi] * lambda with lambda from power_its power-iteration steps
+    smoother: int = SMOOTH_JACOBI
+    cheb_lo: float = 0.15
+    cheb_hi: float = 1.1
+    power_its: int = 12
     # index (in the full coarsening hierarchy) of the level solved exactly; the paper allows
     # the coarse mesh to be the starting mesh or any finer one that balances multigrid work
     # against the cost of the direct solve (Sec. 2.2)
@@ -270,6 +277,14 @@ def noise(seed: int, n: int, nrhs: int = 1) -> np.ndarray:
     """Seeded N(0,1) samples, shape (n, nrhs)."""
     rng = np.random.default_rng(np.random.SeedSequence([seed, 77]))
     return rng.standard_normal((n, nrhs))
+
+
+def weyl_vec(n: int) -> np.ndarray:
+    """Start vector of the smoother's power iteration: frac(i g) - 1/2 for i = 0 .. n-1,
+    g = (sqrt(5) - 1) / 2 (Weyl's equidistributed sequence), every operation exact or
+    correctly rounded in FP64 so that any implementation of the definition agrees."""
+    t = np.arange(n, dtype=np.float64) * 0.61803398874989484820
+    return t - np.floor(t) - 0.5
 
 
 def rand_vec(seed: int, n: int) -> np.ndarray:
