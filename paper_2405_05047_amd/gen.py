@@ -56,6 +56,22 @@ class LevelView(C.Structure):
                 ("node_lattice", C.POINTER(C.c_int32)), ("max_depth", C.c_int32)]
 
 
+class NSConfig(C.Structure):
+    _fields_ = [("cells", C.c_int32 * 3), ("length", C.c_double * 3), ("n_levels", C.c_int32)]
+
+
+class NSView(C.Structure):
+    _fields_ = [("n_v", C.c_int32), ("n_p", C.c_int32), ("v_nnz", C.c_int64),
+                ("V_rowptr", C.POINTER(C.c_int32)), ("V_col", C.POINTER(C.c_int32)),
+                ("K_val", C.POINTER(C.c_double)), ("C_val", C.POINTER(C.c_double) * 3),
+                ("g_nnz", C.c_int64), ("G_rowptr", C.POINTER(C.c_int32)), ("G_col", C.POINTER(C.c_int32)),
+                ("G_val", C.POINTER(C.c_double) * 3), ("d_nnz", C.c_int64),
+                ("D_rowptr", C.POINTER(C.c_int32)), ("D_col", C.POINTER(C.c_int32)),
+                ("D_val", C.POINTER(C.c_double) * 3), ("m_v", C.POINTER(C.c_double)),
+                ("m_p", C.POINTER(C.c_double)), ("dir_mask", C.POINTER(C.c_uint8)),
+                ("dir_val", C.POINTER(C.c_double)), ("coords_v", C.POINTER(C.c_double))]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -76,6 +92,18 @@ def lib():
         L.mggen_free.restype = None
         L.mggen_last_error.argtypes = []
         L.mggen_last_error.restype = C.c_char_p
+        L.mgns_build.argtypes = [C.POINTER(NSConfig), C.POINTER(C.c_void_p)]
+        L.mgns_build.restype = C.c_int
+        L.mgns_operators.argtypes = [C.c_void_p, C.POINTER(NSView)]
+        L.mgns_operators.restype = C.c_int
+        L.mgns_num_levels.argtypes = [C.c_void_p]
+        L.mgns_num_levels.restype = C.c_int32
+        L.mgns_pressure_level.argtypes = [C.c_void_p, C.c_int32, C.POINTER(LevelView)]
+        L.mgns_pressure_level.restype = C.c_int
+        L.mgns_free.argtypes = [C.c_void_p]
+        L.mgns_free.restype = None
+        L.mgns_last_error.argtypes = []
+        L.mgns_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -248,3 +276,93 @@ def build(wl: W.Workload, nrhs: int = 1, time_ops: bool = False) -> Problem:
         return Problem(wl, levels, b, time=tops)
     finally:
         L.mggen_free(h)
+
+
+# ---------------------------------------------------------------- pressure-correction workload
+@dataclasses.dataclass
+class PressureLevel:
+    """One pressure multigrid level in the layout mg.Hierarchy takes (block 1)."""
+    n: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray              # (nnz, 1, 1)
+    p_cols: int
+    p_rowptr: Optional[np.ndarray]
+    p_col: Optional[np.ndarray]
+    p_val: Optional[np.ndarray]
+    mask: np.ndarray             # (n, 1) uint8, the pinned node
+    block: int = 1
+
+    @property
+    def nnzb(self):
+        return len(self.col)
+
+
+@dataclasses.dataclass
+class NSProblem:
+    """Matrices of the explicit pressure-correction step (host CSR arrays)."""
+    cells: tuple
+    n_v: int
+    n_p: int
+    V_rowptr: np.ndarray
+    V_col: np.ndarray
+    K_val: np.ndarray
+    C_val: List[np.ndarray]
+    G_rowptr: np.ndarray
+    G_col: np.ndarray
+    G_val: List[np.ndarray]
+    D_rowptr: np.ndarray
+    D_col: np.ndarray
+    D_val: List[np.ndarray]
+    m_v: np.ndarray
+    m_p: np.ndarray
+    dir_mask: np.ndarray         # (n_v, 3) uint8
+    dir_val: np.ndarray          # (n_v, 3)
+    coords_v: np.ndarray         # (n_v, 3)
+    levels: List[PressureLevel]  # pressure hierarchy, coarsest first
+
+
+def build_ns(cells=(32, 32, 64), lengths=(1.0, 1.0, 2.0), n_levels=5) -> NSProblem:
+    L = lib()
+    cfg = NSConfig()
+    for a in range(3):
+        cfg.cells[a] = int(cells[a])
+        cfg.length[a] = float(lengths[a])
+    cfg.n_levels = int(n_levels)
+    h = C.c_void_p()
+    if L.mgns_build(C.byref(cfg), C.byref(h)) != 0:
+        raise RuntimeError(L.mgns_last_error().decode())
+    try:
+        v = NSView()
+        if L.mgns_operators(h, C.byref(v)) != 0:
+            raise RuntimeError(L.mgns_last_error().decode())
+        nv, npr = v.n_v, v.n_p
+        f64, i32 = np.float64, np.int32
+        levels = []
+        for l in range(L.mgns_num_levels(h)):
+            lv = LevelView()
+            if L.mgns_pressure_level(h, l, C.byref(lv)) != 0:
+                raise RuntimeError(L.mgns_last_error().decode())
+            n = lv.n_nodes
+            has_p = l > 0
+            levels.append(PressureLevel(
+                n=n, rowptr=_arr(lv.rowptr, n + 1, i32), col=_arr(lv.col, lv.nnzb, i32),
+                val=_arr(lv.val, lv.nnzb, f64).reshape(-1, 1, 1), p_cols=lv.p_cols,
+                p_rowptr=_arr(lv.p_rowptr, n + 1, i32) if has_p else None,
+                p_col=_arr(lv.p_col, lv.p_nnz, i32) if has_p else None,
+                p_val=_arr(lv.p_val, lv.p_nnz, f64) if has_p else None,
+                mask=_arr(lv.dof_mask, n, np.uint8).reshape(n, 1)))
+        return NSProblem(
+            cells=tuple(cells), n_v=nv, n_p=npr,
+            V_rowptr=_arr(v.V_rowptr, nv + 1, i32), V_col=_arr(v.V_col, v.v_nnz, i32),
+            K_val=_arr(v.K_val, v.v_nnz, f64), C_val=[_arr(v.C_val[a], v.v_nnz, f64) for a in range(3)],
+            G_rowptr=_arr(v.G_rowptr, nv + 1, i32), G_col=_arr(v.G_col, v.g_nnz, i32),
+            G_val=[_arr(v.G_val[a], v.g_nnz, f64) for a in range(3)],
+            D_rowptr=_arr(v.D_rowptr, npr + 1, i32), D_col=_arr(v.D_col, v.d_nnz, i32),
+            D_val=[_arr(v.D_val[a], v.d_nnz, f64) for a in range(3)],
+            m_v=_arr(v.m_v, nv, f64), m_p=_arr(v.m_p, npr, f64),
+            dir_mask=_arr(v.dir_mask, nv * 3, np.uint8).reshape(nv, 3),
+            dir_val=_arr(v.dir_val, nv * 3, f64).reshape(nv, 3),
+            coords_v=_arr(v.coords_v, nv * 3, f64).reshape(nv, 3), levels=levels)
+    finally:
+        L.mgns_free(h)
