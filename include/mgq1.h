@@ -284,6 +284,93 @@ int mg_time_run(mg_time* t, int32_t steps, double* theta, const double* F, const
                 double* history, mg_solve_stats* stats, void* stream);
 void mg_time_destroy(mg_time* t);
 
+/* ---- explicit pressure correction: Algorithm "The fully discrete solution procedure for
+ * the Navier-Stokes equations" (Sec. 5.3) ------------------------------------------------
+ * Velocity Q1 on n_v nodes (3 components, node-major), pressure Q1 on n_p nodes; lumped
+ * masses m_v, m_p (eq. mass_lumping).  Per step, with k = dt and s = p + q:
+ *   Step 1: u_ic <- k / m_i (m_i (f_ic + u_ic / k) - nu (K u_c)_i + sum_a (C_a (u_a u_c))_i
+ *           + (G_c s)_i) on free DoFs, the Dirichlet value on the others (eq. tp gives the
+ *           nodal products u_a u_c, eq. multC their C_a products);
+ *   Step 2: q solves K_p q = -(1/k) D u (GMRES + V-cycle on the caller's pressure
+ *           hierarchy, from the previous q; zero right-hand side on its constrained
+ *           nodes), D u = sum_a D_a u_a;
+ *   Step 3: p <- p + q - nu D u / m_p.
+ * Matrices (host CSR, deep-copied at setup): K and C_a = (phi_j, d_a phi_i) on one
+ * n_v x n_v pattern; G_a = (phi^p_q, d_a phi^v_i) (n_v x n_p) on one pattern; D_a = G_a^T
+ * (n_p x n_v) on one pattern.  dir_mask / dir_val: n_v * 3.  The pressure handle must be
+ * an FP64 scalar hierarchy with n_p finest nodes; it stays owned by the caller and must
+ * outlive the object. */
+typedef struct {
+  int32_t n_v, n_p;
+  const int32_t *V_rowptr, *V_col;
+  const double* K_val;
+  const double* C_val[3];
+  const int32_t *G_rowptr, *G_col;
+  const double* G_val[3];
+  const int32_t *D_rowptr, *D_col;
+  const double* D_val[3];
+  const double *m_v, *m_p;
+  const uint8_t* dir_mask;
+  const double* dir_val;
+  double nu, dt;
+} mg_ns_in;
+typedef struct mg_ns mg_ns;
+int mg_ns_setup(const mg_ns_in* in, mg_handle* pressure, void* stream, mg_ns** out);
+/* Step 1 into u_out (device, n_v * 3; must not alias u); f: n_v * 3 or NULL (no forcing) */
+int mg_ns_momentum(mg_ns* t, const double* u, const double* p, const double* q, const double* f, double* u_out,
+                   void* stream);
+/* du = D u and rhs = -(1/k) du (0 on the pressure hierarchy's constrained nodes) */
+int mg_ns_divergence(mg_ns* t, const double* u, double* du, double* rhs, void* stream);
+/* Step 3 in place: p <- p + q - nu du / m_p */
+int mg_ns_pressure_update(mg_ns* t, double* p, const double* q, const double* du, void* stream);
+/* `steps` time steps: u, p, q (device) in/out; stats: NULL or `steps` entries (the
+ * pressure solves).  Stops at the first failing solve and returns its code. */
+int mg_ns_run(mg_ns* t, int32_t steps, double* u, double* p, double* q, const double* f, mg_solve_stats* stats,
+              void* stream);
+void mg_ns_destroy(mg_ns* t);
+
+/* ---- GPU-side assembly of the constrained Q1 operators on adaptive meshes -----------
+ * A = Z (H^T A_full H) Z + I_C (Sec. 2.2: hanging nodes through the interpolation H,
+ * constrained DoFs eliminated with identity rows / columns), the assembly the paper keeps
+ * on the CPU ("init", Sec. 5.1; Sec. 6).  mg_asm_setup takes the mesh once: the leaves
+ * (2^dim corner nodes each, bit k of the corner index = offset along axis k, and the
+ * edge length), the hanging nodes with up to 4 masters and weights (powers of two, as on
+ * box meshes: 1/2 on edges, 1/4 on faces), the DoF mask and the BSR pattern of A (sorted
+ * columns per row; blocks the mesh does not reach stay zero); at most 32 distinct cell
+ * sizes.  mg_asm_values then fills the nnzb * b * b block values (device FP64, block
+ * row-major) for the given coefficients entirely on the GPU: element matrices of every
+ * cell size from the tensor-product formulas, then one gather per stored block in a fixed
+ * order (no atomics; repeated calls are bitwise identical).  Host inputs, deep-copied. */
+enum { MG_ASM_POISSON = 0, MG_ASM_TD = 1, MG_ASM_ELASTICITY = 2 };
+typedef struct {
+  int32_t pde;                /* MG_ASM_*: (grad u, grad v); eps (grad u, grad v) + (b.grad u, v)
+                                 [+ streamline term]; 2 mu (eps(u), eps(v)) + lam (div u, div v) */
+  int32_t supg;               /* transport-diffusion: 1 = streamline stabilisation tau_K (b.grad u,
+                                 b.grad v), tau_K = h_K/(2|b|)(coth Pe - 1/Pe), Pe = |b| h_K/(2 eps) */
+  double eps, bvec[3];
+  double lam, mu;
+  double mass_coef;           /* c of a lumped-mass term c M_l (eq. mass_lumping); 0 = none */
+} mg_asm_coef;
+typedef struct {
+  int32_t dim, block;         /* 2 or 3; 1 (Laplace / transport-diffusion) or dim (elasticity) */
+  int32_t n_nodes, n_cells;
+  const int32_t* cell_corner; /* n_cells * 2^dim */
+  const double* cell_size;    /* n_cells */
+  int32_t n_hanging;
+  const int32_t* hang_node;   /* n_hanging */
+  const int32_t* hang_master; /* n_hanging * 4, -1 = unused */
+  const double* hang_weight;  /* n_hanging * 4 */
+  const uint8_t* dof_mask;    /* n_nodes * block, 1 = constrained */
+  int64_t nnzb;
+  const int32_t* A_rowptr;    /* n_nodes + 1 */
+  const int32_t* A_col;       /* nnzb */
+} mg_asm_in;
+typedef struct mg_asm mg_asm;
+int mg_asm_setup(const mg_asm_in* in, void* stream, mg_asm** out);
+/* val: device, nnzb * block * block doubles; enqueued on `stream`, nothing synchronised */
+int mg_asm_values(mg_asm* a, const mg_asm_coef* coef, double* val, void* stream);
+void mg_asm_destroy(mg_asm* a);
+
 const char* mg_status_string(int status);
 const char* mg_last_error(void);
 

@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_GEN = os.path.join(HERE, "libmggen.so")
 LIB_MG = os.path.join(HERE, "libmgq1.so")
 
-HIP_SOURCES = ["mgq1_kernels.hip", "mgq1_batch.hip", "mgq1_runtime.hip", "mgq1_time.hip", "mgq1_cheb.hip"]
+HIP_SOURCES = ["mgq1_kernels.hip", "mgq1_batch.hip", "mgq1_runtime.hip", "mgq1_time.hip", "mgq1_cheb.hip",
+               "mgq1_ns.hip", "mgq1_asm.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -178,6 +178,46 @@ hipError_t launch_time_theta(int32_t n, const int32_t* rowptr, const int32_t* co
                              const int32_t* gpos, const double* x, const double* g, double* theta,
                              hipStream_t s);
 
+// ------------------------------------------------------------------ pressure correction
+// Sliced ELL over rows with several FP64 value arrays on one pattern: slice s holds rows
+// [64 s, 64 s + 64); its slots t in [sptr[s], sptr[s+1]) hold col[t * 64 + lane] and the
+// values val[(t * V + v) * 64 + lane], v < V (V = 4 for K, C_x, C_y, C_z; 3 for G_a and
+// D_a); padding slots carry a valid column and zero values.
+struct NsEll {
+  int64_t nrows = 0, nslices = 0;
+  const int32_t* sptr = nullptr;
+  const int32_t* col = nullptr;
+  const double* val = nullptr;
+};
+// Step 1: u_out (n_v x 3) from u, s = p + q, optional forcing f (NULL = 0)
+hipError_t launch_ns_momentum(const NsEll& V, const NsEll& G, const double* u, const double* p, const double* q,
+                              const double* f, const double* m_v, const uint8_t* dmask, const double* dval, double nu,
+                              double k, double* uo, hipStream_t s);
+// du = D u, rhs = -du / k (0 where pin)
+hipError_t launch_ns_divergence(const NsEll& D, const double* u, const uint8_t* pin, double k, double* du, double* rhs,
+                                hipStream_t s);
+// Step 3: p = p + q - nu du / m_p
+hipError_t launch_ns_pressure(int64_t n, double* p, const double* q, const double* du, const double* m_p, double nu,
+                              hipStream_t s);
+
+// ------------------------------------------------------------------ GPU assembly
+enum { kAsmPoisson = 0, kAsmTD = 1, kAsmElasticity = 2 };
+struct AsmCoef {
+  int pde = kAsmPoisson;
+  double eps = 1.0, bvec[3] = {0.0, 0.0, 0.0};
+  int supg = 0;
+  double lam = 0.0, mu = 0.0, mass_coef = 0.0;
+};
+// element matrices of nd cell sizes: table[((d nb + a) nb + b) B^2 + ci B + cj]
+hipError_t launch_asm_table(const AsmCoef& c, int dim, int B, int nd, const double* sizes, double* table,
+                            hipStream_t s);
+// val[k] (B x B, row-major) of every stored block k = (brow[k], bcol[k]) from its
+// contributions code[cptr[k] .. cptr[k+1]) (d | a << 5 | b << 8 | e << 11, weight 2^-e),
+// then identity rows / zero columns of the masked DoFs
+hipError_t launch_asm_gather(int64_t nnzb, int dim, int B, const int32_t* brow, const int32_t* bcol,
+                             const uint32_t* cptr, const uint16_t* code, const double* table, const uint8_t* mask,
+                             double* val, hipStream_t s);
+
 // ------------------------------------------------------------------ batched form
 // Many independent problems (same block size) with NR right-hand sides each.  Vectors
 // of one problem are stored [node][component][rhs]; the problems' vectors are

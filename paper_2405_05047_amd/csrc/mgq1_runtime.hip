@@ -2049,6 +2049,246 @@ int time_setup(TimeDev* t, const int32_t* R_rowptr, const int32_t* R_col, const 
   return MG_OK;
 }
 
+// ---------------------------------------------------------------- pressure correction
+// Matrices and work vectors of the explicit pressure-correction step on the device.
+struct NsDev : DevOwner {
+  mg_handle* hp = nullptr;      // pressure Poisson hierarchy (caller-owned)
+  int32_t n_v = 0, n_p = 0;
+  double nu = 0.0, dt = 1.0;
+  NsEll V, G, D;
+  const double *m_v = nullptr, *m_p = nullptr, *dval = nullptr;
+  const uint8_t* dmask = nullptr;
+  double *ubuf = nullptr, *du = nullptr, *rhs = nullptr;
+};
+
+// sliced ELL of `nval` value arrays on one CSR pattern (rows x cols), see NsEll
+int upload_ns_ell(DevOwner* h, int32_t rows, const int32_t* rowptr, const int32_t* col, const double* const* vals,
+                  int nval, NsEll& E, hipStream_t s) {
+  const int64_t nsl = (int64_t(rows) + kWave - 1) / kWave;
+  std::vector<int32_t> sptr(size_t(nsl) + 1, 0);
+  for (int64_t sl = 0; sl < nsl; ++sl) {
+    int32_t w = 0;
+    for (int64_t r = sl * kWave; r < std::min<int64_t>(rows, (sl + 1) * kWave); ++r)
+      w = std::max(w, rowptr[r + 1] - rowptr[r]);
+    if (int64_t(sptr[size_t(sl)]) + w > INT32_MAX) return fail(MG_EUNSUPPORTED, "matrix too large for 32-bit slot offsets");
+    sptr[size_t(sl) + 1] = sptr[size_t(sl)] + w;
+  }
+  const int64_t slots = sptr.back();
+  std::vector<int32_t> ce(size_t(slots) * kWave, 0);
+  std::vector<double> ve(size_t(slots) * kWave * size_t(nval), 0.0);
+  for (int64_t sl = 0; sl < nsl; ++sl)
+    for (int lane = 0; lane < kWave; ++lane) {
+      const int64_t r = sl * kWave + lane;
+      if (r >= rows) continue;
+      const int32_t b0 = rowptr[r], len = rowptr[r + 1] - b0;
+      for (int32_t t = 0; t < sptr[size_t(sl) + 1] - sptr[size_t(sl)]; ++t) {
+        const int64_t slot = int64_t(sptr[size_t(sl)]) + t;
+        const size_t e = size_t(slot) * kWave + size_t(lane);
+        if (t < len) {
+          ce[e] = col[b0 + t];
+          for (int v = 0; v < nval; ++v) ve[(size_t(slot) * size_t(nval) + size_t(v)) * kWave + size_t(lane)] = vals[v][b0 + t];
+        } else {
+          ce[e] = len > 0 ? col[b0 + len - 1] : 0;   // a valid column with weight 0
+        }
+      }
+    }
+  int32_t *ps, *pc;
+  double* pv;
+  int rc;
+  if ((rc = upload(h, &ps, sptr, s)) || (rc = upload(h, &pc, ce, s)) || (rc = upload(h, &pv, ve, s))) return rc;
+  MG_HIP(hipStreamSynchronize(s));   // the host vectors are freed on return
+  E.nrows = rows;
+  E.nslices = nsl;
+  E.sptr = ps;
+  E.col = pc;
+  E.val = pv;
+  return MG_OK;
+}
+
+template <class T>
+int upload_array(DevOwner* h, const T** out, const T* src, size_t n, hipStream_t s) {
+  std::vector<T> v(src, src + n);
+  T* p;
+  int rc = upload(h, &p, v, s);
+  if (rc) return rc;
+  MG_HIP(hipStreamSynchronize(s));
+  *out = p;
+  return MG_OK;
+}
+
+int ns_setup(NsDev* t, const mg_ns_in& in, hipStream_t s) {
+  int rc;
+  const int32_t nv = in.n_v, np = in.n_p;
+  for (int a = 0; a < 3; ++a) {
+    if ((rc = check_csr(in.V_rowptr, in.V_col, in.C_val[a], nv, nv, "C"))) return rc;
+    if ((rc = check_csr(in.G_rowptr, in.G_col, in.G_val[a], nv, np, "G"))) return rc;
+    if ((rc = check_csr(in.D_rowptr, in.D_col, in.D_val[a], np, nv, "D"))) return rc;
+  }
+  if ((rc = check_csr(in.V_rowptr, in.V_col, in.K_val, nv, nv, "K"))) return rc;
+  for (int32_t i = 0; i < nv; ++i)
+    if (!(in.m_v[i] > 0.0) || !std::isfinite(in.m_v[i])) return fail(MG_EINVAL, "velocity lumped mass must be positive");
+  for (int32_t i = 0; i < np; ++i)
+    if (!(in.m_p[i] > 0.0) || !std::isfinite(in.m_p[i])) return fail(MG_EINVAL, "pressure lumped mass must be positive");
+  for (int64_t i = 0; i < int64_t(nv) * 3; ++i)
+    if (!std::isfinite(in.dir_val[i])) return fail(MG_EINVAL, "non-finite Dirichlet value");
+  const double* vv[4] = {in.K_val, in.C_val[0], in.C_val[1], in.C_val[2]};
+  if ((rc = upload_ns_ell(t, nv, in.V_rowptr, in.V_col, vv, 4, t->V, s))) return rc;
+  if ((rc = upload_ns_ell(t, nv, in.G_rowptr, in.G_col, in.G_val, 3, t->G, s))) return rc;
+  if ((rc = upload_ns_ell(t, np, in.D_rowptr, in.D_col, in.D_val, 3, t->D, s))) return rc;
+  if ((rc = upload_array(t, &t->m_v, in.m_v, size_t(nv), s))) return rc;
+  if ((rc = upload_array(t, &t->m_p, in.m_p, size_t(np), s))) return rc;
+  if ((rc = upload_array(t, &t->dmask, in.dir_mask, size_t(nv) * 3, s))) return rc;
+  if ((rc = upload_array(t, &t->dval, in.dir_val, size_t(nv) * 3, s))) return rc;
+  if ((rc = dalloc(t, &t->ubuf, size_t(nv) * 3))) return rc;
+  if ((rc = dalloc(t, &t->du, size_t(np)))) return rc;
+  if ((rc = dalloc(t, &t->rhs, size_t(np)))) return rc;
+  return MG_OK;
+}
+
+// ---------------------------------------------------------------- GPU assembly
+// Contribution lists of the assembly: for every stored block, the (cell size class,
+// corner a, corner b, hanging weight) of every element entry that reaches it through H.
+struct AsmDev : DevOwner {
+  int dim = 2, B = 1, nd = 0;
+  int64_t nnzb = 0;
+  const int32_t *brow = nullptr, *bcol = nullptr;
+  const uint32_t* cptr = nullptr;
+  const uint16_t* code = nullptr;
+  const double* sizes = nullptr;
+  const uint8_t* mask = nullptr;
+  double* table = nullptr;
+};
+
+// exponent e with w = 2^-e (0 <= e <= 7), or -1
+int dyadic_exponent(double w) {
+  for (int e = 0; e <= 7; ++e)
+    if (w == std::ldexp(1.0, -e)) return e;
+  return -1;
+}
+
+int asm_setup(AsmDev* A, const mg_asm_in& in, hipStream_t s) {
+  const int dim = in.dim, B = in.block, nb = 1 << dim;
+  const int32_t n = in.n_nodes;
+  // cell size classes
+  std::vector<double> sizes(in.cell_size, in.cell_size + in.n_cells);
+  for (double v : sizes)
+    if (!(v > 0.0) || !std::isfinite(v)) return fail(MG_EINVAL, "cell sizes must be positive");
+  std::sort(sizes.begin(), sizes.end());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  if (sizes.size() > 32) return fail(MG_EUNSUPPORTED, "more than 32 distinct cell sizes");
+  // node expansions through H: (node, weight exponent)
+  std::vector<int32_t> hslot(size_t(n), -1);
+  for (int32_t h = 0; h < in.n_hanging; ++h) {
+    const int32_t v = in.hang_node[h];
+    if (v < 0 || v >= n || hslot[size_t(v)] >= 0) return fail(MG_EINVAL, "bad or repeated hanging node");
+    hslot[size_t(v)] = h;
+    for (int q = 0; q < 4; ++q) {
+      const int32_t m = in.hang_master[4 * h + q];
+      if (m < 0) continue;
+      if (m >= n) return fail(MG_EINVAL, "hanging master out of range");
+      if (dyadic_exponent(in.hang_weight[4 * h + q]) < 0) return fail(MG_EUNSUPPORTED, "hanging weights must be 2^-e, e <= 7");
+    }
+  }
+  auto expand = [&](int32_t v, int32_t* node, int* ex) {
+    const int32_t h = hslot[size_t(v)];
+    if (h < 0) {
+      node[0] = v;
+      ex[0] = 0;
+      return 1;
+    }
+    int c = 0;
+    for (int q = 0; q < 4; ++q) {
+      const int32_t m = in.hang_master[4 * h + q];
+      if (m < 0) continue;
+      node[c] = m;
+      ex[c] = dyadic_exponent(in.hang_weight[4 * h + q]);
+      ++c;
+    }
+    return c;
+  };
+  auto row_free = [&](int32_t i) {
+    for (int c = 0; c < B; ++c)
+      if (!in.dof_mask[size_t(i) * B + c]) return true;
+    return false;
+  };
+  // pattern checks
+  if (in.A_rowptr[0] != 0 || int64_t(in.A_rowptr[n]) != in.nnzb) return fail(MG_EINVAL, "bad row pointers");
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t k = in.A_rowptr[i]; k < in.A_rowptr[i + 1]; ++k)
+      if (in.A_col[k] < 0 || in.A_col[k] >= n || (k > in.A_rowptr[i] && in.A_col[k] <= in.A_col[k - 1]))
+        return fail(MG_EINVAL, "columns must be in range, sorted and unique");
+  // contributions, cell by cell, counted per block then placed (stable)
+  std::vector<std::pair<int64_t, uint16_t>> contrib;
+  for (int32_t e = 0; e < in.n_cells; ++e) {
+    const int d = int(std::lower_bound(sizes.begin(), sizes.end(), in.cell_size[e]) - sizes.begin());
+    for (int a = 0; a < nb; ++a) {
+      const int32_t va = in.cell_corner[size_t(e) * nb + a];
+      if (va < 0 || va >= n) return fail(MG_EINVAL, "cell corner out of range");
+      int32_t na[4];
+      int xa[4];
+      const int ca = expand(va, na, xa);
+      for (int b = 0; b < nb; ++b) {
+        const int32_t vb = in.cell_corner[size_t(e) * nb + b];
+        if (vb < 0 || vb >= n) return fail(MG_EINVAL, "cell corner out of range");
+        int32_t nbn[4];
+        int xb[4];
+        const int cb = expand(vb, nbn, xb);
+        for (int qa = 0; qa < ca; ++qa) {
+          const int32_t i = na[qa];
+          if (!row_free(i)) continue;
+          const int32_t* r0 = in.A_col + in.A_rowptr[i];
+          const int32_t* r1 = in.A_col + in.A_rowptr[i + 1];
+          for (int qb = 0; qb < cb; ++qb) {
+            const int32_t* it = std::lower_bound(r0, r1, nbn[qb]);
+            if (it == r1 || *it != nbn[qb]) continue;   // a constrained column node
+            const int ex = xa[qa] + xb[qb];
+            if (ex > 7) return fail(MG_EUNSUPPORTED, "hanging weight product below 2^-7");
+            contrib.push_back({int64_t(it - in.A_col), uint16_t(d | a << 5 | b << 8 | ex << 11)});
+          }
+        }
+      }
+    }
+  }
+  if (contrib.size() >= (size_t(1) << 32)) return fail(MG_EUNSUPPORTED, "more than 2^32 contributions");
+  std::vector<uint32_t> cptr(size_t(in.nnzb) + 1, 0);
+  for (const auto& c : contrib) ++cptr[size_t(c.first) + 1];
+  for (int64_t k = 0; k < in.nnzb; ++k) cptr[size_t(k) + 1] += cptr[size_t(k)];
+  std::vector<uint16_t> code(contrib.size());
+  {
+    std::vector<uint32_t> fill(cptr.begin(), cptr.end() - 1);
+    for (const auto& c : contrib) code[fill[size_t(c.first)]++] = c.second;
+  }
+  std::vector<int32_t> brow(size_t(in.nnzb)), bcol(in.A_col, in.A_col + in.nnzb);
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t k = in.A_rowptr[i]; k < in.A_rowptr[i + 1]; ++k) brow[size_t(k)] = i;
+  std::vector<uint8_t> mask(in.dof_mask, in.dof_mask + size_t(n) * B);
+  int rc;
+  int32_t *p32;
+  uint32_t* pu;
+  uint16_t* p16;
+  double* pd;
+  uint8_t* p8;
+  if ((rc = upload(A, &p32, brow, s))) return rc;
+  A->brow = p32;
+  if ((rc = upload(A, &p32, bcol, s))) return rc;
+  A->bcol = p32;
+  if ((rc = upload(A, &pu, cptr, s))) return rc;
+  A->cptr = pu;
+  if ((rc = upload(A, &p16, code, s))) return rc;
+  A->code = p16;
+  if ((rc = upload(A, &pd, sizes, s))) return rc;
+  A->sizes = pd;
+  if ((rc = upload(A, &p8, mask, s))) return rc;
+  A->mask = p8;
+  A->nd = int(sizes.size());
+  if ((rc = dalloc(A, &A->table, size_t(A->nd) * nb * nb * B * B))) return rc;
+  MG_HIP(hipStreamSynchronize(s));   // the host vectors are freed on return
+  A->dim = dim;
+  A->B = B;
+  A->nnzb = in.nnzb;
+  return MG_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- C ABI
@@ -2460,5 +2700,129 @@ int mg_time_run(mg_time* t, int32_t steps, double* theta, const double* F, const
 }
 
 void mg_time_destroy(mg_time* t) { delete t; }
+
+struct mg_ns : NsDev {};
+
+int mg_ns_setup(const mg_ns_in* in, mg_handle* pressure, void* stream, mg_ns** out) {
+  if (!in || !pressure || !out) return fail(MG_EINVAL, "null argument");
+  *out = nullptr;
+  if (in->n_v < 1 || in->n_p < 1 || !in->m_v || !in->m_p || !in->dir_mask || !in->dir_val)
+    return fail(MG_EINVAL, "empty problem or missing array");
+  if (!(in->dt > 0.0) || !std::isfinite(in->dt) || !(in->nu >= 0.0) || !std::isfinite(in->nu))
+    return fail(MG_EINVAL, "dt must be positive and nu non-negative");
+  const LevelDev& T = pressure->lv[pressure->L];
+  if (T.B != 1 || T.n != in->n_p) return fail(MG_EINVAL, "pressure hierarchy must be scalar with n_p finest nodes");
+  if (pressure->xk != X_F64) return fail(MG_EUNSUPPORTED, "the pressure solve runs on an FP64 handle");
+  if (int64_t(in->n_v) * 3 > INT32_MAX) return fail(MG_EUNSUPPORTED, "too many velocity nodes");
+  mg_ns* t = new (std::nothrow) mg_ns();
+  if (!t) return fail(MG_ENOMEM, "host allocation failed");
+  t->hp = pressure;
+  t->n_v = in->n_v;
+  t->n_p = in->n_p;
+  t->nu = in->nu;
+  t->dt = in->dt;
+  int rc;
+  try {
+    rc = ns_setup(t, *in, static_cast<hipStream_t>(stream));
+  } catch (const std::bad_alloc&) {
+    rc = fail(MG_ENOMEM, "host allocation failed");
+  }
+  if (rc) {
+    delete t;
+    return rc;
+  }
+  *out = t;
+  return MG_OK;
+}
+
+int mg_ns_momentum(mg_ns* t, const double* u, const double* p, const double* q, const double* f, double* u_out,
+                   void* stream) {
+  if (!t || !u || !p || !q || !u_out) return fail(MG_EINVAL, "null argument");
+  if (u_out == u) return fail(MG_EINVAL, "u_out must not alias u");
+  MG_HIP(launch_ns_momentum(t->V, t->G, u, p, q, f, t->m_v, t->dmask, t->dval, t->nu, t->dt, u_out,
+                            static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
+int mg_ns_divergence(mg_ns* t, const double* u, double* du, double* rhs, void* stream) {
+  if (!t || !u || !du || !rhs) return fail(MG_EINVAL, "null argument");
+  if (du == rhs) return fail(MG_EINVAL, "du and rhs must differ");
+  MG_HIP(launch_ns_divergence(t->D, u, t->hp->lv[t->hp->L].mask, t->dt, du, rhs, static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
+int mg_ns_pressure_update(mg_ns* t, double* p, const double* q, const double* du, void* stream) {
+  if (!t || !p || !q || !du) return fail(MG_EINVAL, "null argument");
+  MG_HIP(launch_ns_pressure(t->n_p, p, q, du, t->m_p, t->nu, static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
+int mg_ns_run(mg_ns* t, int32_t steps, double* u, double* p, double* q, const double* f, mg_solve_stats* stats,
+              void* stream) {
+  if (!t || !u || !p || !q || steps < 0) return fail(MG_EINVAL, "null argument or negative step count");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t nu3 = size_t(t->n_v) * 3;
+  for (int32_t k = 0; k < steps; ++k) {
+    MG_HIP(launch_ns_momentum(t->V, t->G, u, p, q, f, t->m_v, t->dmask, t->dval, t->nu, t->dt, t->ubuf, s));
+    MG_HIP(hipMemcpyAsync(u, t->ubuf, nu3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    MG_HIP(launch_ns_divergence(t->D, u, t->hp->lv[t->hp->L].mask, t->dt, t->du, t->rhs, s));
+    const int rc = solve_impl(t->hp, t->rhs, q, stats ? stats + k : nullptr, s, 0);
+    if (rc) return rc;
+    MG_HIP(launch_ns_pressure(t->n_p, p, q, t->du, t->m_p, t->nu, s));
+  }
+  return MG_OK;
+}
+
+void mg_ns_destroy(mg_ns* t) { delete t; }
+
+struct mg_asm : AsmDev {};
+
+int mg_asm_setup(const mg_asm_in* in, void* stream, mg_asm** out) {
+  if (!in || !out) return fail(MG_EINVAL, "null argument");
+  *out = nullptr;
+  if ((in->dim != 2 && in->dim != 3) || (in->block != 1 && in->block != in->dim))
+    return fail(MG_EINVAL, "dim must be 2 or 3 and block 1 or dim");
+  if (in->n_nodes < 1 || in->n_cells < 1 || in->nnzb < 1 || !in->cell_corner || !in->cell_size || !in->dof_mask ||
+      !in->A_rowptr || !in->A_col || in->n_hanging < 0 || (in->n_hanging > 0 && (!in->hang_node || !in->hang_master ||
+                                                                               !in->hang_weight)))
+    return fail(MG_EINVAL, "empty mesh or missing array");
+  mg_asm* a = new (std::nothrow) mg_asm();
+  if (!a) return fail(MG_ENOMEM, "host allocation failed");
+  int rc;
+  try {
+    rc = asm_setup(a, *in, static_cast<hipStream_t>(stream));
+  } catch (const std::bad_alloc&) {
+    rc = fail(MG_ENOMEM, "host allocation failed");
+  }
+  if (rc) {
+    delete a;
+    return rc;
+  }
+  *out = a;
+  return MG_OK;
+}
+
+int mg_asm_values(mg_asm* a, const mg_asm_coef* coef, double* val, void* stream) {
+  if (!a || !coef || !val) return fail(MG_EINVAL, "null argument");
+  const bool scalar = coef->pde == MG_ASM_POISSON || coef->pde == MG_ASM_TD;
+  if ((coef->pde != MG_ASM_POISSON && coef->pde != MG_ASM_TD && coef->pde != MG_ASM_ELASTICITY) ||
+      (scalar ? a->B != 1 : a->B != a->dim))
+    return fail(MG_EINVAL, "pde does not match the block size");
+  if (coef->pde == MG_ASM_TD && !(coef->eps > 0.0)) return fail(MG_EINVAL, "diffusion must be positive");
+  AsmCoef c;
+  c.pde = coef->pde;
+  c.eps = coef->eps;
+  for (int k = 0; k < 3; ++k) c.bvec[k] = coef->bvec[k];
+  c.supg = coef->supg;
+  c.lam = coef->lam;
+  c.mu = coef->mu;
+  c.mass_coef = coef->mass_coef;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MG_HIP(launch_asm_table(c, a->dim, a->B, a->nd, a->sizes, a->table, s));
+  MG_HIP(launch_asm_gather(a->nnzb, a->dim, a->B, a->brow, a->bcol, a->cptr, a->code, a->table, a->mask, val, s));
+  return MG_OK;
+}
+
+void mg_asm_destroy(mg_asm* a) { delete a; }
 
 }  // extern "C"

@@ -37,6 +37,26 @@ class Config(C.Structure):
                 ("cheb_lo", C.c_double), ("cheb_hi", C.c_double)]
 
 
+class NSIn(C.Structure):
+    _fields_ = [("n_v", C.c_int32), ("n_p", C.c_int32), ("V_rowptr", C.c_void_p), ("V_col", C.c_void_p),
+                ("K_val", C.c_void_p), ("C_val", C.c_void_p * 3), ("G_rowptr", C.c_void_p), ("G_col", C.c_void_p),
+                ("G_val", C.c_void_p * 3), ("D_rowptr", C.c_void_p), ("D_col", C.c_void_p),
+                ("D_val", C.c_void_p * 3), ("m_v", C.c_void_p), ("m_p", C.c_void_p), ("dir_mask", C.c_void_p),
+                ("dir_val", C.c_void_p), ("nu", C.c_double), ("dt", C.c_double)]
+
+
+class AsmCoef(C.Structure):
+    _fields_ = [("pde", C.c_int32), ("supg", C.c_int32), ("eps", C.c_double), ("bvec", C.c_double * 3),
+                ("lam", C.c_double), ("mu", C.c_double), ("mass_coef", C.c_double)]
+
+
+class AsmIn(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("block", C.c_int32), ("n_nodes", C.c_int32), ("n_cells", C.c_int32),
+                ("cell_corner", C.c_void_p), ("cell_size", C.c_void_p), ("n_hanging", C.c_int32),
+                ("hang_node", C.c_void_p), ("hang_master", C.c_void_p), ("hang_weight", C.c_void_p),
+                ("dof_mask", C.c_void_p), ("nnzb", C.c_int64), ("A_rowptr", C.c_void_p), ("A_col", C.c_void_p)]
+
+
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32),
                 ("converged", C.c_int32), ("res0", C.c_double), ("res_final", C.c_double),
@@ -53,7 +73,9 @@ SYMBOLS = ["mg_setup_hierarchy", "mg_vcycle", "mg_solve", "mg_solve_fixed", "mg_
            "mg_setup_batch", "mg_batch_offsets", "mg_solve_batch", "mg_destroy_batch",
            "mg_level_tuning", "mg_outer_defect", "mg_level_export", "mg_time_setup", "mg_time_rhs",
            "mg_time_theta", "mg_time_run", "mg_time_destroy", "mg_outer_defect_noalloc",
-           "mg_level_smooth", "mg_level_eigen_estimate"]
+           "mg_level_smooth", "mg_level_eigen_estimate", "mg_ns_setup", "mg_ns_momentum", "mg_ns_divergence",
+           "mg_ns_pressure_update", "mg_ns_run", "mg_ns_destroy", "mg_asm_setup", "mg_asm_values",
+           "mg_asm_destroy"]
 
 
 def lib():
@@ -101,9 +123,20 @@ def lib():
         L.mg_time_run.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
         L.mg_time_destroy.argtypes = [vp]
         L.mg_time_destroy.restype = None
+        L.mg_ns_setup.argtypes = [C.POINTER(NSIn), vp, vp, C.POINTER(vp)]
+        L.mg_ns_momentum.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.mg_ns_divergence.argtypes = [vp, vp, vp, vp, vp]
+        L.mg_ns_pressure_update.argtypes = [vp, vp, vp, vp, vp]
+        L.mg_ns_run.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.mg_ns_destroy.argtypes = [vp]
+        L.mg_ns_destroy.restype = None
+        L.mg_asm_setup.argtypes = [C.POINTER(AsmIn), vp, C.POINTER(vp)]
+        L.mg_asm_values.argtypes = [vp, C.POINTER(AsmCoef), vp, vp]
+        L.mg_asm_destroy.argtypes = [vp]
+        L.mg_asm_destroy.restype = None
         for name in SYMBOLS:
             if name not in ("mg_destroy", "mg_status_string", "mg_last_error", "mg_num_levels",
-                            "mg_destroy_batch", "mg_time_destroy"):
+                            "mg_destroy_batch", "mg_time_destroy", "mg_ns_destroy", "mg_asm_destroy"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -393,6 +426,122 @@ class TimeStepper:
         _check(lib().mg_time_run(self.t, steps, _ptr(theta), _ptr(F), _ptr(G) if self.n_g else None, _ptr(x),
                                  _ptr(history), st, _stream(stream)))
         return [st[i].as_dict() for i in range(steps)]
+
+
+class PressureCorrection:
+    """The explicit pressure-correction step (library object mg_ns) on a pressure
+    hierarchy: `prob` carries the host CSR matrices (gen.NSProblem)."""
+
+    def __init__(self, prob, pressure: Hierarchy, nu: float, dt: float, stream=None):
+        L = lib()
+        keep = []
+
+        def a(v, dt_):
+            arr = np.ascontiguousarray(v, dt_)
+            keep.append(arr)
+            return arr.ctypes.data
+
+        i32, f64 = np.int32, np.float64
+        s = NSIn()
+        s.n_v, s.n_p = prob.n_v, prob.n_p
+        s.V_rowptr, s.V_col, s.K_val = a(prob.V_rowptr, i32), a(prob.V_col, i32), a(prob.K_val, f64)
+        s.G_rowptr, s.G_col = a(prob.G_rowptr, i32), a(prob.G_col, i32)
+        s.D_rowptr, s.D_col = a(prob.D_rowptr, i32), a(prob.D_col, i32)
+        for c in range(3):
+            s.C_val[c] = a(prob.C_val[c], f64)
+            s.G_val[c] = a(prob.G_val[c], f64)
+            s.D_val[c] = a(prob.D_val[c], f64)
+        s.m_v, s.m_p = a(prob.m_v, f64), a(prob.m_p, f64)
+        s.dir_mask, s.dir_val = a(prob.dir_mask, np.uint8), a(prob.dir_val, f64)
+        s.nu, s.dt = float(nu), float(dt)
+        t = C.c_void_p()
+        _check(L.mg_ns_setup(C.byref(s), pressure.h, _stream(stream), C.byref(t)))
+        self.t, self.pressure = t, pressure
+
+    def close(self):
+        if getattr(self, "t", None):
+            lib().mg_ns_destroy(self.t)
+            self.t = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def momentum(self, u, p, q, u_out, f=None, stream=None):
+        _check(lib().mg_ns_momentum(self.t, _ptr(u), _ptr(p), _ptr(q), _ptr(f), _ptr(u_out), _stream(stream)))
+
+    def divergence(self, u, du, rhs, stream=None):
+        _check(lib().mg_ns_divergence(self.t, _ptr(u), _ptr(du), _ptr(rhs), _stream(stream)))
+
+    def pressure_update(self, p, q, du, stream=None):
+        _check(lib().mg_ns_pressure_update(self.t, _ptr(p), _ptr(q), _ptr(du), _stream(stream)))
+
+    def run(self, steps, u, p, q, f=None, stream=None):
+        st = (Stats * max(int(steps), 1))()
+        _check(lib().mg_ns_run(self.t, int(steps), _ptr(u), _ptr(p), _ptr(q), _ptr(f), st, _stream(stream)))
+        return [st[i].as_dict() for i in range(int(steps))]
+
+
+ASM_PDE = {W.PDE_POISSON: 0, W.PDE_TD: 1, W.PDE_ELASTICITY: 2}
+
+
+def asm_coef(wl: W.Workload) -> AsmCoef:
+    """Coefficients of the workload's operator for the GPU assembly."""
+    c = AsmCoef()
+    c.pde = ASM_PDE[wl.pde]
+    c.supg = 1 if (wl.pde == W.PDE_TD and wl.supg) else 0
+    c.eps = wl.eps
+    for a in range(len(wl.bvec)):
+        c.bvec[a] = wl.bvec[a]
+    c.lam, c.mu, c.mass_coef = wl.lam, wl.mu, wl.mass_coef
+    return c
+
+
+class Assembly:
+    """GPU assembly of one level's constrained operator (library object mg_asm) from the
+    level's mesh (leaf corners and sizes, hanging nodes, DoF mask, block pattern)."""
+
+    def __init__(self, level, dim, stream=None):
+        L = lib()
+        keep = []
+
+        def a(v, dt_):
+            arr = np.ascontiguousarray(v, dt_)
+            keep.append(arr)
+            return arr.ctypes.data
+
+        s = AsmIn()
+        s.dim, s.block, s.n_nodes = dim, level.block, level.n
+        s.n_cells = len(level.cell_size)
+        s.cell_corner, s.cell_size = a(level.cells, np.int32), a(level.cell_size, np.float64)
+        s.n_hanging = len(level.hang_node)
+        if s.n_hanging:
+            s.hang_node = a(level.hang_node, np.int32)
+            s.hang_master = a(level.hang_master, np.int32)
+            s.hang_weight = a(level.hang_weight, np.float64)
+        s.dof_mask = a(level.mask, np.uint8)
+        s.nnzb = len(level.col)
+        s.A_rowptr, s.A_col = a(level.rowptr, np.int32), a(level.col, np.int32)
+        t = C.c_void_p()
+        _check(L.mg_asm_setup(C.byref(s), _stream(stream), C.byref(t)))
+        self.t, self.nnzb, self.block = t, s.nnzb, level.block
+
+    def close(self):
+        if getattr(self, "t", None):
+            lib().mg_asm_destroy(self.t)
+            self.t = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def values(self, coef: AsmCoef, val, stream=None):
+        """Fill val (device FP64, nnzb * b * b) with the operator's block values."""
+        _check(lib().mg_asm_values(self.t, C.byref(coef), _ptr(val), _stream(stream)))
 
 
 def validate_level(level, coarser=None) -> int:

@@ -1,0 +1,145 @@
+"""GPU parity of the explicit pressure-correction step (Sec. 5.3, Algorithm "The fully
+discrete solution procedure for the Navier-Stokes equations") against the oracle,
+through the C ABI.
+
+Both sides build the matrices independently (native generator / oracle Kronecker
+products, equal to ~1e-16).  Tolerances:
+  * one momentum step: 1e-12 of the row scale |u| + k |f| + (k / m_i) (nu |K||u| +
+    sum_a |C_a| |u_a u_c| + |G_c||s|) -- sums of at most 27 + 27 FP64 products whose
+    operands agree to ~1e-16;
+  * D u and the right-hand side: 1e-12 of |D||u|; the pressure update: 1e-12 of its
+    terms;
+  * the time loop: u, p and q after step m (m = 1, 2, ...) to m max(1e-10, 100 kappa 2^-52)
+    relative, kappa the condition number of the pinned pressure Laplacian (3.0e4 and
+    9.9e5 on the two graded test meshes): the pressure increment solves that system, so
+    right-hand sides that agree to rounding (D u is a sum with cancellation) give
+    increments that agree to about kappa times rounding, and each step carries the
+    previous steps' differences forward through u, p and the initial guess q; the
+    pressure-solve cycle counts are asserted equal.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import multigrid as MG, ns
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+NU, DT = 1e-3, 1e-4
+
+
+def _log(*a):
+    print("[gpu-ns]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def pressure_wl():
+    return ns.pressure_workload().with_(smoother=W.SMOOTH_CHEBYSHEV, gmres_m=30)
+
+
+_cache = {}
+
+
+def _pair(cells, levels):
+    key = (cells, levels)
+    if key not in _cache:
+        from paper_2405_05047_amd import gen, mg
+        _log("building", cells)
+        ops = ns.build_operators(cells)
+        H = ns.pressure_hierarchy(ops.xp, levels, pressure_wl())
+        mgo = MG.Multigrid(H)
+        prob = gen.build_ns(cells, n_levels=levels)
+        hp = mg.Hierarchy(prob.levels, mg.config_from(pressure_wl()))
+        pc = mg.PressureCorrection(prob, hp, NU, DT)
+        _cache[key] = (ops, H, mgo, prob, hp, pc)
+    return _cache[key]
+
+
+CASES = [((4, 4, 8), 3), ((8, 8, 16), 3)]
+
+
+@pytest.mark.parametrize("cells,levels", CASES)
+def test_momentum_step_parity(cells, levels):
+    ops, H, mgo, prob, hp, pc = _pair(cells, levels)
+    u = W.rand_vec(1, ops.n_v * 3).reshape(-1, 3)
+    p, q = W.rand_vec(2, ops.n_p), W.rand_vec(3, ops.n_p)
+    for f in (None, W.rand_vec(4, ops.n_v * 3).reshape(-1, 3)):
+        out = torch.empty(ops.n_v * 3, dtype=torch.float64, device="cuda")
+        pc.momentum(dev(u), dev(p), dev(q), out, f=None if f is None else dev(f))
+        ref = ns.momentum(ops, u, p + q, np.zeros_like(u) if f is None else f, NU, DT)
+        conv = sum(abs(ops.C[a]) @ np.abs(u[:, a:a + 1] * u) for a in range(3))
+        scale = (np.abs(u) + (0 if f is None else DT * np.abs(f))
+                 + DT / ops.m_v[:, None] * (NU * (abs(ops.K_v) @ np.abs(u)) + conv
+                                            + np.stack([abs(ops.G[c]) @ np.abs(p + q) for c in range(3)], 1)))
+        err = np.abs(host(out).reshape(-1, 3) - ref)
+        assert np.all(err <= 1e-12 * scale.max()), err.max() / scale.max()
+
+
+@pytest.mark.parametrize("cells,levels", CASES)
+def test_divergence_and_pressure_update_parity(cells, levels):
+    ops, H, mgo, prob, hp, pc = _pair(cells, levels)
+    u = W.rand_vec(5, ops.n_v * 3).reshape(-1, 3)
+    du = torch.empty(ops.n_p, dtype=torch.float64, device="cuda")
+    rhs = torch.empty_like(du)
+    pc.divergence(dev(u), du, rhs)
+    ref = ns.divergence(ops, u)
+    scale = sum(abs(ops.G[a]).T @ np.abs(u[:, a]) for a in range(3)).max()
+    assert np.abs(host(du) - ref).max() <= 1e-12 * scale
+    pinned = H.finest.mask[:, 0]
+    rref = ns.pressure_rhs(ref, DT, pinned)
+    assert np.abs(host(rhs) - rref).max() <= 1e-12 * scale / DT
+    assert np.all(host(rhs)[pinned] == 0.0)
+    p, q = W.rand_vec(6, ops.n_p), W.rand_vec(7, ops.n_p)
+    pd = dev(p)
+    pc.pressure_update(pd, dev(q), du)
+    pref = ns.pressure_update(ops, p, q, host(du), NU)
+    assert np.abs(host(pd) - pref).max() <= 1e-12 * (np.abs(p) + np.abs(q) + NU * np.abs(host(du)) / ops.m_p).max()
+
+
+@pytest.mark.parametrize("cells,levels,steps", [((4, 4, 8), 3, 5), ((8, 8, 16), 3, 4)])
+def test_time_steps_match_oracle(cells, levels, steps):
+    """Steps 1-3 from rest with the moving wall: u, p, q after every step equal the
+    oracle's time loop, with the same number of pressure-solve cycles."""
+    ops, H, mgo, prob, hp, pc = _pair(cells, levels)
+    kappa = np.linalg.cond(H.finest.A.toarray())
+    tol = max(1e-10, 100 * kappa * 2.0 ** -52)
+    ref = ns.run(ops, mgo, steps, NU, DT)
+    u = dev(np.where(ops.dir_mask, ops.dir_val, 0.0))
+    p = torch.zeros(ops.n_p, dtype=torch.float64, device="cuda")
+    q = torch.zeros_like(p)
+    worst = 0.0
+    for k, r in enumerate(ref):
+        st = pc.run(1, u, p, q)[0]
+        assert st["converged"] == 1 and st["iters"] == r.iters, (k, st["iters"], r.iters)
+        for name, got, want in (("u", host(u).reshape(-1, 3), r.u), ("p", host(p), r.p), ("q", host(q), r.q)):
+            err = np.linalg.norm(got - want) / np.linalg.norm(want)
+            worst = max(worst, err)
+            assert err <= (k + 1) * tol, (k, name, err, (k + 1) * tol)
+    _log(cells, steps, "steps, cycles", [r.iters for r in ref], f"kappa {kappa:.2e}, worst {worst:.2e}, tol {tol:.2e}")
+
+
+def test_invalid_setup_refused():
+    from paper_2405_05047_amd import gen, mg
+    ops, H, mgo, prob, hp, pc = _pair((4, 4, 8), 3)
+    with pytest.raises(mg.MGError):
+        mg.PressureCorrection(prob, hp, NU, 0.0)
+    bad = gen.NSProblem(**{**prob.__dict__, "m_p": np.where(np.arange(prob.n_p) == 3, 0.0, prob.m_p)})
+    with pytest.raises(mg.MGError):
+        mg.PressureCorrection(bad, hp, NU, DT)
+    other = gen.build_ns((4, 4, 8), n_levels=2)
+    hp2 = mg.Hierarchy(gen.build_ns((8, 8, 16), n_levels=2).levels, mg.config_from(pressure_wl()))
+    with pytest.raises(mg.MGError):
+        mg.PressureCorrection(other, hp2, NU, DT)
