@@ -131,6 +131,14 @@ typedef struct {
   const double* coords;
 } mggen_time_view;
 int mggen_time_ops(const mggen_problem* p, mggen_time_view* out);
+/* The leaves of level `level`: corner node numbers (n_cells * corners, corners = 2^dim;
+ * bit k of the corner index is the offset along axis k) and edge lengths. */
+typedef struct {
+  int32_t n_cells, corners;
+  const int32_t* corner;
+  const double* size;
+} mggen_cells_view;
+int mggen_level_cells(const mggen_problem* p, int32_t level, mggen_cells_view* out);
 void mggen_free(mggen_problem* p);
 const char* mggen_last_error(void);
 

@@ -556,6 +556,8 @@ struct LevelOut {
   std::vector<int32_t> hang_node, hang_master, lat;
   std::vector<double> hang_weight;
   int32_t max_depth = 0;
+  std::vector<int32_t> cells;      // leaf corners, leaves * 2^dim (bit k of a corner = axis k)
+  std::vector<double> cell_size;   // leaf edge lengths
 };
 
 struct Expand { int cnt; int32_t node[4]; double w[4]; };
@@ -724,6 +726,9 @@ void assemble(const mggen_config& c, const Tree& t, const MeshLevel& m, LevelOut
       L.hang_weight.push_back(m.hweight[4 * h + q]);
     }
   L.lat = m.lat;
+  L.cells = m.corner;
+  L.cell_size.resize(ne);
+  for (size_t e = 0; e < ne; ++e) L.cell_size[e] = hf * double(m.leaves[e].s);
 }
 
 // P~ = Q H_coarse: coarse nodal basis at the fine nodes, hanging coarse corners expanded
@@ -1053,6 +1058,19 @@ int mggen_time_ops(const mggen_problem* p, mggen_time_view* o) {
   o->H_val = T.hval.data();
   o->g_idx = T.gidx.data();
   o->coords = T.coords.data();
+  return MGGEN_OK;
+}
+
+int mggen_level_cells(const mggen_problem* p, int32_t level, mggen_cells_view* o) {
+  if (!p || !o || level < 0 || level >= int32_t(p->levels.size())) {
+    g_err = "bad problem, level or output";
+    return MGGEN_EINVAL;
+  }
+  const LevelOut& L = p->levels[size_t(level)];
+  o->corners = 1 << p->cfg.dim;
+  o->n_cells = int32_t(L.cell_size.size());
+  o->corner = L.cells.data();
+  o->size = L.cell_size.data();
   return MGGEN_OK;
 }
 

@@ -56,6 +56,11 @@ class LevelView(C.Structure):
                 ("node_lattice", C.POINTER(C.c_int32)), ("max_depth", C.c_int32)]
 
 
+class CellsView(C.Structure):
+    _fields_ = [("n_cells", C.c_int32), ("corners", C.c_int32), ("corner", C.POINTER(C.c_int32)),
+                ("size", C.POINTER(C.c_double))]
+
+
 class NSConfig(C.Structure):
     _fields_ = [("cells", C.c_int32 * 3), ("length", C.c_double * 3), ("n_levels", C.c_int32)]
 
@@ -92,6 +97,8 @@ def lib():
         L.mggen_free.restype = None
         L.mggen_last_error.argtypes = []
         L.mggen_last_error.restype = C.c_char_p
+        L.mggen_level_cells.argtypes = [C.c_void_p, C.c_int32, C.POINTER(CellsView)]
+        L.mggen_level_cells.restype = C.c_int
         L.mgns_build.argtypes = [C.POINTER(NSConfig), C.POINTER(C.c_void_p)]
         L.mgns_build.restype = C.c_int
         L.mgns_operators.argtypes = [C.c_void_p, C.POINTER(NSView)]
@@ -131,6 +138,8 @@ class GenLevel:
     hang_weight: np.ndarray      # (k, 4)
     lattice: np.ndarray          # (n, 3)
     max_depth: int
+    cells: Optional[np.ndarray] = None      # (n_cells, 2^dim) leaf corner nodes
+    cell_size: Optional[np.ndarray] = None  # (n_cells,) leaf edge lengths
 
     @property
     def nnzb(self):
@@ -246,6 +255,11 @@ def build(wl: W.Workload, nrhs: int = 1, time_ops: bool = False) -> Problem:
                 hang_weight=_arr(v.hang_weight, 4 * v.n_hanging, np.float64).reshape(-1, 4),
                 lattice=_arr(v.node_lattice, 3 * n, np.int32).reshape(n, 3),
                 max_depth=v.max_depth))
+            cv = CellsView()
+            if L.mggen_level_cells(h, l, C.byref(cv)) != 0:
+                raise RuntimeError(L.mggen_last_error().decode())
+            levels[-1].cells = _arr(cv.corner, cv.n_cells * cv.corners, np.int32).reshape(cv.n_cells, cv.corners)
+            levels[-1].cell_size = _arr(cv.size, cv.n_cells, np.float64)
         # the coarse mesh may be any level of the hierarchy; drop the levels below it
         levels = levels[min(wl.coarse_level, len(levels) - 1):]
         levels[0].p_rowptr = levels[0].p_col = levels[0].p_val = None

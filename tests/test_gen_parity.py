@@ -91,3 +91,25 @@ def test_generator_c2_full_structure():
     for g, o in zip(p.levels, h.levels):
         assert np.array_equal(g.col, o.col) and np.array_equal(g.rowptr, o.rowptr)
     assert np.array_equal(p.finest.p_val, h.finest.Pt.data)
+
+
+@pytest.mark.parametrize("wl", [W.c2_td(band_rounds=3, uniform_rounds=1), W.c3_adaptive("edge", 3)],
+                         ids=["td_band", "edge3"])
+def test_generator_cells_are_the_leaves(wl):
+    """The exported leaves (input of the GPU assembly): corner a sits at the first corner
+    plus the edge length along every axis whose bit is set in a, and the leaf volumes sum
+    to the domain's."""
+    p = gen.build(wl)
+    for lv in p.levels:
+        d = wl.dim
+        lat = lv.lattice[:, :d].astype(np.int64)
+        c0 = lat[lv.cells[:, 0]]
+        step = lat[lv.cells[:, 1]][:, 0] - c0[:, 0]
+        assert np.all(step > 0)
+        for a in range(1 << d):
+            off = np.array([(a >> k) & 1 for k in range(d)])
+            assert np.array_equal(lat[lv.cells[:, a]], c0 + step[:, None] * off[None, :])
+        vol = np.prod(np.array(wl.coarse[:d], float) * wl.h0)
+        assert np.sum(lv.cell_size ** d) == pytest.approx(vol, rel=1e-13)
+        ratio = lv.cell_size / step
+        assert np.allclose(ratio, ratio[0], rtol=1e-13, atol=0)
