@@ -259,6 +259,102 @@ def batched(torch, gen, mg, n_problems, nrhs, steps, precisions=("fp64", "fp32",
                         for k, v in res.items()}}
 
 
+def time_stepping(torch, gen, mg, n=10, steps=100):
+    """Algorithm "Nonstationary Linear Problem" on the Sec. 5.1 problem at the paper's
+    finest level (n = 10: 1,050,625 DoFs), dt = 0.02, 100 backward-Euler steps to T = 2:
+    one hierarchy for all steps, each right-hand side formed on the GPU by the lumped mass,
+    each solve from the previous solution.  Source and Dirichlet values of every step are
+    made on the host and resident in HBM before the timed region."""
+    wl = W.td_time(n)
+    p = gen.build(wl, time_ops=True)
+    h = mg.Hierarchy(p.levels, mg.config_from(wl))
+    ts = mg.TimeStepper(h, p.time, wl.dt)
+    X = p.time.coords
+    gi = p.time.g_idx
+    F = np.stack([W.td_source(k * wl.dt, X[:, 0], X[:, 1]) for k in range(1, steps + 1)])
+    G = np.stack([W.td_exact(k * wl.dt, X[:, 0], X[:, 1])[gi] for k in range(1, steps + 1)])
+    th0 = W.td_exact(0.0, X[:, 0], X[:, 1])
+    Fd, Gd = torch.from_numpy(F).cuda(), torch.from_numpy(G).cuda()
+    th = torch.from_numpy(th0).cuda()
+    x = torch.from_numpy(np.where(p.finest.mask.ravel() != 0, 0.0, th0)).cuda()
+    ts.run(th, Fd[:2], Gd[:2], x)                   # warm-up (graphs)
+    th.copy_(torch.from_numpy(th0))
+    x.copy_(torch.from_numpy(np.where(p.finest.mask.ravel() != 0, 0.0, th0)))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = ts.run(th, Fd, Gd, x)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t
+    err = float(np.abs(th.cpu().numpy() - W.td_exact(steps * wl.dt, X[:, 0], X[:, 1])).max())
+    its = [s["iters"] for s in st]
+    N = p.time.n_dofs
+    return {"workload": f"Sec. 5.1 transport-diffusion, uniform (2^{n}+1)^2 mesh, {N:,} DoFs, dt = {wl.dt}, "
+                        f"{steps} backward-Euler steps, lumped mass, FGMRES(10) + V(2,2) Jacobi, rtol 1e-8",
+            "dofs": N, "steps": steps, "total_s": round(sec, 4), "ms_per_step": round(sec / steps * 1e3, 3),
+            "dof_per_s": N * steps / sec, "cycles_min": min(its), "cycles_max": max(its),
+            "all_converged": all(s["converged"] for s in st), "max_nodal_error_at_T": err,
+            "context_paper_h100_solve_s": 9.0}
+
+
+def pressure_correction(torch, gen, mg, cells=(32, 32, 64), levels=5, steps=20, oracle_step=True):
+    """Sec. 5.3 driven cavity: explicit momentum step, pressure Poisson solve (FGMRES(30) +
+    V(2,2) with the Chebyshev smoother on the graded mesh) and pressure update per time
+    step, from rest with the moving wall; dt = 1e-4, nu = 1e-3."""
+    nu, dt = 1e-3, 1e-4
+    prob = gen.build_ns(cells, n_levels=levels)
+    pw = W.Workload(name="ns_pressure", dim=3, coarse=(1, 1, 1), h0=1.0, rounds=(), pde=W.PDE_POISSON, block=1,
+                    omega=0.8, nu1=2, nu2=2, outer=W.OUTER_FGMRES, gmres_m=30, rtol=1e-8, maxit=400,
+                    smoother=W.SMOOTH_CHEBYSHEV)
+    hp = mg.Hierarchy(prob.levels, mg.config_from(pw))
+    pc = mg.PressureCorrection(prob, hp, nu, dt)
+    u0 = np.where(prob.dir_mask != 0, prob.dir_val, 0.0)
+    u = torch.from_numpy(u0.copy()).cuda()
+    pp = torch.zeros(prob.n_p, dtype=torch.float64, device="cuda")
+    q = torch.zeros_like(pp)
+    pc.run(2, u, pp, q)                             # warm-up (graphs)
+    u.copy_(torch.from_numpy(u0))
+    pp.zero_()
+    q.zero_()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = pc.run(steps, u, pp, q)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t
+    # the explicit parts alone (momentum + divergence + update) per step
+    ub = torch.empty_like(u)
+    du = torch.empty_like(pp)
+    rhs = torch.empty_like(pp)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        pc.momentum(u, pp, q, ub)
+        pc.divergence(ub, du, rhs)
+        pc.pressure_update(pp, q, du)
+    e1.record()
+    torch.cuda.synchronize()
+    explicit_ms = e0.elapsed_time(e1) / 20
+    its = [s["iters"] for s in st]
+    out = {"workload": f"Sec. 5.3 driven cavity, pressure Q1 on the graded {cells[0]}x{cells[1]}x{cells[2]} mesh "
+                       f"({prob.n_p:,} nodes), velocity Q1 on its refinement ({prob.n_v:,} nodes x 3), "
+                       f"{levels}-level pressure hierarchy, dt = {dt}, nu = {nu}, {steps} steps from rest",
+           "velocity_dofs": prob.n_v * 3, "pressure_dofs": prob.n_p, "steps": steps,
+           "ms_per_step": round(sec / steps * 1e3, 3), "explicit_ms_per_step": round(explicit_ms, 4),
+           "pressure_cycles_min": min(its), "pressure_cycles_max": max(its),
+           "all_converged": all(s["converged"] for s in st)}
+    if oracle_step:
+        from threadpoolctl import threadpool_limits
+        from oracle import multigrid as MG, ns
+        with threadpool_limits(limits=1):
+            ops = ns.build_operators(cells)
+            H = ns.pressure_hierarchy(ops.xp, levels, pw)
+            mgo = MG.Multigrid(H)
+            t = time.perf_counter()
+            ns.run(ops, mgo, 1, nu, dt)
+            out["oracle_s_first_step"] = round(time.perf_counter() - t, 3)
+            out["oracle_cores"] = 1
+    return out
+
+
 def cpu_baseline(wl, n_full, sample_wl=None, budget_s=30.0):
     """The oracle (NumPy/SciPy, FP64) timed on the host, single-threaded, on a bounded
     sample: the same workload, or (sample_wl) the same PDE, configuration and solver on a
@@ -307,6 +403,8 @@ def main():
                     help="Chebyshev-smoothed variants added for the elasticity workloads ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cache-served", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the time-stepping and pressure-correction sections")
     ap.add_argument("--batch-problems", type=int, default=64,
                     help="problems of the batched section (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=3)
@@ -398,6 +496,11 @@ def main():
         r2["workload"] = f"{wl2.name}: {p2.finest.n:,} DoFs; its operator stream fits the 256 MB memory-side cache"
         out["roofline_cache_served"] = r2
         del h2, p2
+    if not args.no_extra:
+        _progress("time stepping (Sec. 5.1, 1,050,625 DoFs, 100 steps)")
+        out["time_stepping"] = time_stepping(torch, gen, mg)
+        _progress("pressure correction (Sec. 5.3)")
+        out["pressure_correction"] = pressure_correction(torch, gen, mg, oracle_step=not args.no_cpu_baseline)
     if args.batch_problems > 0:
         _progress("batched section")
         out["batched"] = batched(torch, gen, mg, args.batch_problems, 8, args.batch_steps)
