@@ -8,7 +8,7 @@
 //                 (exact for constant coefficients): Laplace, transport-diffusion with
 //                 the streamline-stabilisation term, linear elasticity, plus a lumped-mass
 //                 term c m_i (eq. mass_lumping)
-//   k_asm_gather  one thread per stored block (i, j): the sum over its precomputed
+//   k_asm_gather  one thread per entry of a stored block (i, j): the sum over its precomputed
 //                 contributions w K_e[a][b] (cell size class, corners a, b, w = the
 //                 product of the two hanging-node weights, a power of two), in a fixed
 //                 order, then the constraint rows and columns; no atomics, so repeated
@@ -115,7 +115,10 @@ __global__ __launch_bounds__(kAsmThreads) void k_asm_table(AsmCoef c, int dim, i
   }
 }
 
-// code = d | a << 5 | b << 8 | k << 11: cell size class, corners, weight 2^-k
+// code = d | a << 5 | b << 8 | k << 11: cell size class, corners, weight 2^-k.  One
+// thread per block entry (k, ci, cj): the B^2 threads of a block read the same short
+// contribution list (cached) and write consecutive values, so the value stream is
+// written with whole-wave contiguous stores
 __global__ __launch_bounds__(kAsmThreads) void k_asm_gather(int64_t nnzb, int dim, int B,
                                                             const int32_t* __restrict__ brow,
                                                             const int32_t* __restrict__ bcol,
@@ -124,29 +127,24 @@ __global__ __launch_bounds__(kAsmThreads) void k_asm_gather(int64_t nnzb, int di
                                                             const double* __restrict__ table,
                                                             const uint8_t* __restrict__ mask,
                                                             double* __restrict__ val) {
-  const int64_t k = int64_t(blockIdx.x) * kAsmThreads + threadIdx.x;
-  if (k >= nnzb) return;
+  const int BB = B * B;
+  const int64_t t = int64_t(blockIdx.x) * kAsmThreads + threadIdx.x;
+  if (t >= nnzb * BB) return;
+  const int64_t k = t / BB;
+  const int z = int(t - k * BB);
   const int nb = 1 << dim;
-  double acc[16];
-  for (int z = 0; z < 16; ++z) acc[z] = 0.0;
+  double acc = 0.0;
   const uint32_t t0 = cptr[k], t1 = cptr[k + 1];
-  for (uint32_t t = t0; t < t1; ++t) {
-    const uint32_t cd = code[t];
+  for (uint32_t u = t0; u < t1; ++u) {
+    const uint32_t cd = code[u];
     const int d = int(cd & 31u), a = int((cd >> 5) & 7u), b = int((cd >> 8) & 7u), e = int((cd >> 11) & 7u);
-    const double w = ldexp(1.0, -e);
-    const double* T = table + int64_t((d * nb + a) * nb + b) * B * B;
-    for (int z = 0; z < B * B; ++z) {
-      const double p = w * T[z];
-      acc[z] = acc[z] + p;
-    }
+    const double p = ldexp(1.0, -e) * table[int64_t((d * nb + a) * nb + b) * BB + z];
+    acc = acc + p;
   }
+  const int ci = z / B, cj = z - ci * B;
   const int64_t i = brow[k], j = bcol[k];
-  for (int ci = 0; ci < B; ++ci)
-    for (int cj = 0; cj < B; ++cj) {
-      double v = acc[ci * B + cj];
-      if (mask[i * B + ci] || mask[j * B + cj]) v = (i == j && ci == cj) ? 1.0 : 0.0;
-      val[k * B * B + ci * B + cj] = v;
-    }
+  if (mask[i * B + ci] || mask[j * B + cj]) acc = (i == j && ci == cj) ? 1.0 : 0.0;
+  val[t] = acc;
 }
 
 }  // namespace
@@ -165,7 +163,8 @@ hipError_t launch_asm_gather(int64_t nnzb, int dim, int B, const int32_t* brow, 
                              double* val, hipStream_t s) {
   if (nnzb == 0) return hipSuccess;
   if (B < 1 || B > 4) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_asm_gather, unsigned((nnzb + kAsmThreads - 1) / kAsmThreads), kAsmThreads, 0, s, nnzb, dim, B,
+  const int64_t n = nnzb * B * B;
+  hipLaunchKernelGGL(k_asm_gather, unsigned((n + kAsmThreads - 1) / kAsmThreads), kAsmThreads, 0, s, nnzb, dim, B,
                      brow, bcol, cptr, code, table, mask, val);
   return hipGetLastError();
 }

@@ -363,7 +363,9 @@ __device__ __forceinline__ void sweep_slice(const SellDev& A, const X* __restric
   if (s.valid) {
     bv = b[s.dof];
     xv = x[s.dof];
-    if (pmode == 1) pv = xo[s.dof];
+    // unconditional load (a load inside a branch would make the slot loop wait for it);
+    // with pmode != 1 it rereads x and the value is not used
+    pv = (pmode == 1 ? static_cast<const X*>(xo) : x)[s.dof];
 #pragma unroll
     for (int cc = 0; cc < B; ++cc) sv[cc] = S[(int64_t(s.slice) * B + cc) * W + rl];
   }
@@ -378,7 +380,7 @@ __device__ __forceinline__ void sweep_slice(const SellDev& A, const X* __restric
   }
   if (s.valid) {
     T nx = T(xv) + omega * upd;
-    if (pmode != 0) nx = nx + beta * (T(xv) - T(pv));
+    if (pmode != 0) nx = nx + beta * (T(xv) - (pmode == 1 ? T(pv) : T(0)));
     xo[s.dof] = X(nx);
   }
 }

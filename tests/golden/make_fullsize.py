@@ -4,7 +4,8 @@ For each benchmark workload at its full size this runs the oracle (FP64, test-on
 stores, at a seeded sample of DoF indices: one finest-level smoothing sweep of seeded
 vectors, one V-cycle of the workload's right-hand side from zero, and the converged
 FGMRES solution, plus the norms the tolerances are scaled by and the iteration count.
-Run from the repository root:  python tests/golden/make_fullsize.py c2 c4 c3 c3f
+Also `timestep_td10.json`: the first steps of the Sec. 5.1 time loop at 1,050,625 DoFs.
+Run from the repository root:  python tests/golden/make_fullsize.py c2 c4 c3 c3f td10
 """
 import json
 import os
@@ -61,6 +62,41 @@ def make(name):
     print("wrote", path, flush=True)
 
 
+TIME_STEPS = 3
+
+
+def make_time():
+    """The Sec. 5.1 time loop at the paper's finest level (1,050,625 DoFs): the first
+    TIME_STEPS backward-Euler steps, theta sampled after each, and the cycle counts."""
+    from oracle import timestep as TS
+    wl = W.td_time(10)
+    t = time.time()
+    o = Hh.build(wl)
+    print("td_time10 oracle hierarchy", o.finest.ndof, "DoFs, %.0f s" % (time.time() - t), flush=True)
+    mgo = MG.Multigrid(o)
+    ops = TS.operators(o)
+    X = ops.coords
+    N = o.finest.ndof
+    theta0 = W.td_exact(0.0, X[:, 0], X[:, 1])
+    F = [W.td_source(k * wl.dt, X[:, 0], X[:, 1]) for k in range(1, TIME_STEPS + 1)]
+    G = [W.td_exact(k * wl.dt, X[:, 0], X[:, 1])[ops.g_idx] for k in range(1, TIME_STEPS + 1)]
+    t = time.time()
+    res = TS.run(o, mgo, ops, theta0, F, G, wl.dt)
+    print("td_time10 %d steps %.1f s, cycles %s" % (TIME_STEPS, time.time() - t, [r.iters for r in res]), flush=True)
+    rng = np.random.default_rng(np.random.SeedSequence([4243, N]))
+    idx = np.unique(np.concatenate([[0, N - 1], rng.choice(N, N_SAMPLES, replace=False)])).astype(np.int64)
+    out = {"workload": wl.name, "ndof": int(N), "dt": wl.dt, "idx": idx.tolist(),
+           "theta": [r.theta[idx].tolist() for r in res], "theta_maxabs": [float(np.abs(r.theta).max()) for r in res],
+           "iters": [int(r.iters) for r in res]}
+    path = os.path.join(ROOT, "tests", "golden", "timestep_td10.json")
+    with open(path, "w") as f:
+        json.dump(out, f, separators=(",", ":"))
+    print("wrote", path, flush=True)
+
+
 if __name__ == "__main__":
     for n in sys.argv[1:] or ["c2", "c4"]:
-        make(n)
+        if n == "td10":
+            make_time()
+        else:
+            make(n)
