@@ -13,7 +13,10 @@ variants, the roofline of the dominant kernel (finest-level smoothing sweep) aga
 transport-diffusion problem (its 91 MB operator is served from the 256 MB memory-side
 cache, reported separately), the oracle timed on the host and the batched form (64
 uneven transport-diffusion problems x 8 right-hand sides solved together, against the
-same 512 solves done one at a time).  Progress goes to stderr.
+same 512 solves done one at a time).  Further sections: the same solve with the
+Chebyshev smoother, the GPU assembly of every level's operator, 100 backward-Euler steps
+of the Sec. 5.1 problem on 1,050,625 DoFs, and the Sec. 5.3 pressure-correction step on
+the graded 32x32x64 mesh.  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -80,12 +83,15 @@ def time_solves(torch, h, b, x, steps, warmup):
         h.solve(b, x)
     torch.cuda.synchronize()
     stats = []
+    per = []
     t0 = time.perf_counter()
     for _ in range(steps):
+        t = time.perf_counter()
         x.zero_()
-        stats.append(h.solve(b, x))
+        stats.append(h.solve(b, x))      # returns after the solve's final synchronisation
+        per.append(time.perf_counter() - t)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps, stats
+    return (time.perf_counter() - t0) / steps, stats, per
 
 
 def counter_traffic(workload_name):
@@ -355,6 +361,41 @@ def pressure_correction(torch, gen, mg, cells=(32, 32, 64), levels=5, steps=20, 
     return out
 
 
+def gpu_assembly(torch, gen, mg, prob, wl, reps=5):
+    """GPU-side assembly of every level's constrained operator of `prob` (the paper's CPU
+    "init"): host symbolic phase once per mesh, then the numeric phase on the GPU (element
+    matrices per cell size + one gather per stored block), timed with HIP events; checked
+    against the generator's host assembly."""
+    out = {"levels": []}
+    total_ms = 0.0
+    worst = 0.0
+    for l, lv in enumerate(prob.levels):
+        t = time.perf_counter()
+        a = mg.Assembly(lv, wl.dim)
+        t_sym = time.perf_counter() - t
+        val = torch.empty(lv.nnzb * lv.block * lv.block, dtype=torch.float64, device="cuda")
+        coef = mg.asm_coef(wl)
+        a.values(coef, val)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            a.values(coef, val)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        total_ms += ms
+        ref = np.asarray(lv.val).reshape(-1)
+        worst = max(worst, float(np.abs(val.cpu().numpy() - ref).max() / np.abs(ref).max()))
+        out["levels"].append({"level": l, "blocks": int(lv.nnzb), "numeric_ms": round(ms, 4),
+                              "write_gbs": round(lv.nnzb * lv.block * lv.block * 8 / (ms * 1e-3) / 1e9, 1),
+                              "host_symbolic_s": round(t_sym, 3)})
+        del a, val
+    out["numeric_ms_all_levels"] = round(total_ms, 4)
+    out["max_rel_diff_vs_host_generator"] = worst
+    return out
+
+
 def cpu_baseline(wl, n_full, sample_wl=None, budget_s=30.0):
     """The oracle (NumPy/SciPy, FP64) timed on the host, single-threaded, on a bounded
     sample: the same workload, or (sample_wl) the same PDE, configuration and solver on a
@@ -438,13 +479,15 @@ def main():
         over = {"smoother": W.SMOOTH_CHEBYSHEV} if sm == "cheb" else {}
         h = mg.Hierarchy(prob.levels, mg.config_from(wl, precision=base_prec, **over))
         t_setup = time.perf_counter() - t
-        sec, stats = time_solves(torch, h, b, x, args.steps, args.warmup)
+        sec, stats, per = time_solves(torch, h, b, x, args.steps, args.warmup)
         xs = x.cpu().numpy()
         # FP64 residual of the last solution, recomputed on the host from the generator's operator
         import scipy.sparse as sp
         A = sp.bsr_matrix((top.val, top.col, top.rowptr), shape=(N, N)).tocsr()
         rel = float(np.linalg.norm(prob.b - A @ xs) / np.linalg.norm(prob.b))
-        results[prec] = {"dof_per_s": N / sec, "ms_per_solve": sec * 1e3, "cycles": stats[-1]["iters"],
+        results[prec] = {"dof_per_s": N / sec, "ms_per_solve": sec * 1e3, "ms_min": min(per) * 1e3,
+                         "ms_median": float(np.median(per)) * 1e3, "ms_max": max(per) * 1e3,
+                         "cycles": stats[-1]["iters"],
                          "converged": all(s["converged"] for s in stats), "rel_residual": rel,
                          "setup_s": round(t_setup, 3),
                          "slot_batch_per_level": [h.tuning(l)[0] for l in range(h.n_levels)]}
@@ -496,6 +539,12 @@ def main():
         r2["workload"] = f"{wl2.name}: {p2.finest.n:,} DoFs; its operator stream fits the 256 MB memory-side cache"
         out["roofline_cache_served"] = r2
         del h2, p2
+    if not args.no_extra and wl.pde in mg.ASM_PDE:
+        _progress("GPU assembly of every level")
+        ga = gpu_assembly(torch, gen, mg, prob, wl)
+        ga["workload"] = wl.name
+        ga["host_generator_s"] = round(t_gen, 2)
+        out["gpu_assembly"] = ga
     if not args.no_extra:
         _progress("time stepping (Sec. 5.1, 1,050,625 DoFs, 100 steps)")
         out["time_stepping"] = time_stepping(torch, gen, mg)

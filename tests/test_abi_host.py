@@ -16,10 +16,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared(header):
     txt = open(os.path.join(ROOT, "include", header)).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)          # drop comments
-    return sorted(set(re.findall(r"\b((?:mg|mggen)_[a-z0-9_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b((?:mg|mggen|mgns)_[a-z0-9_]+)\s*\(", txt)))
 
 
-@pytest.mark.parametrize("header,lib", [("mgq1.h", "libmgq1.so"), ("mggen.h", "libmggen.so")])
+@pytest.mark.parametrize("header,lib", [("mgq1.h", "libmgq1.so"), ("mggen.h", "libmggen.so"),
+                                        ("mgns.h", "libmggen.so")])
 def test_symbols_exported(header, lib):
     path = os.path.join(ROOT, "paper_2405_05047_amd", lib)
     out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True, check=True).stdout
@@ -151,4 +152,61 @@ def test_invalid_config_rejected(levels, field, value):
     arr, keep = mg.level_structs(levels)
     h = C.c_void_p()
     assert mg.lib().mg_setup_hierarchy(arr, len(levels), C.byref(cfg), 0, None, C.byref(h)) == -1
+    assert mg.last_error()
+
+
+def _asm_rc(level, dim):
+    """Status of mg_asm_setup on a malformed level (refused before any device work)."""
+    import ctypes as C
+    L = mg.lib()
+    keep = []
+
+    def a(v, dt):
+        arr = np.ascontiguousarray(v, dt)
+        keep.append(arr)
+        return arr.ctypes.data
+
+    s = mg.AsmIn()
+    s.dim, s.block, s.n_nodes = dim, level.block, level.n
+    s.n_cells = len(level.cell_size)
+    s.cell_corner, s.cell_size = a(level.cells, np.int32), a(level.cell_size, np.float64)
+    s.n_hanging = len(level.hang_node)
+    if s.n_hanging:
+        s.hang_node = a(level.hang_node, np.int32)
+        s.hang_master = a(level.hang_master, np.int32)
+        s.hang_weight = a(level.hang_weight, np.float64)
+    s.dof_mask = a(level.mask, np.uint8)
+    s.nnzb = len(level.col)
+    s.A_rowptr, s.A_col = a(level.rowptr, np.int32), a(level.col, np.int32)
+    t = C.c_void_p()
+    return L.mg_asm_setup(C.byref(s), None, C.byref(t))
+
+
+@pytest.mark.parametrize("breakage", ["corner", "weight", "unsorted", "sizes"])
+def test_assembly_input_refused_on_host(breakage):
+    """mg_asm_setup validates the mesh before touching the device: corners out of range
+    and unsorted patterns are MG_EINVAL, non-dyadic hanging weights and more than 32 cell
+    sizes are MG_EUNSUPPORTED."""
+    import dataclasses
+    wl = W.c2_td(band_rounds=2, uniform_rounds=1)
+    lv = gen.build(wl).finest
+    assert len(lv.hang_node) > 0
+    if breakage == "corner":
+        cells = lv.cells.copy()
+        cells[3, 1] = lv.n
+        bad, want = dataclasses.replace(lv, cells=cells), -1
+    elif breakage == "weight":
+        w = lv.hang_weight.copy()
+        w[0, 0] = 0.3
+        bad, want = dataclasses.replace(lv, hang_weight=w), -7
+    elif breakage == "unsorted":
+        col = lv.col.copy()
+        i = int(np.nonzero(np.diff(lv.rowptr) >= 3)[0][0])
+        k = lv.rowptr[i]
+        col[k], col[k + 1] = col[k + 1], col[k]
+        bad, want = dataclasses.replace(lv, col=col), -1
+    else:
+        sizes = lv.cell_size * (1.0 + 1e-3 * (np.arange(len(lv.cell_size)) % 40))
+        bad, want = dataclasses.replace(lv, cell_size=sizes), -7
+    assert _asm_rc(bad, wl.dim) == want
     assert mg.last_error()
