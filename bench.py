@@ -153,7 +153,9 @@ def sweep_roofline(torch, h, name, bound):
 
 def kernel_time(torch, h, level, n_dof, launches=50):
     """Average duration of the finest-level smoothing sweep with HIP events on the
-    stream the library launches on (torch's current stream)."""
+    stream the library launches on (torch's current stream).  The launches are queued
+    behind a bounded spin kernel, so the GPU runs them back to back even when one launch
+    is shorter than the host's time to issue it (the 2D sweeps take ~19 us)."""
     g = torch.Generator(device="cuda")
     g.manual_seed(7)
     xa = torch.rand(n_dof, dtype=torch.float64, device="cuda", generator=g)
@@ -164,6 +166,7 @@ def kernel_time(torch, h, level, n_dof, launches=50):
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda._sleep(20_000_000)
     e0.record()
     for i in range(launches):
         if i % 2 == 0:

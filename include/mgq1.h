@@ -218,6 +218,16 @@ int32_t mg_num_levels(const mg_handle* h);
 int mg_level_tuning(const mg_handle* h, int32_t level, int32_t* slot_batch, int32_t* col_bytes,
                     double* us_default, double* us_other);
 
+/* Storage of the transfers between level `level` - 1 and `level` (level >= 1) on a
+ * single-problem handle: bytes per stored column index of P~ and of R = P~^T (2: 16-bit
+ * offsets from a per-slot base, when every slot of every slice spans less than 2^16
+ * columns; else 4) and bytes per weight (1: the code w * 128 of dyadic weights
+ * k / 128 <= 255 / 128, the weights of nested box meshes; 4: FP32 when every weight is
+ * FP32-exact; else 8).  Every form gives the same bits (Sec. 4.1: prolongation and
+ * restriction as sparse products).  Any output pointer may be NULL. */
+int mg_level_transfer_format(const mg_handle* h, int32_t level, int32_t* p_col_bytes, int32_t* r_col_bytes,
+                             int32_t* weight_bytes);
+
 /* Host-only structural validation of one level (and its coarser neighbour for P~);
  * no device is touched.  Returns MG_OK or MG_EINVAL with a message. */
 int mg_validate_level(const mg_level_in* lv, const mg_level_in* coarser);

@@ -440,7 +440,14 @@ __device__ __forceinline__ void prolong_dof(const CsrDev& P, const X* __restrict
 // ---- sliced transfers: NB slots of one node row, loads first (straight-line), then the
 // weighted sum in slot order.  MC: apply the column mask (entries whose column DoF is
 // masked contribute 0).
-template <int NB, int B, int NR, class X, class T, class WT, bool MC, bool NT>
+// weight of a transfer slot: float / double as stored, or an 8-bit code w = code / 128
+template <class WT>
+__device__ __forceinline__ auto tsell_weight(WT w) {
+  if constexpr (sizeof(WT) == 1) return float(w) * 0.0078125f;
+  else return w;
+}
+
+template <int NB, int B, int NR, class X, class T, class WT, bool MC, bool NT, bool C16>
 __device__ __forceinline__ void tsell_batch(const TSellDev& M, int k, int r, int c, int q,
                                             const X* __restrict__ in, const uint8_t* __restrict__ mcol,
                                             T& acc) {
@@ -451,7 +458,8 @@ __device__ __forceinline__ void tsell_batch(const TSellDev& M, int k, int r, int
   uint8_t ms[NB];
 #pragma unroll
   for (int qq = 0; qq < NB; ++qq) {
-    js[qq] = unsigned(stream_load<NT>(M.col + int64_t(k + qq) * R + r));
+    if constexpr (C16) js[qq] = unsigned(M.colbase[k + qq]) + unsigned(stream_load<NT>(M.col16 + int64_t(k + qq) * R + r));
+    else js[qq] = unsigned(stream_load<NT>(M.col + int64_t(k + qq) * R + r));
     ws[qq] = stream_load<NT>(static_cast<const WT*>(M.w) + int64_t(k + qq) * R + r);
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -463,21 +471,21 @@ __device__ __forceinline__ void tsell_batch(const TSellDev& M, int k, int r, int
   }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int qq = 0; qq < NB; ++qq) acc += T(ws[qq]) * (ms[qq] ? T(0) : T(vs[qq]));
+  for (int qq = 0; qq < NB; ++qq) acc += T(tsell_weight(ws[qq])) * (ms[qq] ? T(0) : T(vs[qq]));
 }
 
-template <int N, int B, int NR, class X, class T, class WT, bool MC, bool NT>
+template <int N, int B, int NR, class X, class T, class WT, bool MC, bool NT, bool C16>
 __device__ __forceinline__ void tsell_rest(int rem, const TSellDev& M, int k, int r, int c, int q,
                                            const X* __restrict__ in, const uint8_t* __restrict__ mcol, T& acc) {
   if constexpr (N >= 1) {
-    if (rem == N) tsell_batch<N, B, NR, X, T, WT, MC, NT>(M, k, r, c, q, in, mcol, acc);
-    else tsell_rest<N - 1, B, NR, X, T, WT, MC, NT>(rem, M, k, r, c, q, in, mcol, acc);
+    if (rem == N) tsell_batch<N, B, NR, X, T, WT, MC, NT, C16>(M, k, r, c, q, in, mcol, acc);
+    else tsell_rest<N - 1, B, NR, X, T, WT, MC, NT, C16>(rem, M, k, r, c, q, in, mcol, acc);
   }
 }
 
 // one lane of a sliced transfer.  MODE 0: out = restriction sum (zero on masked rows);
 // MODE 1: out += prolongation sum (rows whose DoF is masked are left unchanged)
-template <int B, int NR, class X, class T, class WT, bool MC, int MODE>
+template <int B, int NR, class X, class T, class WT, bool MC, int MODE, bool C16 = false>
 __device__ __forceinline__ void tsell_lane(const TSellDev& M, int slice, int lane, const X* __restrict__ in,
                                            X* __restrict__ out, const uint8_t* __restrict__ mrow,
                                            const uint8_t* __restrict__ mcol) {
@@ -499,23 +507,23 @@ __device__ __forceinline__ void tsell_lane(const TSellDev& M, int slice, int lan
   slot_range(M, su, k, k1);
   T acc = T(0);
   if (M.nt) {
-    for (; k + KB <= k1; k += KB) tsell_batch<KB, B, NR, X, T, WT, MC, true>(M, k, r, c, q, in, mcol, acc);
-    tsell_rest<KB - 1, B, NR, X, T, WT, MC, true>(k1 - k, M, k, r, c, q, in, mcol, acc);
+    for (; k + KB <= k1; k += KB) tsell_batch<KB, B, NR, X, T, WT, MC, true, C16>(M, k, r, c, q, in, mcol, acc);
+    tsell_rest<KB - 1, B, NR, X, T, WT, MC, true, C16>(k1 - k, M, k, r, c, q, in, mcol, acc);
   } else {
-    for (; k + KB <= k1; k += KB) tsell_batch<KB, B, NR, X, T, WT, MC, false>(M, k, r, c, q, in, mcol, acc);
-    tsell_rest<KB - 1, B, NR, X, T, WT, MC, false>(k1 - k, M, k, r, c, q, in, mcol, acc);
+    for (; k + KB <= k1; k += KB) tsell_batch<KB, B, NR, X, T, WT, MC, false, C16>(M, k, r, c, q, in, mcol, acc);
+    tsell_rest<KB - 1, B, NR, X, T, WT, MC, false, C16>(k1 - k, M, k, r, c, q, in, mcol, acc);
   }
   if (MODE == 0) out[t] = masked ? X(0) : X(acc);
   else if (!masked) out[t] = X(T(old) + acc);
 }
 
-template <int B, int NR, class X, class T, class WT, bool MC, int MODE>
+template <int B, int NR, class X, class T, class WT, bool MC, int MODE, bool C16>
 __global__ __launch_bounds__(kThreads) void k_tsell(TSellDev M, const X* __restrict__ in, X* __restrict__ out,
                                                     const uint8_t* __restrict__ mrow,
                                                     const uint8_t* __restrict__ mcol) {
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  tsell_lane<B, NR, X, T, WT, MC, MODE>(M, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave, in, out,
-                                        mrow, mcol);
+  tsell_lane<B, NR, X, T, WT, MC, MODE, C16>(M, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave, in,
+                                             out, mrow, mcol);
 }
 
 inline unsigned grid_for(int64_t n, int threads) { return unsigned((n + threads - 1) / threads); }

@@ -68,6 +68,11 @@ struct TSellDev {
   const int32_t* col = nullptr;
   const void* w = nullptr;
   int f32 = 1;
+  // compact form (single right-hand side): 16-bit column offsets from a per-slot base
+  // (col16[k * R + r] + colbase[k]; NULL: col) and weights as 8-bit codes w = code / 128
+  const uint16_t* col16 = nullptr;
+  const int32_t* colbase = nullptr;
+  int w8 = 0;
 };
 
 // d = M_c P~^T M_f r (rows = coarse nodes; mask_f may be NULL) and x += M_f P~ M_c y

@@ -757,28 +757,38 @@ hipError_t launch_sweep0(const SellDev& A, const void* S, const void* b, void* x
 }
 
 namespace {
-template <int B, class X, class T, class WT>
-hipError_t tsell_w(int mode, const TSellDev& M, const void* in, void* out, const uint8_t* mrow,
-                   const uint8_t* mcol, hipStream_t s) {
+template <int B, class X, class T, class WT, bool C16>
+hipError_t tsell_wc(int mode, const TSellDev& M, const void* in, void* out, const uint8_t* mrow,
+                    const uint8_t* mcol, hipStream_t s) {
   const unsigned g = slice_grid(M.nslices);
   if (g == 0) return hipSuccess;
   const X* ii = static_cast<const X*>(in);
   X* oo = static_cast<X*>(out);
   if (mode == 0) {
-    if (mcol) hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, true, 0>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
-    else hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, false, 0>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
+    if (mcol) hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, true, 0, C16>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
+    else hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, false, 0, C16>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
   } else {
-    hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, true, 1>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
+    hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, true, 1, C16>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
   }
   return hipGetLastError();
+}
+
+template <int B, class X, class T, class WT>
+hipError_t tsell_w(int mode, const TSellDev& M, const void* in, void* out, const uint8_t* mrow,
+                   const uint8_t* mcol, hipStream_t s) {
+  if (M.col16) return tsell_wc<B, X, T, WT, true>(mode, M, in, out, mrow, mcol, s);
+  return tsell_wc<B, X, T, WT, false>(mode, M, in, out, mrow, mcol, s);
 }
 
 template <int B>
 hipError_t tsell_b(int mode, const TSellDev& M, const void* in, void* out, const uint8_t* mrow,
                    const uint8_t* mcol, int xk, hipStream_t s) {
-  if (xk == X_F64)
+  if (xk == X_F64) {
+    if (M.w8) return tsell_w<B, double, double, uint8_t>(mode, M, in, out, mrow, mcol, s);
     return M.f32 ? tsell_w<B, double, double, float>(mode, M, in, out, mrow, mcol, s)
                  : tsell_w<B, double, double, double>(mode, M, in, out, mrow, mcol, s);
+  }
+  if (M.w8) return tsell_w<B, float, float, uint8_t>(mode, M, in, out, mrow, mcol, s);
   return M.f32 ? tsell_w<B, float, float, float>(mode, M, in, out, mrow, mcol, s)
                : tsell_w<B, float, float, double>(mode, M, in, out, mrow, mcol, s);
 }

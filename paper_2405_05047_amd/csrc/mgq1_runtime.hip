@@ -340,6 +340,7 @@ struct TSellHost {
   int32_t nrows = 0, ncols = 0, R = 64, nslices = 0, ell = 0;
   std::vector<int32_t> sptr, col;
   std::vector<double> w;
+  std::vector<uint8_t> empty;   // per slot entry: lane of an empty row or past the last row
 };
 
 TSellHost build_tsell(const CsrHost& C, int B, int NR) {
@@ -365,11 +366,14 @@ TSellHost build_tsell(const CsrHost& C, int B, int NR) {
   const int64_t slots = S.sptr[S.nslices];
   S.col.assign(size_t(slots) * S.R, 0);
   S.w.assign(size_t(slots) * S.R, 0.0);
+  S.empty.assign(size_t(slots) * S.R, 1);
   for (int32_t sl = 0; sl < S.nslices; ++sl)
     for (int r = 0; r < S.R; ++r) {
       const int64_t i = int64_t(sl) * S.R + r;
       if (i >= C.nrows) continue;
       const int32_t b0 = C.rowptr[i], len = C.rowptr[i + 1] - b0;
+      if (len > 0)
+        for (int32_t k = 0; k < S.sptr[sl + 1] - S.sptr[sl]; ++k) S.empty[size_t((S.sptr[sl] + k) * S.R + r)] = 0;
       for (int32_t k = 0; k < S.sptr[sl + 1] - S.sptr[sl]; ++k) {
         const int64_t slot = int64_t(S.sptr[sl]) + k;
         if (k < len) {
@@ -632,7 +636,14 @@ int upload_csr(DevOwner* h, const CsrHost& C, CsrDev& D, hipStream_t s) {
   return MG_OK;
 }
 
-int upload_tsell(DevOwner* h, const TSellHost& T, TSellDev& D, hipStream_t s) {
+// compact: allow 16-bit column offsets (every slot's columns span less than 2^16) and
+// 8-bit weight codes (every weight is code / 128, code <= 255: the dyadic transfer weights
+// of box meshes); used for single-right-hand-side transfers, the batch keeps the plain form.
+// Either form gives the same bits (the codes decode exactly, the slot order is unchanged);
+// MGQ1_PLAIN_TRANSFERS=1 keeps the plain form everywhere (tests).
+int upload_tsell(DevOwner* h, const TSellHost& T, TSellDev& D, hipStream_t s, bool compact = false) {
+  const char* plain = std::getenv("MGQ1_PLAIN_TRANSFERS");
+  if (plain && std::atoi(plain) != 0) compact = false;
   D.nrows = T.nrows;
   D.ncols = T.ncols;
   D.R = T.R;
@@ -641,14 +652,59 @@ int upload_tsell(DevOwner* h, const TSellHost& T, TSellDev& D, hipStream_t s) {
   bool exact = true;
   for (double w : T.w) exact = exact && (double(float(w)) == w);
   D.f32 = exact;
-  D.nt = stream_nt(int64_t(T.col.size()) * (4 + (exact ? 4 : 8)));
+  bool w8 = compact, c16 = compact;
+  for (double w : T.w) {
+    const double cd = w * 128.0;
+    w8 = w8 && cd >= 0.0 && cd <= 255.0 && cd == std::floor(cd);
+  }
+  // the span of a slot counts the lanes of non-empty rows only: an empty row (a Dirichlet
+  // node's row of P~) adds 0 * in[c] to +0 whatever its column c, so its lanes read the
+  // slot's base column in the compact form (the same bits)
+  const int64_t slots = int64_t(T.col.size()) / T.R;
+  std::vector<int32_t> base(size_t(std::max<int64_t>(slots, 1)), 0);
+  for (int64_t k = 0; c16 && k < slots; ++k) {
+    int32_t lo = INT32_MAX, hi = INT32_MIN;
+    for (int r = 0; r < T.R; ++r) {
+      if (T.empty[size_t(k * T.R + r)]) continue;
+      lo = std::min(lo, T.col[size_t(k * T.R + r)]);
+      hi = std::max(hi, T.col[size_t(k * T.R + r)]);
+    }
+    if (lo > hi) lo = hi = 0;
+    if (int64_t(hi) - lo >= 65536) c16 = false;
+    base[size_t(k)] = lo;
+  }
+  D.nt = stream_nt(int64_t(T.col.size()) * ((c16 ? 2 : 4) + (w8 ? 1 : exact ? 4 : 8)));
   int rc;
-  int32_t *sp, *cl;
+  int32_t* sp;
   if ((rc = upload(h, &sp, T.sptr, s))) return rc;
-  if ((rc = upload(h, &cl, T.col, s))) return rc;
   D.sptr = sp;
-  D.col = cl;
-  if (exact) {
+  if (c16) {
+    std::vector<uint16_t> off(T.col.size());
+    for (int64_t k = 0; k < slots; ++k)
+      for (int r = 0; r < T.R; ++r) {
+        const size_t e = size_t(k * T.R + r);
+        off[e] = T.empty[e] ? uint16_t(0) : uint16_t(T.col[e] - base[size_t(k)]);
+      }
+    uint16_t* o;
+    int32_t* b;
+    if ((rc = upload(h, &o, off, s)) || (rc = upload(h, &b, base, s))) return rc;
+    MG_HIP(hipStreamSynchronize(s));
+    D.col16 = o;
+    D.colbase = b;
+  } else {
+    int32_t* cl;
+    if ((rc = upload(h, &cl, T.col, s))) return rc;
+    D.col = cl;
+  }
+  if (w8) {
+    std::vector<uint8_t> code(T.w.size());
+    for (size_t i = 0; i < T.w.size(); ++i) code[i] = uint8_t(T.w[i] * 128.0);
+    uint8_t* v;
+    if ((rc = upload(h, &v, code, s))) return rc;
+    MG_HIP(hipStreamSynchronize(s));
+    D.w = v;
+    D.w8 = 1;
+  } else if (exact) {
     std::vector<float> f(T.w.begin(), T.w.end());
     float* v;
     if ((rc = upload(h, &v, f, s))) return rc;
@@ -1054,8 +1110,11 @@ int load_hierarchy(const mg_level_in* lv, int n_levels, bool on_dev, std::vector
 
 // one level on the device: FP64 and cycle operators (sliced ELL for NR right-hand sides),
 // smoother blocks, mask, P~ and R = P~^T; with vectors = true also x, b, r, t
+// single: a single-problem handle (keeps the host pattern for the step-wise entry points
+// and stores its transfers in the compact form); the batch reads the plain form
 int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, int xk, bool vectors, int* flag,
-                hipStream_t s, LevelDev& D, bool keep_host = false) {
+                hipStream_t s, LevelDev& D, bool single = false) {
+  const bool keep_host = single;
   int rc;
   D.n = L.n;
   D.B = L.B;
@@ -1108,8 +1167,8 @@ int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, 
     if ((rc = upload_csr(h, P, D.P, s))) return rc;
     CsrHost R = transpose(L.n, L.pc, L.prow, L.pcol, L.pval);
     if ((rc = upload_csr(h, R, D.R, s))) return rc;
-    if ((rc = upload_tsell(h, build_tsell(P, L.B, NR), D.Ps, s))) return rc;
-    if ((rc = upload_tsell(h, build_tsell(R, L.B, NR), D.Rs, s))) return rc;
+    if ((rc = upload_tsell(h, build_tsell(P, L.B, NR), D.Ps, s, single && NR == 1))) return rc;
+    if ((rc = upload_tsell(h, build_tsell(R, L.B, NR), D.Rs, s, single && NR == 1))) return rc;
   }
   if (vectors) {
     const size_t vb = size_t(D.N) * NR * xsize(xk);
@@ -2553,6 +2612,17 @@ int mg_level_tuning(const mg_handle* h, int32_t level, int32_t* slot_batch, int3
   if (col_bytes) *col_bytes = L.A64.col16 ? 2 : 4;
   if (us_default) *us_default = L.us_def;
   if (us_other) *us_other = L.us_alt;
+  return MG_OK;
+}
+
+int mg_level_transfer_format(const mg_handle* h, int32_t level, int32_t* p_col_bytes, int32_t* r_col_bytes,
+                             int32_t* weight_bytes) {
+  if (!h || level < 1 || level > h->L) return fail(MG_EINVAL, "bad handle or level (transfers exist on levels >= 1)");
+  const TSellDev& P = h->lv[level].Ps;
+  const TSellDev& R = h->lv[level].Rs;
+  if (p_col_bytes) *p_col_bytes = P.col16 ? 2 : 4;
+  if (r_col_bytes) *r_col_bytes = R.col16 ? 2 : 4;
+  if (weight_bytes) *weight_bytes = P.w8 ? 1 : P.f32 ? 4 : 8;
   return MG_OK;
 }
 

@@ -75,7 +75,7 @@ SYMBOLS = ["mg_setup_hierarchy", "mg_vcycle", "mg_solve", "mg_solve_fixed", "mg_
            "mg_time_theta", "mg_time_run", "mg_time_destroy", "mg_outer_defect_noalloc",
            "mg_level_smooth", "mg_level_eigen_estimate", "mg_ns_setup", "mg_ns_momentum", "mg_ns_divergence",
            "mg_ns_pressure_update", "mg_ns_run", "mg_ns_destroy", "mg_asm_setup", "mg_asm_values",
-           "mg_asm_destroy"]
+           "mg_asm_destroy", "mg_level_transfer_format"]
 
 
 def lib():
@@ -102,6 +102,7 @@ def lib():
         L.mg_level_info.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_int64)]
         L.mg_level_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]
+        L.mg_level_transfer_format.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.mg_num_levels.argtypes = [vp]
         L.mg_num_levels.restype = i32
         L.mg_validate_level.argtypes = [C.POINTER(LevelIn), C.POINTER(LevelIn)]
@@ -258,6 +259,12 @@ class Hierarchy:
         cb = C.c_int32()
         _check(lib().mg_level_tuning(self.h, l, None, C.byref(cb), None, None))
         return cb.value
+
+    def transfer_format(self, l):
+        """(bytes per column index of P~, of R, bytes per weight) between levels l-1 and l."""
+        pc, rc, wb = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().mg_level_transfer_format(self.h, l, C.byref(pc), C.byref(rc), C.byref(wb)))
+        return pc.value, rc.value, wb.value
 
     def ndof(self, l=-1):
         n, b, _ = self.sizes[l]

@@ -143,3 +143,19 @@ def test_invalid_setup_refused():
     hp2 = mg.Hierarchy(gen.build_ns((8, 8, 16), n_levels=2).levels, mg.config_from(pressure_wl()))
     with pytest.raises(mg.MGError):
         mg.PressureCorrection(other, hp2, NU, DT)
+
+
+def test_zero_steps_and_aliasing():
+    """An empty run leaves u, p, q unchanged; an output aliasing its input is refused."""
+    from paper_2405_05047_amd import mg
+    ops, H, mgo, prob, hp, pc = _pair((4, 4, 8), 3)
+    u0 = W.rand_vec(41, ops.n_v * 3)
+    u = dev(u0)
+    p = dev(W.rand_vec(42, ops.n_p))
+    q = dev(W.rand_vec(43, ops.n_p))
+    assert pc.run(0, u, p, q) == []
+    assert np.array_equal(host(u), u0)
+    with pytest.raises(mg.MGError):
+        pc.momentum(u, p, q, u)
+    with pytest.raises(mg.MGError):
+        pc.divergence(u, p, p)

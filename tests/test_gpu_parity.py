@@ -398,6 +398,46 @@ def test_mixed_column_format_bitwise_equal(name, prec, monkeypatch):
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
 
 
+@pytest.mark.parametrize("name", ["poisson33", "td_band", "elast17", "oseen17", "edge4", "oseen_tall"])
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_compact_transfers_bitwise_equal(name, prec, monkeypatch):
+    """Transfers stored with 16-bit column offsets and 8-bit weight codes (w = code / 128,
+    the dyadic weights of nested box meshes) give bitwise the restriction, prolongation,
+    V-cycle and solve of 32-bit columns with FP32/FP64 weights: the codes decode exactly
+    and every row keeps its slot order."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    outs = []
+    for plain in ("0", "1"):
+        monkeypatch.setenv("MGQ1_PLAIN_TRANSFERS", plain)
+        h = mg.Hierarchy(p.levels, mg.config_from(wl, precision=prec))
+        fmt = [h.transfer_format(l) for l in range(1, h.n_levels)]
+        if plain == "1":
+            assert all(f[0] == 4 and f[1] == 4 and f[2] in (4, 8) for f in fmt), fmt
+        else:
+            assert fmt[-1] == (2, 2, 1), fmt
+            compact = fmt
+        steps = []
+        if prec == "fp64":
+            for l in range(1, h.n_levels):
+                f, c = o.levels[l], o.levels[l - 1]
+                d = torch.zeros(c.ndof, dtype=torch.float64, device="cuda")
+                h.restrict(l, dev(_rand(900 + l, f.ndof)), d)
+                xt = dev(_rand(950 + l, f.ndof))
+                h.prolong(l, dev(_rand(990 + l, c.ndof)), xt)
+                steps += [host(d), host(xt)]
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        h.vcycle(dev(o.b), x)
+        vc = host(x)
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        st = h.solve(dev(o.b), x)
+        outs.append((steps, vc, host(x), st["iters"]))
+    (s0, v0, x0, i0), (s1, v1, x1, i1) = outs
+    assert all(np.array_equal(a, b) for a, b in zip(s0, s1))
+    assert np.array_equal(v0, v1) and np.array_equal(x0, x1) and i0 == i1
+    _log(name, prec, "compact transfers bitwise equal; formats", compact)
+
+
 @pytest.mark.parametrize("name", ["td_band", "elast17"])
 @pytest.mark.parametrize("prec", ["fp64", "fp16"])
 def test_load_kinds_bitwise_equal(name, prec, monkeypatch):

@@ -158,3 +158,16 @@ def test_invalid_time_setup_refused():
     bad = p.time.__class__(**{**p.time.__dict__, "R_col": col})
     with pytest.raises(mg.MGError):
         mg.TimeStepper(h, bad, wl.dt)
+
+
+def test_zero_steps_leave_the_state_unchanged():
+    """An empty run is a no-op: theta and x keep their values, no statistics."""
+    p, h, ts = _setup(W.td_time(4))
+    N = p.time.n_dofs
+    th0 = W.rand_vec(31, N)
+    th = dev(th0)
+    x = dev(np.zeros(N))
+    F = torch.empty((0, N), dtype=torch.float64, device="cuda")
+    G = torch.empty((0, p.time.n_g), dtype=torch.float64, device="cuda")
+    assert ts.run(th, F, G, x) == []
+    assert np.array_equal(host(th), th0) and not host(x).any()
