@@ -440,14 +440,7 @@ __device__ __forceinline__ void prolong_dof(const CsrDev& P, const X* __restrict
 // ---- sliced transfers: NB slots of one node row, loads first (straight-line), then the
 // weighted sum in slot order.  MC: apply the column mask (entries whose column DoF is
 // masked contribute 0).
-// weight of a transfer slot: float / double as stored, or an 8-bit code w = code / 128
-template <class WT>
-__device__ __forceinline__ auto tsell_weight(WT w) {
-  if constexpr (sizeof(WT) == 1) return float(w) * 0.0078125f;
-  else return w;
-}
-
-template <int NB, int B, int NR, class X, class T, class WT, bool MC, bool NT, bool C16>
+template <int NB, int B, int NR, class X, class T, class WT, bool MC, bool NT>
 __device__ __forceinline__ void tsell_batch(const TSellDev& M, int k, int r, int c, int q,
                                             const X* __restrict__ in, const uint8_t* __restrict__ mcol,
                                             T& acc) {
@@ -458,8 +451,7 @@ __device__ __forceinline__ void tsell_batch(const TSellDev& M, int k, int r, int
   uint8_t ms[NB];
 #pragma unroll
   for (int qq = 0; qq < NB; ++qq) {
-    if constexpr (C16) js[qq] = unsigned(M.colbase[k + qq]) + unsigned(stream_load<NT>(M.col16 + int64_t(k + qq) * R + r));
-    else js[qq] = unsigned(stream_load<NT>(M.col + int64_t(k + qq) * R + r));
+    js[qq] = unsigned(stream_load<NT>(M.col + int64_t(k + qq) * R + r));
     ws[qq] = stream_load<NT>(static_cast<const WT*>(M.w) + int64_t(k + qq) * R + r);
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -471,21 +463,21 @@ __device__ __forceinline__ void tsell_batch(const TSellDev& M, int k, int r, int
   }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int qq = 0; qq < NB; ++qq) acc += T(tsell_weight(ws[qq])) * (ms[qq] ? T(0) : T(vs[qq]));
+  for (int qq = 0; qq < NB; ++qq) acc += T(ws[qq]) * (ms[qq] ? T(0) : T(vs[qq]));
 }
 
-template <int N, int B, int NR, class X, class T, class WT, bool MC, bool NT, bool C16>
+template <int N, int B, int NR, class X, class T, class WT, bool MC, bool NT>
 __device__ __forceinline__ void tsell_rest(int rem, const TSellDev& M, int k, int r, int c, int q,
                                            const X* __restrict__ in, const uint8_t* __restrict__ mcol, T& acc) {
   if constexpr (N >= 1) {
-    if (rem == N) tsell_batch<N, B, NR, X, T, WT, MC, NT, C16>(M, k, r, c, q, in, mcol, acc);
-    else tsell_rest<N - 1, B, NR, X, T, WT, MC, NT, C16>(rem, M, k, r, c, q, in, mcol, acc);
+    if (rem == N) tsell_batch<N, B, NR, X, T, WT, MC, NT>(M, k, r, c, q, in, mcol, acc);
+    else tsell_rest<N - 1, B, NR, X, T, WT, MC, NT>(rem, M, k, r, c, q, in, mcol, acc);
   }
 }
 
 // one lane of a sliced transfer.  MODE 0: out = restriction sum (zero on masked rows);
 // MODE 1: out += prolongation sum (rows whose DoF is masked are left unchanged)
-template <int B, int NR, class X, class T, class WT, bool MC, int MODE, bool C16 = false>
+template <int B, int NR, class X, class T, class WT, bool MC, int MODE>
 __device__ __forceinline__ void tsell_lane(const TSellDev& M, int slice, int lane, const X* __restrict__ in,
                                            X* __restrict__ out, const uint8_t* __restrict__ mrow,
                                            const uint8_t* __restrict__ mcol) {
@@ -507,23 +499,107 @@ __device__ __forceinline__ void tsell_lane(const TSellDev& M, int slice, int lan
   slot_range(M, su, k, k1);
   T acc = T(0);
   if (M.nt) {
-    for (; k + KB <= k1; k += KB) tsell_batch<KB, B, NR, X, T, WT, MC, true, C16>(M, k, r, c, q, in, mcol, acc);
-    tsell_rest<KB - 1, B, NR, X, T, WT, MC, true, C16>(k1 - k, M, k, r, c, q, in, mcol, acc);
+    for (; k + KB <= k1; k += KB) tsell_batch<KB, B, NR, X, T, WT, MC, true>(M, k, r, c, q, in, mcol, acc);
+    tsell_rest<KB - 1, B, NR, X, T, WT, MC, true>(k1 - k, M, k, r, c, q, in, mcol, acc);
   } else {
-    for (; k + KB <= k1; k += KB) tsell_batch<KB, B, NR, X, T, WT, MC, false, C16>(M, k, r, c, q, in, mcol, acc);
-    tsell_rest<KB - 1, B, NR, X, T, WT, MC, false, C16>(k1 - k, M, k, r, c, q, in, mcol, acc);
+    for (; k + KB <= k1; k += KB) tsell_batch<KB, B, NR, X, T, WT, MC, false>(M, k, r, c, q, in, mcol, acc);
+    tsell_rest<KB - 1, B, NR, X, T, WT, MC, false>(k1 - k, M, k, r, c, q, in, mcol, acc);
   }
   if (MODE == 0) out[t] = masked ? X(0) : X(acc);
   else if (!masked) out[t] = X(T(old) + acc);
 }
 
-template <int B, int NR, class X, class T, class WT, bool MC, int MODE, bool C16>
+template <int B, int NR, class X, class T, class WT, bool MC, int MODE>
 __global__ __launch_bounds__(kThreads) void k_tsell(TSellDev M, const X* __restrict__ in, X* __restrict__ out,
                                                     const uint8_t* __restrict__ mrow,
                                                     const uint8_t* __restrict__ mcol) {
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  tsell_lane<B, NR, X, T, WT, MC, MODE, C16>(M, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave, in,
-                                             out, mrow, mcol);
+  tsell_lane<B, NR, X, T, WT, MC, MODE>(M, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave, in, out,
+                                        mrow, mcol);
+}
+
+// ---- node form of the sliced transfers: one lane per node computes its B components.  Per
+// slot one packed 32-bit entry (16-bit column offset, 8-bit weight code w * 128, the column
+// DoFs' mask bits) and B gathers of the column node's vector; the FMAs run in slot order
+// with the same operands as the per-DoF form, so the sums are the same bit for bit.  A
+// wave issues one entry load per slot for 64 nodes where the per-DoF form issues an index,
+// a weight and a mask load per slot for 64 / B nodes.
+template <int NB, int B, class X, class T, bool MC>
+__device__ __forceinline__ void tnode_batch(const TSellDev& M, int k, int lane, const X* __restrict__ in,
+                                            T (&acc)[B]) {
+  uint32_t e[NB];
+  int32_t base[NB];
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) {
+    e[qq] = M.ent[int64_t(k + qq) * kWave + lane];
+    base[qq] = M.colbase[k + qq];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  X v[NB][B];
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) {
+    const uint64_t j = uint64_t(uint32_t(base[qq]) + (e[qq] & 0xffffu));
+#pragma unroll
+    for (int c = 0; c < B; ++c) v[qq][c] = in[j * B + c];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int qq = 0; qq < NB; ++qq) {
+    const T w = T(float((e[qq] >> 16) & 0xffu) * 0.0078125f);
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      const bool ms = MC && ((e[qq] >> (24 + c)) & 1u);
+      acc[c] += w * (ms ? T(0) : T(v[qq][c]));
+    }
+  }
+}
+
+template <int N, int B, class X, class T, bool MC>
+__device__ __forceinline__ void tnode_rest(int rem, const TSellDev& M, int k, int lane, const X* __restrict__ in,
+                                           T (&acc)[B]) {
+  if constexpr (N >= 1) {
+    if (rem == N) tnode_batch<N, B, X, T, MC>(M, k, lane, in, acc);
+    else tnode_rest<N - 1, B, X, T, MC>(rem, M, k, lane, in, acc);
+  }
+}
+
+// MODE 0: out = restriction sum (zero on masked row DoFs); MODE 1: out += prolongation sum
+// (masked row DoFs left unchanged)
+template <int B, class X, class T, bool MC, int MODE>
+__device__ __forceinline__ void tnode_lane(const TSellDev& M, int slice, int lane, const X* __restrict__ in,
+                                           X* __restrict__ out) {
+  // slot batch: restriction rows hold up to 3^d entries (27 on 3D box meshes), prolongation
+  // rows at most 2^d; a batch is one dependent round trip (entries, then gathers)
+  constexpr int KB = MODE == 0 ? 8 : 4;
+  const int node = slice * kWave + lane;
+  if (slice >= M.nslices || node >= M.nrows) return;
+  const int64_t d0 = int64_t(node) * B;
+  const uint8_t rm = M.rmask[node];
+  X old[B];
+  if (MODE == 1) {
+#pragma unroll
+    for (int c = 0; c < B; ++c) old[c] = out[d0 + c];
+  }
+  const int su = __builtin_amdgcn_readfirstlane(slice);
+  int k, k1;
+  slot_range(M, su, k, k1);
+  T acc[B];
+#pragma unroll
+  for (int c = 0; c < B; ++c) acc[c] = T(0);
+  for (; k + KB <= k1; k += KB) tnode_batch<KB, B, X, T, MC>(M, k, lane, in, acc);
+  tnode_rest<KB - 1, B, X, T, MC>(k1 - k, M, k, lane, in, acc);
+#pragma unroll
+  for (int c = 0; c < B; ++c) {
+    const bool masked = (rm >> c) & 1u;
+    if (MODE == 0) out[d0 + c] = masked ? X(0) : X(acc[c]);
+    else if (!masked) out[d0 + c] = X(T(old[c]) + acc[c]);
+  }
+}
+
+template <int B, class X, class T, bool MC, int MODE>
+__global__ __launch_bounds__(kThreads) void k_tnode(TSellDev M, const X* __restrict__ in, X* __restrict__ out) {
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  tnode_lane<B, X, T, MC, MODE>(M, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave, in, out);
 }
 
 inline unsigned grid_for(int64_t n, int threads) { return unsigned((n + threads - 1) / threads); }

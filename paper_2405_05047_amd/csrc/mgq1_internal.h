@@ -68,11 +68,14 @@ struct TSellDev {
   const int32_t* col = nullptr;
   const void* w = nullptr;
   int f32 = 1;
-  // compact form (single right-hand side): 16-bit column offsets from a per-slot base
-  // (col16[k * R + r] + colbase[k]; NULL: col) and weights as 8-bit codes w = code / 128
-  const uint16_t* col16 = nullptr;
+  // node form (single right-hand side, dyadic weights): slices of R = 64 nodes, one lane per
+  // node computing its B components; per slot entry ent[k * 64 + r] = column offset from
+  // colbase[k] | weight code (w * 128) << 16 | mask bits of the column's B DoFs << 24, and
+  // rmask[node] = mask bits of the row's B DoFs
+  int node = 0;
+  const uint32_t* ent = nullptr;
   const int32_t* colbase = nullptr;
-  int w8 = 0;
+  const uint8_t* rmask = nullptr;
 };
 
 // d = M_c P~^T M_f r (rows = coarse nodes; mask_f may be NULL) and x += M_f P~ M_c y

@@ -757,44 +757,66 @@ hipError_t launch_sweep0(const SellDev& A, const void* S, const void* b, void* x
 }
 
 namespace {
-template <int B, class X, class T, class WT, bool C16>
-hipError_t tsell_wc(int mode, const TSellDev& M, const void* in, void* out, const uint8_t* mrow,
-                    const uint8_t* mcol, hipStream_t s) {
+template <int B, class X, class T, class WT>
+hipError_t tsell_w(int mode, const TSellDev& M, const void* in, void* out, const uint8_t* mrow,
+                   const uint8_t* mcol, hipStream_t s) {
   const unsigned g = slice_grid(M.nslices);
   if (g == 0) return hipSuccess;
   const X* ii = static_cast<const X*>(in);
   X* oo = static_cast<X*>(out);
   if (mode == 0) {
-    if (mcol) hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, true, 0, C16>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
-    else hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, false, 0, C16>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
+    if (mcol) hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, true, 0>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
+    else hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, false, 0>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
   } else {
-    hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, true, 1, C16>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
+    hipLaunchKernelGGL((k_tsell<B, 1, X, T, WT, true, 1>), g, kThreads, 0, s, M, ii, oo, mrow, mcol);
   }
   return hipGetLastError();
-}
-
-template <int B, class X, class T, class WT>
-hipError_t tsell_w(int mode, const TSellDev& M, const void* in, void* out, const uint8_t* mrow,
-                   const uint8_t* mcol, hipStream_t s) {
-  if (M.col16) return tsell_wc<B, X, T, WT, true>(mode, M, in, out, mrow, mcol, s);
-  return tsell_wc<B, X, T, WT, false>(mode, M, in, out, mrow, mcol, s);
 }
 
 template <int B>
 hipError_t tsell_b(int mode, const TSellDev& M, const void* in, void* out, const uint8_t* mrow,
                    const uint8_t* mcol, int xk, hipStream_t s) {
-  if (xk == X_F64) {
-    if (M.w8) return tsell_w<B, double, double, uint8_t>(mode, M, in, out, mrow, mcol, s);
+  if (xk == X_F64)
     return M.f32 ? tsell_w<B, double, double, float>(mode, M, in, out, mrow, mcol, s)
                  : tsell_w<B, double, double, double>(mode, M, in, out, mrow, mcol, s);
-  }
-  if (M.w8) return tsell_w<B, float, float, uint8_t>(mode, M, in, out, mrow, mcol, s);
   return M.f32 ? tsell_w<B, float, float, float>(mode, M, in, out, mrow, mcol, s)
                : tsell_w<B, float, float, double>(mode, M, in, out, mrow, mcol, s);
 }
 
+template <int B, class X>
+hipError_t tnode_x(int mode, const TSellDev& M, const void* in, void* out, bool mc, hipStream_t s) {
+  const unsigned g = slice_grid(M.nslices);
+  if (g == 0) return hipSuccess;
+  const X* ii = static_cast<const X*>(in);
+  X* oo = static_cast<X*>(out);
+  if (mode == 1) hipLaunchKernelGGL((k_tnode<B, X, X, true, 1>), g, kThreads, 0, s, M, ii, oo);
+  else if (mc) hipLaunchKernelGGL((k_tnode<B, X, X, true, 0>), g, kThreads, 0, s, M, ii, oo);
+  else hipLaunchKernelGGL((k_tnode<B, X, X, false, 0>), g, kThreads, 0, s, M, ii, oo);
+  return hipGetLastError();
+}
+
+template <int B>
+hipError_t tnode_b(int mode, const TSellDev& M, const void* in, void* out, bool mc, int xk, hipStream_t s) {
+  return xk == X_F64 ? tnode_x<B, double>(mode, M, in, out, mc, s) : tnode_x<B, float>(mode, M, in, out, mc, s);
+}
+
+// node form: the row and column masks are the ones built into the layout (the levels' own
+// masks); mcol only says whether the column mask applies
+hipError_t tnode_launch(int mode, const TSellDev& M, int B, const void* in, void* out, const uint8_t* mcol, int xk,
+                        hipStream_t s) {
+  if (M.R != kWave) return hipErrorInvalidValue;
+  switch (B) {
+    case 1: return tnode_b<1>(mode, M, in, out, mcol != nullptr, xk, s);
+    case 2: return tnode_b<2>(mode, M, in, out, mcol != nullptr, xk, s);
+    case 3: return tnode_b<3>(mode, M, in, out, mcol != nullptr, xk, s);
+    case 4: return tnode_b<4>(mode, M, in, out, mcol != nullptr, xk, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t tsell_launch(int mode, const TSellDev& M, int B, const void* in, void* out, const uint8_t* mrow,
                         const uint8_t* mcol, int xk, hipStream_t s) {
+  if (M.node) return tnode_launch(mode, M, B, in, out, mcol, xk, s);
   if (M.R != kWave / B) return hipErrorInvalidValue;     // single right-hand-side layout
   switch (B) {
     case 1: return tsell_b<1>(mode, M, in, out, mrow, mcol, xk, s);

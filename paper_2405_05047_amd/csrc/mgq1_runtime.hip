@@ -636,14 +636,7 @@ int upload_csr(DevOwner* h, const CsrHost& C, CsrDev& D, hipStream_t s) {
   return MG_OK;
 }
 
-// compact: allow 16-bit column offsets (every slot's columns span less than 2^16) and
-// 8-bit weight codes (every weight is code / 128, code <= 255: the dyadic transfer weights
-// of box meshes); used for single-right-hand-side transfers, the batch keeps the plain form.
-// Either form gives the same bits (the codes decode exactly, the slot order is unchanged);
-// MGQ1_PLAIN_TRANSFERS=1 keeps the plain form everywhere (tests).
-int upload_tsell(DevOwner* h, const TSellHost& T, TSellDev& D, hipStream_t s, bool compact = false) {
-  const char* plain = std::getenv("MGQ1_PLAIN_TRANSFERS");
-  if (plain && std::atoi(plain) != 0) compact = false;
+int upload_tsell(DevOwner* h, const TSellHost& T, TSellDev& D, hipStream_t s) {
   D.nrows = T.nrows;
   D.ncols = T.ncols;
   D.R = T.R;
@@ -652,59 +645,14 @@ int upload_tsell(DevOwner* h, const TSellHost& T, TSellDev& D, hipStream_t s, bo
   bool exact = true;
   for (double w : T.w) exact = exact && (double(float(w)) == w);
   D.f32 = exact;
-  bool w8 = compact, c16 = compact;
-  for (double w : T.w) {
-    const double cd = w * 128.0;
-    w8 = w8 && cd >= 0.0 && cd <= 255.0 && cd == std::floor(cd);
-  }
-  // the span of a slot counts the lanes of non-empty rows only: an empty row (a Dirichlet
-  // node's row of P~) adds 0 * in[c] to +0 whatever its column c, so its lanes read the
-  // slot's base column in the compact form (the same bits)
-  const int64_t slots = int64_t(T.col.size()) / T.R;
-  std::vector<int32_t> base(size_t(std::max<int64_t>(slots, 1)), 0);
-  for (int64_t k = 0; c16 && k < slots; ++k) {
-    int32_t lo = INT32_MAX, hi = INT32_MIN;
-    for (int r = 0; r < T.R; ++r) {
-      if (T.empty[size_t(k * T.R + r)]) continue;
-      lo = std::min(lo, T.col[size_t(k * T.R + r)]);
-      hi = std::max(hi, T.col[size_t(k * T.R + r)]);
-    }
-    if (lo > hi) lo = hi = 0;
-    if (int64_t(hi) - lo >= 65536) c16 = false;
-    base[size_t(k)] = lo;
-  }
-  D.nt = stream_nt(int64_t(T.col.size()) * ((c16 ? 2 : 4) + (w8 ? 1 : exact ? 4 : 8)));
+  D.nt = stream_nt(int64_t(T.col.size()) * (4 + (exact ? 4 : 8)));
   int rc;
-  int32_t* sp;
+  int32_t *sp, *cl;
   if ((rc = upload(h, &sp, T.sptr, s))) return rc;
+  if ((rc = upload(h, &cl, T.col, s))) return rc;
   D.sptr = sp;
-  if (c16) {
-    std::vector<uint16_t> off(T.col.size());
-    for (int64_t k = 0; k < slots; ++k)
-      for (int r = 0; r < T.R; ++r) {
-        const size_t e = size_t(k * T.R + r);
-        off[e] = T.empty[e] ? uint16_t(0) : uint16_t(T.col[e] - base[size_t(k)]);
-      }
-    uint16_t* o;
-    int32_t* b;
-    if ((rc = upload(h, &o, off, s)) || (rc = upload(h, &b, base, s))) return rc;
-    MG_HIP(hipStreamSynchronize(s));
-    D.col16 = o;
-    D.colbase = b;
-  } else {
-    int32_t* cl;
-    if ((rc = upload(h, &cl, T.col, s))) return rc;
-    D.col = cl;
-  }
-  if (w8) {
-    std::vector<uint8_t> code(T.w.size());
-    for (size_t i = 0; i < T.w.size(); ++i) code[i] = uint8_t(T.w[i] * 128.0);
-    uint8_t* v;
-    if ((rc = upload(h, &v, code, s))) return rc;
-    MG_HIP(hipStreamSynchronize(s));
-    D.w = v;
-    D.w8 = 1;
-  } else if (exact) {
+  D.col = cl;
+  if (exact) {
     std::vector<float> f(T.w.begin(), T.w.end());
     float* v;
     if ((rc = upload(h, &v, f, s))) return rc;
@@ -716,6 +664,77 @@ int upload_tsell(DevOwner* h, const TSellHost& T, TSellDev& D, hipStream_t s, bo
     MG_HIP(hipStreamSynchronize(s));
     D.w = v;
   }
+  return MG_OK;
+}
+
+// Node form of a single-right-hand-side transfer C (rows x cols nodes, block size B): slices
+// of 64 nodes, one packed 32-bit entry per slot and lane.  Applies when every weight is a
+// multiple of 1/128 up to 255/128 (the weights of nested box meshes, with their hanging-node
+// products) and every slot's columns span less than 2^16; *applied tells whether it did (else
+// the caller stores the per-DoF form).  The span counts the lanes of non-empty rows only: an
+// empty row (a Dirichlet node's row of P~) and a lane past the last row add 0 * in[j] to +0
+// whatever j, so they read the slot's base column.  Padding slots of a row keep its last
+// column and weight 0, as in the per-DoF form, so every sum is the same bit for bit.
+// MGQ1_PLAIN_TRANSFERS=1 keeps the per-DoF form everywhere (tests).
+int upload_tnode(DevOwner* h, const CsrHost& C, int B, const std::vector<uint8_t>& row_mask,
+                 const std::vector<uint8_t>& col_mask, TSellDev& D, hipStream_t s, bool* applied) {
+  *applied = false;
+  const char* plain = std::getenv("MGQ1_PLAIN_TRANSFERS");
+  if ((plain && std::atoi(plain) != 0) || B < 1 || B > 8) return MG_OK;
+  if (row_mask.size() != size_t(C.nrows) * B || col_mask.size() != size_t(C.ncols) * B) return MG_OK;
+  for (double w : C.val) {
+    const double cd = w * 128.0;
+    if (!(cd >= 0.0 && cd <= 255.0 && cd == std::floor(cd))) return MG_OK;
+  }
+  const TSellHost T = build_tsell(C, 1, 1);            // 64 node rows per slice
+  const int64_t slots = int64_t(T.col.size()) / T.R;
+  std::vector<int32_t> base(size_t(std::max<int64_t>(slots, 1)), 0);
+  for (int64_t k = 0; k < slots; ++k) {
+    int32_t lo = INT32_MAX, hi = INT32_MIN;
+    for (int r = 0; r < T.R; ++r) {
+      const size_t e = size_t(k * T.R + r);
+      if (T.empty[e]) continue;
+      lo = std::min(lo, T.col[e]);
+      hi = std::max(hi, T.col[e]);
+    }
+    if (lo > hi) lo = hi = 0;
+    if (int64_t(hi) - lo >= 65536) return MG_OK;
+    base[size_t(k)] = lo;
+  }
+  std::vector<uint32_t> ent(T.col.size(), 0u);
+  for (int64_t k = 0; k < slots; ++k)
+    for (int r = 0; r < T.R; ++r) {
+      const size_t e = size_t(k * T.R + r);
+      const int32_t j = T.empty[e] ? base[size_t(k)] : T.col[e];
+      uint32_t v = uint32_t(j - base[size_t(k)]) | (uint32_t(T.w[e] * 128.0) << 16);
+      for (int c = 0; c < B; ++c)
+        if (col_mask[size_t(j) * B + c]) v |= 1u << (24 + c);
+      ent[e] = v;
+    }
+  std::vector<uint8_t> rm(size_t(C.nrows), 0);
+  for (int64_t i = 0; i < C.nrows; ++i)
+    for (int c = 0; c < B; ++c)
+      if (row_mask[size_t(i) * B + c]) rm[size_t(i)] |= uint8_t(1u << c);
+  int rc;
+  int32_t *sp, *cb;
+  uint32_t* en;
+  uint8_t* rmd;
+  if ((rc = upload(h, &sp, T.sptr, s)) || (rc = upload(h, &cb, base, s)) || (rc = upload(h, &en, ent, s)) ||
+      (rc = upload(h, &rmd, rm, s)))
+    return rc;
+  MG_HIP(hipStreamSynchronize(s));
+  D = TSellDev();
+  D.nrows = T.nrows;
+  D.ncols = T.ncols;
+  D.R = T.R;
+  D.nslices = T.nslices;
+  D.ell = T.ell;
+  D.sptr = sp;
+  D.node = 1;
+  D.ent = en;
+  D.colbase = cb;
+  D.rmask = rmd;
+  *applied = true;
   return MG_OK;
 }
 
@@ -1113,7 +1132,7 @@ int load_hierarchy(const mg_level_in* lv, int n_levels, bool on_dev, std::vector
 // single: a single-problem handle (keeps the host pattern for the step-wise entry points
 // and stores its transfers in the compact form); the batch reads the plain form
 int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, int xk, bool vectors, int* flag,
-                hipStream_t s, LevelDev& D, bool single = false) {
+                hipStream_t s, LevelDev& D, bool single = false, const HostLevel* coarser = nullptr) {
   const bool keep_host = single;
   int rc;
   D.n = L.n;
@@ -1167,8 +1186,13 @@ int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, 
     if ((rc = upload_csr(h, P, D.P, s))) return rc;
     CsrHost R = transpose(L.n, L.pc, L.prow, L.pcol, L.pval);
     if ((rc = upload_csr(h, R, D.R, s))) return rc;
-    if ((rc = upload_tsell(h, build_tsell(P, L.B, NR), D.Ps, s, single && NR == 1))) return rc;
-    if ((rc = upload_tsell(h, build_tsell(R, L.B, NR), D.Rs, s, single && NR == 1))) return rc;
+    bool pn = false, rn = false;
+    if (single && NR == 1 && coarser) {
+      if ((rc = upload_tnode(h, P, L.B, L.mask, coarser->mask, D.Ps, s, &pn))) return rc;
+      if ((rc = upload_tnode(h, R, L.B, coarser->mask, L.mask, D.Rs, s, &rn))) return rc;
+    }
+    if (!pn && (rc = upload_tsell(h, build_tsell(P, L.B, NR), D.Ps, s))) return rc;
+    if (!rn && (rc = upload_tsell(h, build_tsell(R, L.B, NR), D.Rs, s))) return rc;
   }
   if (vectors) {
     const size_t vb = size_t(D.N) * NR * xsize(xk);
@@ -1306,7 +1330,9 @@ int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
   MG_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
   const int vkind = value_kind(c.precision);
   for (int l = 0; l < n_levels; ++l)
-    if ((rc = setup_level(h, H[l], l > 0, 1, vkind, h->xk, true, flag, s, h->lv[l], true))) return rc;
+    if ((rc = setup_level(h, H[l], l > 0, 1, vkind, h->xk, true, flag, s, h->lv[l], true,
+                          l > 0 ? &H[l - 1] : nullptr)))
+      return rc;
   if ((rc = setup_coarse_inverse(h, H[0], flag, s, &h->Ainv, &h->n0))) return rc;
   if ((rc = check_flag(flag, s))) return rc;
   // outer-loop storage
@@ -2620,9 +2646,9 @@ int mg_level_transfer_format(const mg_handle* h, int32_t level, int32_t* p_col_b
   if (!h || level < 1 || level > h->L) return fail(MG_EINVAL, "bad handle or level (transfers exist on levels >= 1)");
   const TSellDev& P = h->lv[level].Ps;
   const TSellDev& R = h->lv[level].Rs;
-  if (p_col_bytes) *p_col_bytes = P.col16 ? 2 : 4;
-  if (r_col_bytes) *r_col_bytes = R.col16 ? 2 : 4;
-  if (weight_bytes) *weight_bytes = P.w8 ? 1 : P.f32 ? 4 : 8;
+  if (p_col_bytes) *p_col_bytes = P.node ? 2 : 4;
+  if (r_col_bytes) *r_col_bytes = R.node ? 2 : 4;
+  if (weight_bytes) *weight_bytes = P.node ? 1 : P.f32 ? 4 : 8;
   return MG_OK;
 }
 
