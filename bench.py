@@ -39,18 +39,22 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "c2": (lambda: W.c2_td().with_(coarse_level=3),
            "2D transport-diffusion eps=1e-3 b=(1,0.5) SUPG Q1, annulus-refined adaptive mesh (hanging "
-           "nodes), 1,010,113 DoFs, 9-level hierarchy with the exact coarse solve on level 3 (1,749 DoFs), "
+           "nodes), 1,010,113 DoFs, levels 3-8 of the 9-level hierarchy (6 in the cycle) with the exact "
+           "coarse solve on level 3 (1,749 DoFs), "
            "FGMRES(10) + V(2,2) damped Jacobi w=0.8, rtol 1e-8"),
     "c1": (lambda: W.c1_poisson(), "2D Poisson Q1 33x33 nodes, 5 levels, MG iteration V(2,2) w=0.8, rtol 1e-10"),
     "c3": (lambda: W.c3_elasticity().with_(coarse_level=2),
-           "3D elasticity Q1 129^3 nodes, 3x3 blocks, 7-level hierarchy with the exact coarse solve on level 2 "
-           "(2,187 DoFs), FGMRES(10) + V(2,2) nodal block-Jacobi w=0.6, rtol 1e-8"),
+           "3D elasticity Q1 129^3 nodes, 3x3 blocks, levels 2-6 of the 3^3..129^3 hierarchy (5 in the "
+           "cycle) with the exact coarse solve on level 2 (9^3 nodes, 2,187 DoFs), FGMRES(10) + V(2,2) "
+           "nodal block-Jacobi w=0.6, rtol 1e-8"),
     "c4": (lambda: W.c4_oseen().with_(coarse_level=2),
-           "3D Oseen step Q1/Q1 65^3 nodes, 4x4 blocks, 6-level hierarchy with the exact coarse solve on level 2 "
-           "(2,916 DoFs), FGMRES(10) + V(2,2) point-Vanka w=0.6, rtol 1e-8"),
+           "3D Oseen step Q1/Q1 65^3 nodes, 4x4 blocks, levels 2-5 of the 3^3..65^3 hierarchy (4 in the "
+           "cycle) with the exact coarse solve on level 2 (9^3 nodes, 2,916 DoFs), FGMRES(10) + V(2,2) "
+           "point-Vanka w=0.6, rtol 1e-8"),
     "c4b": (lambda: W.c4_oseen(rounds=6, tall=True).with_(coarse_level=2),
-            "3D Oseen step Q1/Q1 129x129x65 nodes, 4x4 blocks, 7-level hierarchy with the exact coarse solve "
-            "on level 2 (1,620 DoFs), FGMRES(10) + V(2,2) point-Vanka, rtol 1e-8"),
+            "3D Oseen step Q1/Q1 129x129x65 nodes, 4x4 blocks, levels 2-6 of the 7-level hierarchy (5 in "
+            "the cycle) with the exact coarse solve on level 2 (1,620 DoFs), FGMRES(10) + V(2,2) "
+            "point-Vanka, rtol 1e-8"),
     "c3f": (lambda: W.c3_adaptive("face", 6),
             "3D elasticity Q1 on the face-refined cube mesh (8^3 coarse cubes, 5 rounds refining the cells "
             "next to the face x = 0), 683,741 nodes x 3 components with edge and face hanging nodes, 6-level "

@@ -438,6 +438,54 @@ def test_compact_transfers_bitwise_equal(name, prec, monkeypatch):
     _log(name, prec, "compact transfers bitwise equal; formats", compact)
 
 
+def _drop_masked_prolongation_rows(levels):
+    """The levels with every P~ row of a fully masked fine node emptied.  Such a row never
+    reaches a result: the prolongation leaves masked DoFs unchanged and the V-cycle's fine
+    defect is zero there, so the restriction only loses terms w * 0."""
+    import dataclasses
+    out = [levels[0]]
+    for lv in levels[1:]:
+        keep = ~lv.mask.all(axis=1)
+        ln = np.diff(lv.p_rowptr) * keep
+        rp = np.concatenate([[0], np.cumsum(ln)]).astype(lv.p_rowptr.dtype)
+        sel = np.repeat(keep, np.diff(lv.p_rowptr))
+        out.append(dataclasses.replace(lv, p_rowptr=rp, p_col=lv.p_col[sel].copy(), p_val=lv.p_val[sel].copy()))
+    return out
+
+
+@pytest.mark.parametrize("name", ["td_band", "elast17", "edge4"])
+def test_node_form_with_empty_rows_bitwise_equal(name, monkeypatch):
+    """Transfers with empty rows (fully masked fine nodes without P~ entries): the node
+    form's lanes of empty rows read the slot's base column and add 0 * x to +0, the per-DoF
+    form reads column 0; prolongation, restriction and V-cycle agree bit for bit."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    levels = _drop_masked_prolongation_rows(p.levels)
+    assert any(np.any(np.diff(lv.p_rowptr) == 0) for lv in levels[1:])
+    outs = []
+    for plain in ("0", "1"):
+        monkeypatch.setenv("MGQ1_PLAIN_TRANSFERS", plain)
+        h = mg.Hierarchy(levels, mg.config_from(wl))
+        assert h.transfer_format(h.n_levels - 1)[0] == (4 if plain == "1" else 2)
+        res = []
+        for l in range(1, h.n_levels):
+            f, c = o.levels[l], o.levels[l - 1]
+            d = torch.zeros(c.ndof, dtype=torch.float64, device="cuda")
+            h.restrict(l, dev(_rand(1100 + l, f.ndof)), d)
+            xt = dev(_rand(1150 + l, f.ndof))
+            h.prolong(l, dev(_rand(1190 + l, c.ndof)), xt)
+            res += [host(d), host(xt)]
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        h.vcycle(dev(o.b), x)
+        res.append(host(x))
+        outs.append(res)
+    assert all(np.array_equal(a, b) for a, b in zip(*outs))
+    # and the V-cycle equals the one with the full transfers (masked rows never reach it)
+    x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+    h64.vcycle(dev(o.b), x)
+    assert np.abs(host(x) - outs[0][-1]).max() <= 1e-14 * np.abs(host(x)).max()
+
+
 @pytest.mark.parametrize("name", ["td_band", "elast17"])
 @pytest.mark.parametrize("prec", ["fp64", "fp16"])
 def test_load_kinds_bitwise_equal(name, prec, monkeypatch):
