@@ -8,7 +8,7 @@
 //                 (exact for constant coefficients): Laplace, transport-diffusion with
 //                 the streamline-stabilisation term, linear elasticity, plus a lumped-mass
 //                 term c m_i (eq. mass_lumping)
-//   k_asm_gather  one thread per entry of a stored block (i, j): the sum over its precomputed
+//   k_asm_gather  one thread per stored block (i, j): the sums over its precomputed
 //                 contributions w K_e[a][b] (cell size class, corners a, b, w = the
 //                 product of the two hanging-node weights, a power of two), in a fixed
 //                 order, then the constraint rows and columns; no atomics, so repeated
@@ -116,10 +116,18 @@ __global__ __launch_bounds__(kAsmThreads) void k_asm_table(AsmCoef c, int dim, i
 }
 
 // code = d | a << 5 | b << 8 | k << 11: cell size class, corners, weight 2^-k.  One
-// thread per block entry (k, ci, cj): the B^2 threads of a block read the same short
-// contribution list (cached) and write consecutive values, so the value stream is
-// written with whole-wave contiguous stores
-__global__ __launch_bounds__(kAsmThreads) void k_asm_gather(int64_t nnzb, int dim, int B,
+// thread per stored block: it reads the block's contribution list once, kAsmBatch codes
+// at a time (the codes first, then their element-table rows), and sums the B^2 entries
+// w K_e[a][b] in list order; then the constraint rows and columns.  LT: the workgroup first
+// copies the element table (tn doubles) into LDS, where the lanes' scattered row reads
+// cost far less than as cached global gathers (1.5x on the 129^3 elasticity level).  The
+// block's values are staged in LDS so that each store instruction of a wave writes 64
+// consecutive values of the value stream.
+constexpr int kAsmBatch = 4;
+constexpr int kAsmLdsBytes = 64 << 10;   // LDS of one workgroup: staging + table
+
+template <int B, bool LT>
+__global__ __launch_bounds__(kAsmThreads) void k_asm_gather(int64_t nnzb, int dim, int tn,
                                                             const int32_t* __restrict__ brow,
                                                             const int32_t* __restrict__ bcol,
                                                             const uint32_t* __restrict__ cptr,
@@ -127,24 +135,76 @@ __global__ __launch_bounds__(kAsmThreads) void k_asm_gather(int64_t nnzb, int di
                                                             const double* __restrict__ table,
                                                             const uint8_t* __restrict__ mask,
                                                             double* __restrict__ val) {
-  const int BB = B * B;
-  const int64_t t = int64_t(blockIdx.x) * kAsmThreads + threadIdx.x;
-  if (t >= nnzb * BB) return;
-  const int64_t k = t / BB;
-  const int z = int(t - k * BB);
-  const int nb = 1 << dim;
-  double acc = 0.0;
-  const uint32_t t0 = cptr[k], t1 = cptr[k + 1];
-  for (uint32_t u = t0; u < t1; ++u) {
-    const uint32_t cd = code[u];
-    const int d = int(cd & 31u), a = int((cd >> 5) & 7u), b = int((cd >> 8) & 7u), e = int((cd >> 11) & 7u);
-    const double p = ldexp(1.0, -e) * table[int64_t((d * nb + a) * nb + b) * BB + z];
-    acc = acc + p;
+  constexpr int BB = B * B;
+  __shared__ double stage[kAsmThreads * BB];
+  extern __shared__ double ltab[];
+  if constexpr (LT) {
+    for (int e = int(threadIdx.x); e < tn; e += kAsmThreads) ltab[e] = table[e];
+    __syncthreads();
   }
-  const int ci = z / B, cj = z - ci * B;
-  const int64_t i = brow[k], j = bcol[k];
-  if (mask[i * B + ci] || mask[j * B + cj]) acc = (i == j && ci == cj) ? 1.0 : 0.0;
-  val[t] = acc;
+  const double* tb = LT ? ltab : table;
+  const int64_t k = int64_t(blockIdx.x) * kAsmThreads + threadIdx.x;
+  const int nb = 1 << dim;
+  double acc[BB];
+#pragma unroll
+  for (int z = 0; z < BB; ++z) acc[z] = 0.0;
+  if (k < nnzb) {
+    const uint32_t t0 = cptr[k], t1 = cptr[k + 1];
+    const int64_t i = brow[k], j = bcol[k];
+    uint8_t mi[B], mj[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      mi[c] = mask[i * B + c];
+      mj[c] = mask[j * B + c];
+    }
+    for (uint32_t u = t0; u < t1; u += kAsmBatch) {
+      uint32_t cd[kAsmBatch];
+#pragma unroll
+      for (int q = 0; q < kAsmBatch; ++q) cd[q] = u + q < t1 ? uint32_t(code[u + q]) : 0u;
+#pragma unroll
+      for (int q = 0; q < kAsmBatch; ++q) {
+        if (u + q < t1) {
+          const int d = int(cd[q] & 31u), a = int((cd[q] >> 5) & 7u), b = int((cd[q] >> 8) & 7u);
+          const int e = int((cd[q] >> 11) & 7u);
+          const double w = ldexp(1.0, -e);
+          const double* row = tb + int64_t((d * nb + a) * nb + b) * BB;
+#pragma unroll
+          for (int z = 0; z < BB; ++z) {
+            const double p = w * row[z];
+            acc[z] = acc[z] + p;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int ci = 0; ci < B; ++ci)
+#pragma unroll
+      for (int cj = 0; cj < B; ++cj)
+        if (mi[ci] || mj[cj]) acc[ci * B + cj] = (i == j && ci == cj) ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int z = 0; z < BB; ++z) stage[threadIdx.x * BB + z] = acc[z];
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * kAsmThreads * BB, total = nnzb * BB;
+#pragma unroll
+  for (int r = 0; r < BB; ++r) {
+    const int e = r * kAsmThreads + int(threadIdx.x);
+    if (base + e < total) val[base + e] = stage[e];
+  }
+}
+
+template <int B>
+void asm_gather_b(unsigned g, int64_t nnzb, int dim, int nd, const int32_t* brow, const int32_t* bcol,
+                  const uint32_t* cptr, const uint16_t* code, const double* table, const uint8_t* mask, double* val,
+                  hipStream_t s) {
+  const int tn = nd * (1 << dim) * (1 << dim) * B * B;
+  const size_t lds = size_t(tn) * sizeof(double);
+  if (lds + size_t(kAsmThreads) * B * B * sizeof(double) <= size_t(kAsmLdsBytes))
+    hipLaunchKernelGGL((k_asm_gather<B, true>), g, kAsmThreads, lds, s, nnzb, dim, tn, brow, bcol, cptr, code,
+                       table, mask, val);
+  else
+    hipLaunchKernelGGL((k_asm_gather<B, false>), g, kAsmThreads, 0, s, nnzb, dim, tn, brow, bcol, cptr, code,
+                       table, mask, val);
 }
 
 }  // namespace
@@ -158,14 +218,18 @@ hipError_t launch_asm_table(const AsmCoef& c, int dim, int B, int nd, const doub
   return hipGetLastError();
 }
 
-hipError_t launch_asm_gather(int64_t nnzb, int dim, int B, const int32_t* brow, const int32_t* bcol,
+hipError_t launch_asm_gather(int64_t nnzb, int dim, int B, int nd, const int32_t* brow, const int32_t* bcol,
                              const uint32_t* cptr, const uint16_t* code, const double* table, const uint8_t* mask,
                              double* val, hipStream_t s) {
   if (nnzb == 0) return hipSuccess;
-  if (B < 1 || B > 4) return hipErrorInvalidValue;
-  const int64_t n = nnzb * B * B;
-  hipLaunchKernelGGL(k_asm_gather, unsigned((n + kAsmThreads - 1) / kAsmThreads), kAsmThreads, 0, s, nnzb, dim, B,
-                     brow, bcol, cptr, code, table, mask, val);
+  const unsigned g = unsigned((nnzb + kAsmThreads - 1) / kAsmThreads);
+  switch (B) {
+    case 1: asm_gather_b<1>(g, nnzb, dim, nd, brow, bcol, cptr, code, table, mask, val, s); break;
+    case 2: asm_gather_b<2>(g, nnzb, dim, nd, brow, bcol, cptr, code, table, mask, val, s); break;
+    case 3: asm_gather_b<3>(g, nnzb, dim, nd, brow, bcol, cptr, code, table, mask, val, s); break;
+    case 4: asm_gather_b<4>(g, nnzb, dim, nd, brow, bcol, cptr, code, table, mask, val, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -222,7 +222,7 @@ hipError_t launch_asm_table(const AsmCoef& c, int dim, int B, int nd, const doub
 // val[k] (B x B, row-major) of every stored block k = (brow[k], bcol[k]) from its
 // contributions code[cptr[k] .. cptr[k+1]) (d | a << 5 | b << 8 | e << 11, weight 2^-e),
 // then identity rows / zero columns of the masked DoFs
-hipError_t launch_asm_gather(int64_t nnzb, int dim, int B, const int32_t* brow, const int32_t* bcol,
+hipError_t launch_asm_gather(int64_t nnzb, int dim, int B, int nd, const int32_t* brow, const int32_t* bcol,
                              const uint32_t* cptr, const uint16_t* code, const double* table, const uint8_t* mask,
                              double* val, hipStream_t s);
 

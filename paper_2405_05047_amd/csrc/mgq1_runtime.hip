@@ -2915,7 +2915,8 @@ int mg_asm_values(mg_asm* a, const mg_asm_coef* coef, double* val, void* stream)
   c.mass_coef = coef->mass_coef;
   hipStream_t s = static_cast<hipStream_t>(stream);
   MG_HIP(launch_asm_table(c, a->dim, a->B, a->nd, a->sizes, a->table, s));
-  MG_HIP(launch_asm_gather(a->nnzb, a->dim, a->B, a->brow, a->bcol, a->cptr, a->code, a->table, a->mask, val, s));
+  MG_HIP(launch_asm_gather(a->nnzb, a->dim, a->B, a->nd, a->brow, a->bcol, a->cptr, a->code, a->table, a->mask, val,
+                           s));
   return MG_OK;
 }
 
