@@ -13,10 +13,13 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/mgq1.h"
 #include "mgq1_internal.h"
+
+#include <cstdio>
 
 using namespace mgq1;
 
@@ -55,13 +58,48 @@ struct HostLevel {
   std::vector<double> sblk;         // caller's smoother blocks (empty: derived on the device)
 };
 
+// f(begin, end) over [0, n) in contiguous chunks of at least min_chunk iterations on up to
+// 16 host threads (MGQ1_HOST_THREADS lowers the cap).  Used by the setup loops whose
+// iterations write disjoint outputs, so the results do not depend on the thread count.
+// f must not throw or allocate.
+template <class F>
+void parallel_for(int64_t n, int64_t min_chunk, const F& f) {
+  int64_t T = std::min<int64_t>(16, std::max<int64_t>(1, int64_t(std::thread::hardware_concurrency())));
+  if (const char* e = std::getenv("MGQ1_HOST_THREADS")) T = std::max<int64_t>(1, std::min<int64_t>(T, std::atoi(e)));
+  T = std::min<int64_t>(T, (n + min_chunk - 1) / std::max<int64_t>(1, min_chunk));
+  if (T <= 1) {
+    if (n > 0) f(int64_t(0), n);
+    return;
+  }
+  const int64_t step = (n + T - 1) / T;
+  std::vector<std::thread> th;
+  th.reserve(size_t(T));
+  for (int64_t t = 1; t < T; ++t) {
+    const int64_t a = t * step, b = std::min(n, a + step);
+    if (a >= b) continue;
+    try {
+      th.emplace_back([&f, a, b] { f(a, b); });
+    } catch (...) {
+      f(a, b);                                      // no thread available: run it here
+    }
+  }
+  f(int64_t(0), std::min(n, step));
+  for (std::thread& x : th) x.join();
+}
+
 template <class T>
 int fetch(std::vector<T>& dst, const T* src, size_t n, bool on_device) {
-  dst.resize(n);
-  if (n == 0) return MG_OK;
+  if (n == 0) {
+    dst.clear();
+    return MG_OK;
+  }
   if (!src) return fail(MG_EINVAL, "null input array");
-  if (on_device) MG_HIP(hipMemcpy(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost));
-  else std::memcpy(dst.data(), src, n * sizeof(T));
+  if (on_device) {
+    dst.resize(n);
+    MG_HIP(hipMemcpy(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost));
+  } else {
+    dst.assign(src, src + n);
+  }
   return MG_OK;
 }
 
@@ -75,26 +113,49 @@ int validate_host(const HostLevel& L, const HostLevel* C, int level) {
   for (int32_t i = 0; i < L.n; ++i)
     if (L.rowptr[i + 1] < L.rowptr[i]) return fail(MG_EINVAL, at + "rowptr not monotone");
   if (L.rowptr[L.n] != L.nnzb) return fail(MG_EINVAL, at + "rowptr[n] != nnzb");
-  for (int32_t i = 0; i < L.n; ++i) {
+  // per-row checks in parallel chunks; the error reported is that of the first failing
+  // row, as in a sequential pass
+  static const char* const kRowError[] = {"", "column index out of range", "columns not sorted/unique",
+                                          "non-finite matrix value",
+                                          "constrained DoF row/column is not an identity row/column",
+                                          "missing diagonal block"};
+  auto row_error = [&](int32_t i) -> int {
     bool diag = false;
     for (int32_t k = L.rowptr[i]; k < L.rowptr[i + 1]; ++k) {
       const int32_t j = L.col[k];
-      if (j < 0 || j >= L.n) return fail(MG_EINVAL, at + "column index out of range");
-      if (k > L.rowptr[i] && L.col[k - 1] >= j) return fail(MG_EINVAL, at + "columns not sorted/unique");
+      if (j < 0 || j >= L.n) return 1;
+      if (k > L.rowptr[i] && L.col[k - 1] >= j) return 2;
       diag |= (j == i);
       for (int z = 0; z < B * B; ++z) {
         const double v = L.val[size_t(k) * B * B + z];
-        if (!std::isfinite(v)) return fail(MG_EINVAL, at + "non-finite matrix value");
+        if (!std::isfinite(v)) return 3;
         const int c = z / B, cc = z % B;
         const bool mr = L.mask[size_t(i) * B + c], mc = L.mask[size_t(j) * B + cc];
         if (mr || mc) {
           const double want = (i == j && c == cc && mr) ? 1.0 : 0.0;
-          if (v != want) return fail(MG_EINVAL, at + "constrained DoF row/column is not an identity row/column");
+          if (v != want) return 4;
         }
       }
     }
-    if (!diag) return fail(MG_EINVAL, at + "missing diagonal block");
-  }
+    return diag ? 0 : 5;
+  };
+  const int64_t nchunk = 64;
+  std::vector<int64_t> first_row(size_t(nchunk), -1);
+  std::vector<int> first_code(size_t(nchunk), 0);
+  const int64_t rows_per = (int64_t(L.n) + nchunk - 1) / nchunk;
+  parallel_for(nchunk, 1, [&](int64_t c0, int64_t c1) {
+    for (int64_t c = c0; c < c1; ++c)
+      for (int64_t i = c * rows_per; i < std::min<int64_t>(L.n, (c + 1) * rows_per); ++i) {
+        const int e = row_error(int32_t(i));
+        if (e) {
+          first_row[size_t(c)] = i;
+          first_code[size_t(c)] = e;
+          break;
+        }
+      }
+  });
+  for (int64_t c = 0; c < nchunk; ++c)
+    if (first_row[size_t(c)] >= 0) return fail(MG_EINVAL, at + kRowError[first_code[size_t(c)]]);
   for (double v : L.sblk)
     if (!std::isfinite(v)) return fail(MG_EINVAL, at + "non-finite smoother block value");
   if (C) {
@@ -298,14 +359,16 @@ HostSell build_sell(const HostLevel& L, int NR = 1) {
   S.col.assign(size_t(S.slots) * S.R, 0);
   S.val.assign(size_t(S.slots) * B * W, 0.0);
   S.rexp.assign(size_t(S.nslices) * W, 0);
-  for (int32_t s = 0; s < S.nslices; ++s) {
+  // every slice fills its own slots and exponents (parallel over slices)
+  parallel_for(S.nslices, 1024, [&](int64_t s0, int64_t s1) {
+  for (int64_t s = s0; s < s1; ++s) {
     const int32_t w = S.sptr[s + 1] - S.sptr[s];
     for (int r = 0; r < S.R; ++r) {
       const int64_t pos = int64_t(s) * S.R + r;
       if (pos >= L.n) continue;
       const int64_t i = node_at(pos);
       const int32_t len = L.rowptr[i + 1] - L.rowptr[i];
-      std::vector<double> mx(B, 0.0);
+      double mx[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       for (int32_t k = 0; k < w; ++k) {
         const int64_t slot = int64_t(S.sptr[s]) + k;
         if (k < len) {
@@ -324,6 +387,7 @@ HostSell build_sell(const HostLevel& L, int NR = 1) {
       for (int c = 0; c < B; ++c) S.rexp[size_t(s) * W + r * B + c] = int8_t(row_exponent(mx[c]));
     }
   }
+  });
   return S;
 }
 
@@ -534,9 +598,10 @@ int upload_sell(DevOwner* h, const HostSell& S, int kind, SellDev& D, hipStream_
   if (const char* e = std::getenv("MGQ1_WIDE_EVERY")) every = std::max(0, std::atoi(e));
   std::vector<uint16_t> c16(S.col.size(), 0);
   std::vector<int32_t> base(size_t(S.slots), 0);
-  std::vector<uint32_t> wide((size_t(S.nslices) + 31) / 32, 0u);
-  int64_t wide_slots = 0;
-  for (int32_t sl = 0; sl < S.nslices; ++sl) {
+  std::vector<uint8_t> is_wide(size_t(S.nslices), 0);
+  // per slice (parallel): offsets and bases, or the wide mark
+  parallel_for(S.nslices, 1024, [&](int64_t s0, int64_t s1) {
+  for (int64_t sl = s0; sl < s1; ++sl) {
     bool fits = !(every > 0 && sl % every == 0);
     for (int64_t k = S.sptr[sl]; k < S.sptr[sl + 1] && fits; ++k) {
       int32_t lo = INT32_MAX, hi = INT32_MIN;
@@ -551,14 +616,21 @@ int upload_sell(DevOwner* h, const HostSell& S, int kind, SellDev& D, hipStream_
         if (int64_t(sl) * S.R + r < S.n) c16[size_t(k) * S.R + r] = uint16_t(S.col[size_t(k) * S.R + r] - lo);
     }
     if (!fits) {
-      wide[size_t(sl) / 32] |= 1u << (sl % 32);
-      wide_slots += S.sptr[sl + 1] - S.sptr[sl];
+      is_wide[size_t(sl)] = 1;
       for (int64_t k = S.sptr[sl]; k < S.sptr[sl + 1]; ++k) {
         base[size_t(k)] = 0;
         for (int r = 0; r < S.R; ++r) c16[size_t(k) * S.R + r] = 0;
       }
     }
   }
+  });
+  std::vector<uint32_t> wide((size_t(S.nslices) + 31) / 32, 0u);
+  int64_t wide_slots = 0;
+  for (int64_t sl = 0; sl < S.nslices; ++sl)
+    if (is_wide[size_t(sl)]) {
+      wide[size_t(sl) / 32] |= 1u << (sl % 32);
+      wide_slots += S.sptr[sl + 1] - S.sptr[sl];
+    }
   const char* off = std::getenv("MGQ1_NO_COL16");
   if (wide_slots * 8 <= S.slots && !(off && std::atoi(off) != 0)) {
     uint16_t* c;
@@ -583,21 +655,25 @@ int upload_sell(DevOwner* h, const HostSell& S, int kind, SellDev& D, hipStream_
     D.val = v;
   } else if (kind == VK_F32) {
     std::vector<float> f(nv);
-    for (size_t i = 0; i < nv; ++i) f[i] = float(S.val[i]);
+    parallel_for(int64_t(nv), int64_t(1) << 20, [&](int64_t a, int64_t b) {
+      for (int64_t i = a; i < b; ++i) f[size_t(i)] = float(S.val[size_t(i)]);
+    });
     float* v;
     if ((rc = upload(h, &v, f, s))) return rc;
     MG_HIP(hipStreamSynchronize(s));
     D.val = v;
   } else {
     std::vector<uint16_t> q(nv);
-    for (int32_t sl = 0; sl < S.nslices; ++sl)
-      for (int32_t k = S.sptr[sl]; k < S.sptr[sl + 1]; ++k)
-        for (int cc = 0; cc < S.B; ++cc)
-          for (int ln = 0; ln < S.W; ++ln) {
-            const size_t idx = (size_t(k) * S.B + cc) * S.W + ln;
-            const double sc = std::ldexp(S.val[idx], -int(S.rexp[size_t(sl) * S.W + ln]));
-            q[idx] = kind == VK_F16 ? to_f16_bits(sc) : to_bf16_bits(sc);
-          }
+    parallel_for(S.nslices, 1024, [&](int64_t s0, int64_t s1) {
+      for (int64_t sl = s0; sl < s1; ++sl)
+        for (int32_t k = S.sptr[sl]; k < S.sptr[sl + 1]; ++k)
+          for (int cc = 0; cc < S.B; ++cc)
+            for (int ln = 0; ln < S.W; ++ln) {
+              const size_t idx = (size_t(k) * S.B + cc) * S.W + ln;
+              const double sc = std::ldexp(S.val[idx], -int(S.rexp[size_t(sl) * S.W + ln]));
+              q[idx] = kind == VK_F16 ? to_f16_bits(sc) : to_bf16_bits(sc);
+            }
+    });
     uint16_t* v;
     if ((rc = upload(h, &v, q, s))) return rc;
     int8_t* re;
@@ -1127,6 +1203,24 @@ int load_hierarchy(const mg_level_in* lv, int n_levels, bool on_dev, std::vector
   return MG_OK;
 }
 
+// MGQ1_SETUP_TIMES=1: print the wall time of each setup phase to stderr (diagnostics)
+struct PhaseTimer {
+  bool on = false;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  PhaseTimer() {
+    const char* e = std::getenv("MGQ1_SETUP_TIMES");
+    on = e && std::atoi(e) != 0;
+  }
+  void mark(const char* what, int level = -1) {
+    if (!on) return;
+    const auto n = std::chrono::steady_clock::now();
+    const double ms = std::chrono::duration<double, std::milli>(n - t).count();
+    if (level >= 0) std::fprintf(stderr, "[mgq1 setup] %s %d: %.1f ms\n", what, level, ms);
+    else std::fprintf(stderr, "[mgq1 setup] %s: %.1f ms\n", what, ms);
+    t = n;
+  }
+};
+
 // one level on the device: FP64 and cycle operators (sliced ELL for NR right-hand sides),
 // smoother blocks, mask, P~ and R = P~^T; with vectors = true also x, b, r, t
 // single: a single-problem handle (keeps the host pattern for the step-wise entry points
@@ -1139,10 +1233,14 @@ int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, 
   D.B = L.B;
   D.N = int64_t(L.n) * L.B;
   D.nnzb = L.nnzb;
+  PhaseTimer pt;
   HostSell S = build_sell(L, NR);
+  pt.mark("  sliced layout");
   if ((rc = upload_sell(h, S, VK_F64, D.A64, s))) return rc;
+  pt.mark("  FP64 operator upload");
   if (vkind == VK_F64) D.Ac = D.A64;
   else if ((rc = upload_sell(h, S, vkind, D.Ac, s))) return rc;
+  pt.mark("  cycle operator");
   const size_t sblk = size_t(S.nslices) * L.B * S.W;
   if ((rc = dalloc(h, reinterpret_cast<char**>(&D.S), sblk * xsize(xk)))) return rc;
   if (L.sblk.empty()) {
@@ -1176,6 +1274,7 @@ int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, 
     D.hperm = S.perm;
   }
   if ((rc = upload(h, &D.mask, L.mask, s))) return rc;
+  pt.mark("  smoother blocks and mask");
   if (has_p) {
     CsrHost P;
     P.nrows = L.n;
@@ -1193,6 +1292,7 @@ int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, 
     }
     if (!pn && (rc = upload_tsell(h, build_tsell(P, L.B, NR), D.Ps, s))) return rc;
     if (!rn && (rc = upload_tsell(h, build_tsell(R, L.B, NR), D.Rs, s))) return rc;
+    pt.mark("  transfers");
   }
   if (vectors) {
     const size_t vb = size_t(D.N) * NR * xsize(xk);
@@ -1321,6 +1421,7 @@ int tune_levels(mg_handle* h, hipStream_t s) {
 }
 
 int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
+  PhaseTimer pt;
   const mg_config& c = h->cfg;
   const int n_levels = int(H.size());
   int rc;
@@ -1329,12 +1430,16 @@ int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
   h->dflag = flag;
   MG_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
   const int vkind = value_kind(c.precision);
-  for (int l = 0; l < n_levels; ++l)
+  for (int l = 0; l < n_levels; ++l) {
     if ((rc = setup_level(h, H[l], l > 0, 1, vkind, h->xk, true, flag, s, h->lv[l], true,
                           l > 0 ? &H[l - 1] : nullptr)))
       return rc;
+    if (pt.on) MG_HIP(hipStreamSynchronize(s));
+    pt.mark("level", l);
+  }
   if ((rc = setup_coarse_inverse(h, H[0], flag, s, &h->Ainv, &h->n0))) return rc;
   if ((rc = check_flag(flag, s))) return rc;
+  pt.mark("coarse inverse");
   // outer-loop storage
   const int64_t N = h->lv[h->L].N;
   const int m = c.gmres_m;
@@ -1362,8 +1467,10 @@ int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
   if ((rc = dalloc(h, &h->pbig, size_t(maxgrid)))) return rc;
   for (int q = 0; q < 2; ++q)
     if ((rc = dalloc(h, &h->pv[q], size_t(kMaxRedBlocks)))) return rc;
+  pt.mark("outer-loop storage");
   if (c.smoother == MG_SMOOTH_CHEBYSHEV && (rc = setup_chebyshev(h, s))) return rc;
   if ((rc = tune_levels(h, s))) return rc;
+  pt.mark("Chebyshev bounds and slot-batch timing");
   if (const char* e = std::getenv("MGQ1_NO_FUSE")) h->fuse2z = std::atoi(e) == 0;
   if (c.smoother == MG_SMOOTH_CHEBYSHEV) h->fuse2z = false;   // the fused pair is two Jacobi sweeps
   // tail: every level up to the largest one with at most tail_dofs unknowns.  Default off:
@@ -2399,7 +2506,9 @@ int mg_setup_hierarchy(const mg_level_in* lv, int32_t n_levels, const mg_config*
   if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<HostLevel> H;
+  PhaseTimer pt;
   if ((rc = load_hierarchy(lv, n_levels, inputs_on_device != 0, H))) return rc;
+  pt.mark("load and validate");
   mg_handle* h = new (std::nothrow) mg_handle();
   if (!h) return fail(MG_ENOMEM, "host allocation failed");
   h->cfg = *cfg;
