@@ -1224,7 +1224,8 @@ struct PhaseTimer {
 // one level on the device: FP64 and cycle operators (sliced ELL for NR right-hand sides),
 // smoother blocks, mask, P~ and R = P~^T; with vectors = true also x, b, r, t
 // single: a single-problem handle (keeps the host pattern for the step-wise entry points
-// and stores its transfers in the compact form); the batch reads the plain form
+// and stores its transfers in the node form where they qualify); the batch reads the
+// per-DoF form
 int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, int xk, bool vectors, int* flag,
                 hipStream_t s, LevelDev& D, bool single = false, const HostLevel* coarser = nullptr) {
   const bool keep_host = single;

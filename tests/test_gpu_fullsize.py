@@ -55,7 +55,7 @@ def test_fullsize_sampled_parity(name):
     fmt = [h.transfer_format(l) for l in range(1, h.n_levels)]
     _log(name, "transfer formats (P col, R col, weight bytes)", fmt)
     if name in ("c3", "c4"):
-        assert fmt[-1] == (2, 2, 1)      # uniform box meshes: every transfer in the compact form
+        assert fmt[-1] == (2, 2, 1)      # uniform box meshes: the finest transfers in the node form
     _log(name, "sweep")
     x = torch.from_numpy(W.rand_vec(ref["sweep_x_seed"], N)).cuda()
     b = torch.from_numpy(W.rand_vec(ref["sweep_b_seed"], N)).cuda()

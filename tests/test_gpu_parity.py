@@ -401,10 +401,11 @@ def test_mixed_column_format_bitwise_equal(name, prec, monkeypatch):
 @pytest.mark.parametrize("name", ["poisson33", "td_band", "elast17", "oseen17", "edge4", "oseen_tall"])
 @pytest.mark.parametrize("prec", ["fp64", "fp16"])
 def test_compact_transfers_bitwise_equal(name, prec, monkeypatch):
-    """Transfers stored with 16-bit column offsets and 8-bit weight codes (w = code / 128,
-    the dyadic weights of nested box meshes) give bitwise the restriction, prolongation,
-    V-cycle and solve of 32-bit columns with FP32/FP64 weights: the codes decode exactly
-    and every row keeps its slot order."""
+    """Transfers in the node form (one lane per node; 16-bit column offsets, 8-bit weight
+    codes w = code / 128 for the dyadic weights of nested box meshes, and the column mask
+    bits packed into one 32-bit word per slot) give bitwise the restriction,
+    prolongation, V-cycle and solve of the per-DoF form with 32-bit columns and FP32/FP64
+    weights: the codes decode exactly and every row keeps its slot order."""
     from paper_2405_05047_amd import mg
     wl, o, mgo, p, h64 = _pair(name)
     outs = []
