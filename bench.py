@@ -311,13 +311,13 @@ def time_stepping(torch, gen, mg, n=10, steps=100):
 
 
 def pressure_correction(torch, gen, mg, cells=(32, 32, 64), levels=3, steps=20, oracle_step=True):
-    """Sec. 5.3 driven cavity: explicit momentum step, pressure Poisson solve (FGMRES(30) +
+    """Sec. 5.3 driven cavity: explicit momentum step, pressure Poisson solve (FGMRES(10) +
     V(2,2) with the Chebyshev smoother on the graded mesh) and pressure update per time
     step, from rest with the moving wall; dt = 1e-4, nu = 1e-3."""
     nu, dt = 1e-3, 1e-4
     prob = gen.build_ns(cells, n_levels=levels)
     pw = W.Workload(name="ns_pressure", dim=3, coarse=(1, 1, 1), h0=1.0, rounds=(), pde=W.PDE_POISSON, block=1,
-                    omega=0.8, nu1=2, nu2=2, outer=W.OUTER_FGMRES, gmres_m=30, rtol=1e-8, maxit=400,
+                    omega=0.8, nu1=2, nu2=2, outer=W.OUTER_FGMRES, gmres_m=10, rtol=1e-8, maxit=400,
                     smoother=W.SMOOTH_CHEBYSHEV)
     hp = mg.Hierarchy(prob.levels, mg.config_from(pw))
     pc = mg.PressureCorrection(prob, hp, nu, dt)
