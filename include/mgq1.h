@@ -49,8 +49,13 @@ enum { MG_COARSE_EXACT = 0, MG_COARSE_SMOOTH = 1 };
 enum { MG_OUTER_IR = 0, MG_OUTER_FGMRES = 1 };
 /* smoother on levels >= 1 (the coarse MG_COARSE_SMOOTH variant always uses damped sweeps) */
 enum { MG_SMOOTH_JACOBI = 0, MG_SMOOTH_CHEBYSHEV = 1 };
-/* precision of the V-cycle; the outer defect, the update and the coarse solve are FP64 */
-enum { MG_PREC_FP64 = 0, MG_PREC_FP32 = 1, MG_PREC_FP32_F16VAL = 2, MG_PREC_FP32_BF16VAL = 3 };
+/* precision of the V-cycle; the outer defect, the update and the coarse solve are FP64.
+ * MG_PREC_FP64_DICT: FP64 throughout with every level's stored blocks kept as a
+ * dictionary (the distinct b x b FP64 blocks once, a 16-bit index per stored block) where
+ * a level has at most 65,535 distinct blocks, else as plain FP64 values; lossless, so
+ * every result is bitwise that of MG_PREC_FP64 (single-problem handles only). */
+enum { MG_PREC_FP64 = 0, MG_PREC_FP32 = 1, MG_PREC_FP32_F16VAL = 2, MG_PREC_FP32_BF16VAL = 3,
+       MG_PREC_FP64_DICT = 4 };
 
 /* One level of the hierarchy (Sec. 2.2: meshes Omega_0 .. Omega_L and their spaces). */
 typedef struct {
@@ -228,6 +233,10 @@ int mg_level_tuning(const mg_handle* h, int32_t level, int32_t* slot_batch, int3
  * prolongation and restriction as sparse products).  Any output pointer may be NULL. */
 int mg_level_transfer_format(const mg_handle* h, int32_t level, int32_t* p_col_bytes, int32_t* r_col_bytes,
                              int32_t* weight_bytes);
+
+/* Distinct blocks of level `level`'s operator in the dictionary form (MG_PREC_FP64_DICT
+ * handles), or 0 when its values are stored plainly. */
+int mg_level_dictionary(const mg_handle* h, int32_t level, int32_t* n_blocks);
 
 /* Host-only structural validation of one level (and its coarser neighbour for P~);
  * no device is touched.  Returns MG_OK or MG_EINVAL with a message. */

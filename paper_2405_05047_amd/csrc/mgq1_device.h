@@ -63,6 +63,11 @@ template <> struct Val<VK_F16> {
   }
   __device__ __forceinline__ static float dec(raw u) { return __half2float(__ushort_as_half(u)); }
 };
+// FP64 blocks from the level's dictionary (loaded in sell_batch, not through load())
+template <> struct Val<VK_DICT> {
+  using raw = double;
+  __device__ __forceinline__ static double dec(raw u) { return u; }
+};
 template <> struct Val<VK_BF16> {
   using raw = unsigned short;
   template <bool NT>
@@ -114,15 +119,32 @@ __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int n
   unsigned js[NB];                         // unsigned: widening needs no sign extension
   VR av[NB][B];
   XI xv[NB][B];
+  if constexpr (K == VK_DICT) {
+    // the dictionary form: column and block index first, then the block's row from the
+    // (cached) dictionary together with the x gathers
+    static_assert(NR == 1, "the dictionary form has one right-hand side");
+    unsigned short di[NB];
 #pragma unroll
-  for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16, NT>(A, k + qq, int64_t(k + qq) * R + r);
+    for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16, NT>(A, k + qq, int64_t(k + qq) * R + r);
 #pragma unroll
-  for (int qq = 0; qq < NB; ++qq) {
-    const int64_t vb = int64_t(k + qq) * B * W + rl;
+    for (int qq = 0; qq < NB; ++qq) di[qq] = stream_load<NT>(A.didx + int64_t(k + qq) * R + r);
+    __builtin_amdgcn_sched_barrier(0);
+    const int c = rl % B;
 #pragma unroll
-    for (int cc = 0; cc < B; ++cc) av[qq][cc] = Val<K>::template load<NT>(A.val, vb + cc * W);
+    for (int qq = 0; qq < NB; ++qq)
+#pragma unroll
+      for (int cc = 0; cc < B; ++cc) av[qq][cc] = A.dtab[(int64_t(di[qq]) * B + c) * B + cc];
+  } else {
+#pragma unroll
+    for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16, NT>(A, k + qq, int64_t(k + qq) * R + r);
+#pragma unroll
+    for (int qq = 0; qq < NB; ++qq) {
+      const int64_t vb = int64_t(k + qq) * B * W + rl;
+#pragma unroll
+      for (int cc = 0; cc < B; ++cc) av[qq][cc] = Val<K>::template load<NT>(A.val, vb + cc * W);
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
-  __builtin_amdgcn_sched_barrier(0);
   if constexpr (B > 1 && NR == 1) {
     // each lane gathers only its own component of the neighbour node (the B lanes of a
     // node read one contiguous B-vector together) and takes the others from its node's

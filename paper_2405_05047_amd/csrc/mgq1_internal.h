@@ -8,7 +8,7 @@
 namespace mgq1 {
 
 // storage kind of matrix values
-enum ValKind { VK_F64 = 0, VK_F32 = 1, VK_F16 = 2, VK_BF16 = 3 };
+enum ValKind { VK_F64 = 0, VK_F32 = 1, VK_F16 = 2, VK_BF16 = 3, VK_DICT = 4 };
 // storage kind of vectors
 enum VecKind { X_F64 = 0, X_F32 = 1 };
 
@@ -40,6 +40,11 @@ struct SellDev {
   const int32_t* perm = nullptr;    // node at row position slice*R + r (NULL: the position
                                     // itself); rows sorted by length inside windows of slices
   int nt = 1;                       // 1: values and indices read with non-temporal loads
+  // kind VK_DICT: the block of node row r in slot k is dtab[didx[k * R + r]] (ndict
+  // distinct B x B FP64 blocks, row-major); val is not read
+  const uint16_t* didx = nullptr;
+  const double* dtab = nullptr;
+  int32_t ndict = 0;
 };
 
 // the two slot-batch sizes the slice kernels are built for (default, alternative)

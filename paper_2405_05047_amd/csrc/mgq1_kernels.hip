@@ -578,6 +578,10 @@ hipError_t spmv_t(const SellDev& A, const void* b, const void* x, void* y, const
 template <int B>
 hipError_t spmv_b(const SellDev& A, const void* b, const void* x, void* y, const uint8_t* mask, int xk, int yk,
                   int mode, double* partials, const double* dotv, hipStream_t s) {
+  if (A.kind == VK_DICT) {
+    if (xk == X_F64 && yk == X_F64) return spmv_t<B, VK_DICT, double, double, double>(A, b, x, y, mask, mode, partials, dotv, s);
+    return hipErrorInvalidValue;
+  }
   if (A.kind == VK_F64) {
     if (xk == X_F64 && yk == X_F64) return spmv_t<B, VK_F64, double, double, double>(A, b, x, y, mask, mode, partials, dotv, s);
     if (xk == X_F32 && yk == X_F64) return spmv_t<B, VK_F64, float, double, double>(A, b, x, y, mask, mode, partials, dotv, s);
@@ -613,8 +617,12 @@ hipError_t sweep_t(const SellDev& A, const void* S, const void* b, const void* x
   }
   // FP64 vectors go with FP64 values only; FP32 vectors with the reduced formats
   if constexpr (sizeof(X) == 8) {
-    if (A.kind != VK_F64) return hipErrorInvalidValue;
-    MGQ1_SWEEP(VK_F64);
+    if (A.kind == VK_DICT) {
+      MGQ1_SWEEP(VK_DICT);
+    } else {
+      if (A.kind != VK_F64) return hipErrorInvalidValue;
+      MGQ1_SWEEP(VK_F64);
+    }
   } else {
     switch (A.kind) {
       case VK_F32: MGQ1_SWEEP(VK_F32); break;

@@ -14,6 +14,7 @@
 #include <numeric>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/mgq1.h"
@@ -685,6 +686,106 @@ int upload_sell(DevOwner* h, const HostSell& S, int kind, SellDev& D, hipStream_
   return MG_OK;
 }
 
+// Dictionary form of a level's FP64 blocks (MG_PREC_FP64_DICT): the distinct B x B blocks
+// of the sliced layout once (padding blocks are zero blocks), a 16-bit index per slot and
+// node row.  Applied when the level has at most 65,535 distinct blocks (blocks compare
+// bitwise); the kernels then read the same doubles, so every result has the same bits.
+struct BlockKey {
+  uint64_t w[16];
+  int n;
+  bool operator==(const BlockKey& o) const {
+    for (int i = 0; i < n; ++i)
+      if (w[i] != o.w[i]) return false;
+    return true;
+  }
+};
+struct BlockHash {
+  size_t operator()(const BlockKey& k) const {
+    uint64_t x = 1469598103934665603ull;
+    for (int i = 0; i < k.n; ++i) {
+      x ^= k.w[i] + 0x9e3779b97f4a7c15ull + (x << 6) + (x >> 2);
+      x *= 1099511628211ull;
+    }
+    return size_t(x ^ (x >> 29));
+  }
+};
+
+int upload_dict(DevOwner* h, const HostSell& S, SellDev& D, hipStream_t s, bool* applied) {
+  *applied = false;
+  const int B = S.B, BB = B * B, W = S.W, R = S.R;
+  if (BB > 16 || W != kWave) return MG_OK;
+  const int64_t nblk = S.slots * R;
+  auto key_at = [&](int64_t e, BlockKey& key) {
+    const int64_t k = e / R, r = e % R;
+    key.n = BB;
+    for (int c = 0; c < B; ++c)
+      for (int cc = 0; cc < B; ++cc) {
+        const double v = S.val[size_t((k * B + cc) * W + r * B + c)];
+        std::memcpy(&key.w[c * B + cc], &v, 8);
+      }
+  };
+  constexpr size_t kMaxDict = 65535;
+  // pass 1: distinct blocks per chunk, in first-seen order
+  const int64_t nchunk = 64;
+  const int64_t per = (nblk + nchunk - 1) / nchunk;
+  std::vector<std::vector<BlockKey>> seen(static_cast<size_t>(nchunk));
+  std::vector<int> bad(size_t(nchunk), 0);
+  parallel_for(nchunk, 1, [&](int64_t c0, int64_t c1) {
+    for (int64_t c = c0; c < c1; ++c) {
+      try {
+        std::unordered_map<BlockKey, uint32_t, BlockHash> m;
+        BlockKey key;
+        for (int64_t e = c * per; e < std::min(nblk, (c + 1) * per); ++e) {
+          key_at(e, key);
+          if (m.emplace(key, uint32_t(m.size())).second) {
+            seen[size_t(c)].push_back(key);
+            if (m.size() > kMaxDict) { bad[size_t(c)] = 1; break; }
+          }
+        }
+      } catch (...) {
+        bad[size_t(c)] = 2;
+      }
+    }
+  });
+  for (int b : bad)
+    if (b == 2) return fail(MG_ENOMEM, "host allocation failed (block dictionary)");
+  for (int b : bad)
+    if (b) return MG_OK;                           // too many distinct blocks: plain values
+  std::unordered_map<BlockKey, uint32_t, BlockHash> dict;
+  std::vector<double> tab;
+  for (const auto& v : seen)
+    for (const BlockKey& key : v)
+      if (dict.emplace(key, uint32_t(dict.size())).second) {
+        if (dict.size() > kMaxDict) return MG_OK;
+        for (int i = 0; i < BB; ++i) {
+          double d;
+          std::memcpy(&d, &key.w[i], 8);
+          tab.push_back(d);
+        }
+      }
+  // pass 2: the index of every block (read-only lookups)
+  std::vector<uint16_t> idx(static_cast<size_t>(nblk));
+  parallel_for(nblk, 1 << 16, [&](int64_t a, int64_t b) {
+    BlockKey key;
+    for (int64_t e = a; e < b; ++e) {
+      key_at(e, key);
+      idx[size_t(e)] = uint16_t(dict.find(key)->second);
+    }
+  });
+  int rc;
+  uint16_t* di;
+  double* dt;
+  if ((rc = upload(h, &di, idx, s)) || (rc = upload(h, &dt, tab, s))) return rc;
+  MG_HIP(hipStreamSynchronize(s));
+  D.kind = VK_DICT;
+  D.didx = di;
+  D.dtab = dt;
+  D.ndict = int32_t(dict.size());
+  D.nt = stream_nt(int64_t(S.col.size()) * (D.col16 ? 2 : 4) + nblk * 2);
+  *applied = true;
+  return MG_OK;
+}
+
 int upload_csr(DevOwner* h, const CsrHost& C, CsrDev& D, hipStream_t s) {
   D.nrows = C.nrows;
   D.ncols = C.ncols;
@@ -1123,12 +1224,13 @@ namespace {
 int value_kind(int precision) {
   return precision == MG_PREC_FP64 ? VK_F64
          : precision == MG_PREC_FP32 ? VK_F32
-         : precision == MG_PREC_FP32_F16VAL ? VK_F16 : VK_BF16;
+         : precision == MG_PREC_FP32_F16VAL ? VK_F16
+         : precision == MG_PREC_FP64_DICT ? VK_F64 : VK_BF16;
 }
 
 int check_config(const mg_config& c) {
   if (!(c.omega > 0.0) || c.nu1 < 0 || c.nu2 < 0 || c.nu1 + c.nu2 < 1 || c.gmres_m < 1 || c.gmres_m > 64 ||
-      c.maxit < 0 || !(c.rtol >= 0.0) || c.precision < MG_PREC_FP64 || c.precision > MG_PREC_FP32_BF16VAL ||
+      c.maxit < 0 || !(c.rtol >= 0.0) || c.precision < MG_PREC_FP64 || c.precision > MG_PREC_FP64_DICT ||
       (c.outer != MG_OUTER_IR && c.outer != MG_OUTER_FGMRES) ||
       (c.coarse_mode != MG_COARSE_EXACT && c.coarse_mode != MG_COARSE_SMOOTH))
     return fail(MG_EINVAL, "invalid configuration");
@@ -1227,7 +1329,8 @@ struct PhaseTimer {
 // and stores its transfers in the node form where they qualify); the batch reads the
 // per-DoF form
 int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, int xk, bool vectors, int* flag,
-                hipStream_t s, LevelDev& D, bool single = false, const HostLevel* coarser = nullptr) {
+                hipStream_t s, LevelDev& D, bool single = false, const HostLevel* coarser = nullptr,
+                bool dict = false) {
   const bool keep_host = single;
   int rc;
   D.n = L.n;
@@ -1276,6 +1379,15 @@ int setup_level(DevOwner* h, const HostLevel& L, bool has_p, int NR, int vkind, 
   }
   if ((rc = upload(h, &D.mask, L.mask, s))) return rc;
   pt.mark("  smoother blocks and mask");
+  if (dict && NR == 1) {
+    // the smoother blocks above were computed from the plain FP64 values; from here on the
+    // level's kernels read the dictionary form of the same values
+    MG_HIP(hipStreamSynchronize(s));
+    bool ok = false;
+    if ((rc = upload_dict(h, S, D.A64, s, &ok))) return rc;
+    if (ok) D.Ac = D.A64;
+    pt.mark("  block dictionary");
+  }
   if (has_p) {
     CsrHost P;
     P.nrows = L.n;
@@ -1433,7 +1545,7 @@ int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
   const int vkind = value_kind(c.precision);
   for (int l = 0; l < n_levels; ++l) {
     if ((rc = setup_level(h, H[l], l > 0, 1, vkind, h->xk, true, flag, s, h->lv[l], true,
-                          l > 0 ? &H[l - 1] : nullptr)))
+                          l > 0 ? &H[l - 1] : nullptr, c.precision == MG_PREC_FP64_DICT)))
       return rc;
     if (pt.on) MG_HIP(hipStreamSynchronize(s));
     pt.mark("level", l);
@@ -1474,6 +1586,7 @@ int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
   pt.mark("Chebyshev bounds and slot-batch timing");
   if (const char* e = std::getenv("MGQ1_NO_FUSE")) h->fuse2z = std::atoi(e) == 0;
   if (c.smoother == MG_SMOOTH_CHEBYSHEV) h->fuse2z = false;   // the fused pair is two Jacobi sweeps
+  if (c.precision == MG_PREC_FP64_DICT) h->fuse2z = false;     // the fused pair reads plain values
   // tail: every level up to the largest one with at most tail_dofs unknowns.  Default off:
   // on MI355X one workgroup walking several levels was measured slower (dependent-load
   // latency serialises) than separate grid launches per step.
@@ -1482,6 +1595,8 @@ int setup_handle(mg_handle* h, const std::vector<HostLevel>& H, hipStream_t s) {
   int top = 0;
   for (int l = 1; l <= h->L; ++l)
     if (h->lv[l].N <= tail_dofs) top = l;
+  if (top >= 1 && c.precision == MG_PREC_FP64_DICT)
+    return fail(MG_EUNSUPPORTED, "the single-workgroup tail reads plain values");
   if (top >= 1 && c.smoother == MG_SMOOTH_CHEBYSHEV)
     return fail(MG_EUNSUPPORTED, "the single-workgroup tail runs damped Jacobi sweeps only");
   h->tail_top = top;
@@ -2514,7 +2629,7 @@ int mg_setup_hierarchy(const mg_level_in* lv, int32_t n_levels, const mg_config*
   if (!h) return fail(MG_ENOMEM, "host allocation failed");
   h->cfg = *cfg;
   h->L = n_levels - 1;
-  h->xk = cfg->precision == MG_PREC_FP64 ? X_F64 : X_F32;
+  h->xk = (cfg->precision == MG_PREC_FP64 || cfg->precision == MG_PREC_FP64_DICT) ? X_F64 : X_F32;
   h->lv.resize(n_levels);
   if (const char* lim = std::getenv("MGQ1_SCRATCH_LIMIT")) h->scratch_cap = std::min(kScratchDoubles, std::max(0, std::atoi(lim)));
   if ((rc = scratch_address(&h->scratch_dev))) {
@@ -2699,6 +2814,7 @@ int mg_level_export(const mg_handle* h, int32_t level, void* values, int8_t* row
   const LevelDev& L = h->lv[level];
   const SellDev& A = L.Ac;
   if (L.hrow.empty()) return fail(MG_EUNSUPPORTED, "no host geometry kept for this level");
+  if (A.kind == VK_DICT) return fail(MG_EUNSUPPORTED, "the level's values are stored as a block dictionary");
   if ((A.kind == VK_F16 || A.kind == VK_BF16) && !row_exp) return fail(MG_EINVAL, "row_exp is required for 16-bit values");
   const int B = L.B, W = kWave, R = A.R;
   const int vb = A.kind == VK_F64 ? 8 : A.kind == VK_F32 ? 4 : 2;
@@ -2762,6 +2878,13 @@ int mg_level_transfer_format(const mg_handle* h, int32_t level, int32_t* p_col_b
   return MG_OK;
 }
 
+int mg_level_dictionary(const mg_handle* h, int32_t level, int32_t* n_blocks) {
+  if (!h || !n_blocks || level < 0 || level > h->L) return fail(MG_EINVAL, "bad handle, level or output");
+  const SellDev& A = h->lv[level].A64;
+  *n_blocks = A.kind == VK_DICT ? A.ndict : 0;
+  return MG_OK;
+}
+
 int32_t mg_num_levels(const mg_handle* h) { return h ? h->L + 1 : 0; }
 
 void mg_destroy(mg_handle* h) { delete h; }
@@ -2792,6 +2915,7 @@ int mg_setup_batch(const mg_level_in* const* problems, const int32_t* n_levels, 
   if (cfg->outer != MG_OUTER_FGMRES) return fail(MG_EUNSUPPORTED, "batched solves use the FGMRES outer loop");
   if (cfg->coarse_mode != MG_COARSE_EXACT) return fail(MG_EUNSUPPORTED, "batched solves use the exact coarse solve");
   if (cfg->smoother != MG_SMOOTH_JACOBI) return fail(MG_EUNSUPPORTED, "batched solves use the damped (block-)Jacobi smoother");
+  if (cfg->precision == MG_PREC_FP64_DICT) return fail(MG_EUNSUPPORTED, "batched solves store plain values");
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::vector<std::vector<HostLevel>> HH(n_problems);
   for (int p = 0; p < n_problems; ++p) {

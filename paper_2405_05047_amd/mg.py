@@ -17,7 +17,7 @@ from ._native import load
 
 _lib = None
 
-PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
+PREC = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "fp64dict": 4}
 
 
 class LevelIn(C.Structure):
@@ -75,7 +75,7 @@ SYMBOLS = ["mg_setup_hierarchy", "mg_vcycle", "mg_solve", "mg_solve_fixed", "mg_
            "mg_time_theta", "mg_time_run", "mg_time_destroy", "mg_outer_defect_noalloc",
            "mg_level_smooth", "mg_level_eigen_estimate", "mg_ns_setup", "mg_ns_momentum", "mg_ns_divergence",
            "mg_ns_pressure_update", "mg_ns_run", "mg_ns_destroy", "mg_asm_setup", "mg_asm_values",
-           "mg_asm_destroy", "mg_level_transfer_format"]
+           "mg_asm_destroy", "mg_level_transfer_format", "mg_level_dictionary"]
 
 
 def lib():
@@ -103,6 +103,7 @@ def lib():
         L.mg_level_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]
         L.mg_level_transfer_format.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.mg_level_dictionary.argtypes = [vp, i32, C.POINTER(i32)]
         L.mg_num_levels.argtypes = [vp]
         L.mg_num_levels.restype = i32
         L.mg_validate_level.argtypes = [C.POINTER(LevelIn), C.POINTER(LevelIn)]
@@ -266,6 +267,12 @@ class Hierarchy:
         _check(lib().mg_level_transfer_format(self.h, l, C.byref(pc), C.byref(rc), C.byref(wb)))
         return pc.value, rc.value, wb.value
 
+    def dictionary_blocks(self, l):
+        """Distinct blocks of level l's operator in the dictionary form (0: plain values)."""
+        n = C.c_int32()
+        _check(lib().mg_level_dictionary(self.h, l, C.byref(n)))
+        return n.value
+
     def ndof(self, l=-1):
         n, b, _ = self.sizes[l]
         return n * b
@@ -273,7 +280,7 @@ class Hierarchy:
     @property
     def cycle_fp64(self):
         """True when the V-cycle (and the step-wise entry points) work on FP64 vectors."""
-        return self.cfg.precision == PREC["fp64"]
+        return self.cfg.precision in (PREC["fp64"], PREC["fp64dict"])
 
     # -- whole-path entry points
     def vcycle(self, b, x, x_is_zero=True, stream=None):

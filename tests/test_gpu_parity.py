@@ -439,6 +439,54 @@ def test_compact_transfers_bitwise_equal(name, prec, monkeypatch):
     _log(name, prec, "compact transfers bitwise equal; formats", compact)
 
 
+@pytest.mark.parametrize("name", ["poisson33", "td_band", "elast17", "oseen17", "edge4", "oseen_tall"])
+def test_dictionary_form_bitwise_equal(name):
+    """MG_PREC_FP64_DICT stores each level's distinct FP64 blocks once and a 16-bit index
+    per stored block: the kernels read the same doubles in the same order, so every step
+    (SpMV, defect, sweep on every level), the V-cycle and the solve are bitwise those of
+    the plain FP64 handle."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    hd = mg.Hierarchy(p.levels, mg.config_from(wl, precision="fp64dict"))
+    nd = [hd.dictionary_blocks(l) for l in range(hd.n_levels)]
+    assert nd[-1] > 0, nd
+    for l, lv in enumerate(o.levels):
+        x = dev(_rand(1300 + l, lv.ndof))
+        b = dev(_rand(1350 + l, lv.ndof))
+        outs = []
+        for h in (h64, hd):
+            y = torch.zeros_like(x)
+            h.spmv(l, x, y)
+            xo = torch.zeros_like(x)
+            h.sweep(l, b, x, xo)
+            outs.append((host(y), host(xo)))
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1]), l
+    res = []
+    for h in (h64, hd):
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        h.vcycle(dev(o.b), x)
+        v = host(x)
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        st = h.solve(dev(o.b), x)
+        res.append((v, host(x), st["iters"]))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1]) and res[0][2] == res[1][2]
+    _log(name, "dictionary form bitwise equal; distinct blocks per level", nd)
+
+
+def test_dictionary_form_with_chebyshev():
+    """The Chebyshev-accelerated smoother on the dictionary form: bitwise the plain FP64
+    solve."""
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair("elast17")
+    res = []
+    for prec in ("fp64", "fp64dict"):
+        h = mg.Hierarchy(p.levels, mg.config_from(wl, precision=prec, smoother=W.SMOOTH_CHEBYSHEV))
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        st = h.solve(dev(o.b), x)
+        res.append((host(x), st["iters"]))
+    assert np.array_equal(res[0][0], res[1][0]) and res[0][1] == res[1][1]
+
+
 def _drop_masked_prolongation_rows(levels):
     """The levels with every P~ row of a fully masked fine node emptied.  Such a row never
     reaches a result: the prolongation leaves masked DoFs unchanged and the V-cycle's fine
