@@ -8,7 +8,8 @@ largest configuration: 3D linear elasticity on 129^3 nodes (6,440,067 DoFs, 3x3 
 blocks, 7-level hierarchy), whose GB-sized operators stream from HBM.
 
 Printed: one JSON line with the FP64 solve throughput as `value`, the mixed-precision
-variants, the roofline of the dominant kernel (finest-level smoothing sweep) against the
+variants, the lossless block-dictionary form of the FP64 operators (bitwise the FP64
+results), the roofline of the dominant kernel (finest-level smoothing sweep) against the
 8 TB/s HBM peak, a measured device-copy rate, the same sweep on the 1M-unknown 2D
 transport-diffusion problem (its 91 MB operator is served from the 256 MB memory-side
 cache, reported separately), the oracle timed on the host and the batched form (64
@@ -79,6 +80,13 @@ def sweep_bytes(n, b, nnzb, col_bytes=4):
     when the operator is stored with 16-bit offsets from a per-slot base) + int32 row pointers, x
     and b read, x_out written, nodal b x b inverse blocks read."""
     return nnzb * (b * b * 8 + col_bytes) + 4 * (n + 1) + 3 * n * b * 8 + n * b * b * 8
+
+
+def dict_sweep_bytes(n, b, nnzb, col_bytes, ndict):
+    """The same sweep with the operator in the dictionary form: a 16-bit block index and
+    the column index per stored block, the distinct blocks once, vectors and smoother
+    blocks as in sweep_bytes."""
+    return nnzb * (2 + col_bytes) + ndict * b * b * 8 + 4 * (n + 1) + 3 * n * b * 8 + n * b * b * 8
 
 
 def time_solves(torch, h, b, x, steps, warmup):
@@ -448,9 +456,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
-    ap.add_argument("--precisions", default="fp64,fp32,fp16,bf16",
+    ap.add_argument("--precisions", default="fp64,fp32,fp16,bf16,fp64dict",
                     help="variants; a '+cheb' suffix runs the variant with the Chebyshev smoother")
-    ap.add_argument("--cheb-variants", default="fp64+cheb,fp16+cheb",
+    ap.add_argument("--cheb-variants", default="fp64+cheb,fp16+cheb,fp64dict+cheb",
                     help="Chebyshev-smoothed variants added for the elasticity workloads ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cache-served", action="store_true")
@@ -501,6 +509,17 @@ def main():
                          "converged": all(s["converged"] for s in stats), "rel_residual": rel,
                          "setup_s": round(t_setup, 3),
                          "slot_batch_per_level": [h.tuning(l)[0] for l in range(h.n_levels)]}
+        if base_prec == "fp64dict":
+            # lossless: the distinct FP64 blocks once per level, a 16-bit index per stored block
+            Ld = h.n_levels - 1
+            nd, bsd, nnzbd = h.sizes[Ld]
+            ndict = h.dictionary_blocks(Ld)
+            results[prec]["dictionary_blocks_per_level"] = [h.dictionary_blocks(l) for l in range(h.n_levels)]
+            if ndict:
+                ksec = kernel_time(torch, h, Ld, nd * bsd)
+                kbytes = dict_sweep_bytes(nd, bsd, nnzbd, h.col_bytes(Ld), ndict)
+                results[prec]["finest_sweep"] = {"us_per_launch": round(ksec * 1e6, 2), "bytes_per_launch": kbytes,
+                                                 "achieved_gbs": round(kbytes / ksec / 1e9, 1)}
         if sm == "cheb":
             results[prec]["smoother"] = (f"Chebyshev on [{wl.cheb_lo}, {wl.cheb_hi}] x lambda(S A), lambda by "
                                          f"{wl.power_its} power-iteration steps")

@@ -32,6 +32,9 @@ def test_sweep_bytes_of_the_2d_workload():
     assert bench.sweep_bytes(n, 1, nnzb, 4) == expect + 2 * nnzb
     # block systems: b*b values per block
     assert bench.sweep_bytes(10, 3, 100, 2) == 100 * (72 + 2) + 44 + 3 * 30 * 8 + 10 * 72
+    # dictionary form: a 2-byte block index per stored block instead of its values, the
+    # distinct blocks once
+    assert bench.dict_sweep_bytes(10, 3, 100, 2, 7) == 100 * (2 + 2) + 7 * 72 + 44 + 3 * 30 * 8 + 10 * 72
 
 
 def test_counter_traffic_tracks_the_sources(tmp_path, monkeypatch):
