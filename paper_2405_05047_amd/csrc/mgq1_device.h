@@ -130,10 +130,18 @@ __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int n
     for (int qq = 0; qq < NB; ++qq) di[qq] = stream_load<NT>(A.didx + int64_t(k + qq) * R + r);
     __builtin_amdgcn_sched_barrier(0);
     const int c = rl % B;
+    if (A.dlds) {
+      extern __shared__ double dict_lds[];
 #pragma unroll
-    for (int qq = 0; qq < NB; ++qq)
+      for (int qq = 0; qq < NB; ++qq)
 #pragma unroll
-      for (int cc = 0; cc < B; ++cc) av[qq][cc] = A.dtab[(int64_t(di[qq]) * B + c) * B + cc];
+        for (int cc = 0; cc < B; ++cc) av[qq][cc] = dict_lds[(int(di[qq]) * B + c) * B + cc];
+    } else {
+#pragma unroll
+      for (int qq = 0; qq < NB; ++qq)
+#pragma unroll
+        for (int cc = 0; cc < B; ++cc) av[qq][cc] = A.dtab[(int64_t(di[qq]) * B + c) * B + cc];
+    }
   } else {
 #pragma unroll
     for (int qq = 0; qq < NB; ++qq) js[qq] = slot_col<C16, NT>(A, k + qq, int64_t(k + qq) * R + r);
@@ -171,6 +179,26 @@ __device__ __forceinline__ void sell_batch(const SellDev& A, int k, int r, int n
   for (int qq = 0; qq < NB; ++qq)
 #pragma unroll
     for (int cc = 0; cc < B; ++cc) acc += T(Val<K>::dec(av[qq][cc])) * T(xv[qq][cc]);
+}
+
+// dictionary form with dlds set: the workgroup copies the dictionary into LDS before any
+// slice work (all threads reach the barrier); launched with ndict * B * B doubles of
+// dynamic shared memory
+template <int K>
+__device__ __forceinline__ void dict_stage(const SellDev& A) {
+  if constexpr (K == VK_DICT) {
+    if (A.dlds) {
+      extern __shared__ double dict_lds[];
+      const int n = A.ndict * A.B * A.B;
+      for (int i = int(threadIdx.x); i < n; i += int(blockDim.x)) dict_lds[i] = A.dtab[i];
+      __syncthreads();
+    }
+  }
+}
+
+template <int K>
+inline size_t dict_lds_bytes(const SellDev& A) {
+  return (K == VK_DICT && A.dlds) ? size_t(A.ndict) * A.B * A.B * sizeof(double) : 0;
 }
 
 // The same batch for the second of two sweeps from x = 0 with b = 1: the iterate after the

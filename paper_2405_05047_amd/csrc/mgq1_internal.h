@@ -45,6 +45,7 @@ struct SellDev {
   const uint16_t* didx = nullptr;
   const double* dtab = nullptr;
   int32_t ndict = 0;
+  int dlds = 0;                     // VK_DICT: every workgroup first copies dtab into LDS
 };
 
 // the two slot-batch sizes the slice kernels are built for (default, alternative)

@@ -51,6 +51,7 @@ template <int B, int K, class XI, class XO, class T, int MODE, bool NORM, int KB
 __global__ __launch_bounds__(kThreads) void k_spmv(SellDev A, const XO* __restrict__ b, const XI* __restrict__ x,
                                                    XO* __restrict__ y, const uint8_t* __restrict__ mask,
                                                    double* __restrict__ partials, const double* __restrict__ dotv) {
+  dict_stage<K>(A);
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const SliceLane s = slice_lane<B, 1>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
   const T out = spmv_slice<B, 1, K, XI, XO, T, MODE, KB, C16>(A, b, x, y, mask, s);
@@ -65,6 +66,7 @@ template <int B, int K, class X, class T, int KB, bool C16>
 __global__ __launch_bounds__(kThreads) void k_sweep(SellDev A, const X* __restrict__ S, const X* __restrict__ b,
                                                     const X* __restrict__ x, X* __restrict__ xo, T omega,
                                                     T beta, int pmode) {
+  dict_stage<K>(A);
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const SliceLane s = slice_lane<B, 1>(A, bid * kSliceWaves + threadIdx.x / kWave, threadIdx.x % kWave);
   sweep_slice<B, 1, K, X, T, KB, C16>(A, S, b, x, xo, omega, s, beta, pmode);
@@ -552,7 +554,7 @@ hipError_t spmv_t(const SellDev& A, const void* b, const void* x, void* y, const
   XO* yy = static_cast<XO*>(y);
   // slot batch and column format are runtime properties of the operator
 #define MGQ1_SPMV4(MODE, NORM, KB, C16)                                                                     \
-  hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, MODE, NORM, KB, C16>), g, kThreads, 0, s, A, bb, xx, yy, mask, partials, \
+  hipLaunchKernelGGL((k_spmv<B, K, XI, XO, T, MODE, NORM, KB, C16>), g, kThreads, dict_lds_bytes<K>(A), s, A, bb, xx, yy, mask, partials, \
                      dotv)
 #define MGQ1_SPMV(MODE, NORM)                                                             \
   if (A.col16) {                                                                          \
@@ -606,7 +608,7 @@ hipError_t sweep_t(const SellDev& A, const void* S, const void* b, const void* x
   const X* xx = static_cast<const X*>(x);
   X* oo = static_cast<X*>(xo);
 #define MGQ1_SWEEP4(KIND, KB, C16) \
-  hipLaunchKernelGGL((k_sweep<B, KIND, X, T, KB, C16>), g, kThreads, 0, s, A, SS, bb, xx, oo, T(omega), T(beta), pmode)
+  hipLaunchKernelGGL((k_sweep<B, KIND, X, T, KB, C16>), g, kThreads, dict_lds_bytes<KIND>(A), s, A, SS, bb, xx, oo, T(omega), T(beta), pmode)
 #define MGQ1_SWEEP(KIND)                                                   \
   if (A.col16) {                                                           \
     if (A.kb == kb_alt<B>()) MGQ1_SWEEP4(KIND, kb_alt<B>(), true);         \

@@ -781,6 +781,7 @@ int upload_dict(DevOwner* h, const HostSell& S, SellDev& D, hipStream_t s, bool*
   D.didx = di;
   D.dtab = dt;
   D.ndict = int32_t(dict.size());
+  D.dlds = tab.size() * sizeof(double) <= 16384 ? 1 : 0;     // small tables: one LDS copy per workgroup
   D.nt = stream_nt(int64_t(S.col.size()) * (D.col16 ? 2 : 4) + nblk * 2);
   *applied = true;
   return MG_OK;
