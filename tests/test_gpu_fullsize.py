@@ -77,6 +77,14 @@ def test_fullsize_sampled_parity(name):
     got = xs.cpu().numpy()
     assert np.abs(got[idx] - np.array(ref["solution"])).max() <= 1e-10 * ref["solution_norm"]
     assert abs(np.linalg.norm(got) - ref["solution_norm"]) <= 1e-10 * ref["solution_norm"]
+    if name in ("c2", "c3"):
+        # the block-dictionary form at full size: bitwise the plain FP64 solve
+        del h
+        hd = mg.Hierarchy(p.levels, mg.config_from(wl, precision="fp64dict"))
+        xd = torch.zeros_like(bd)
+        std = hd.solve(bd, xd)
+        _log(name, "dictionary form", [hd.dictionary_blocks(l) for l in range(hd.n_levels)], std["iters"])
+        assert std["iters"] == st["iters"] and np.array_equal(xd.cpu().numpy(), got)
 
 
 def test_fullsize_batch_converges_and_matches_oracle_members():
