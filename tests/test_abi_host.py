@@ -100,7 +100,7 @@ def test_smoother_blocks_validated(levels):
     assert "smoother" in mg.last_error()
 
 
-@pytest.mark.parametrize("bad", ["nrhs3", "outer_ir", "coarse_smooth", "nrhs8_block3", "block_mismatch"])
+@pytest.mark.parametrize("bad", ["nrhs3", "outer_ir", "coarse_smooth", "dictionary", "nrhs8_block3", "block_mismatch"])
 def test_batch_setup_rejects_unsupported_requests(levels, bad):
     """mg_setup_batch refuses requests it does not implement before touching a device."""
     import ctypes as C
@@ -113,6 +113,8 @@ def test_batch_setup_rejects_unsupported_requests(levels, bad):
         cfg.outer = 0
     elif bad == "coarse_smooth":
         cfg.coarse_mode = 1
+    elif bad == "dictionary":
+        cfg.precision = mg.PREC["fp64dict"]
     elif bad == "nrhs8_block3":
         problems, nrhs = [gen.build(W.c3_elasticity(1)).levels], 8
     else:
