@@ -206,7 +206,9 @@ int mg_coarse_solve(mg_handle* h, const void* b, void* x, void* stream);
  * BF16 with e_i the smallest integer with max_j |a_ij| <= 2^e_i per scalar row).
  * values: host buffer of nnzb * b * b entries of the storage type (double, float or
  * uint16 codes), block row-major; row_exp: host buffer of n_nodes * b exponents e_i,
- * required for FP16 / BF16 handles, ignored (may be NULL) otherwise.  Synchronous. */
+ * required for FP16 / BF16 handles, ignored (may be NULL) otherwise.  Synchronous.
+ * MG_EUNSUPPORTED on a block-dictionary handle (MG_PREC_FP64_DICT), which keeps no
+ * per-block values. */
 int mg_level_export(const mg_handle* h, int32_t level, void* values, int8_t* row_exp);
 
 /* Sizes of level `level`: nodes, block size, stored blocks. */

@@ -297,12 +297,13 @@ class Hierarchy:
 
     def export(self, l):
         """Stored cycle operator of level l in BSR order: (values (nnzb, b, b) of the storage
-        dtype: float64, float32 or uint16 codes; row exponents (n * b,) int8 or None)."""
+        dtype: float64, float32 or uint16 codes; row exponents (n * b,) int8 or None).  A
+        block-dictionary handle keeps no per-block values: the library refuses it (MGError)."""
         n, b, nnzb = self.sizes[l]
         prec = self.cfg.precision
-        dt = {0: np.float64, 1: np.float32, 2: np.uint16, 3: np.uint16}[prec]
+        dt = {0: np.float64, 1: np.float32, 2: np.uint16, 3: np.uint16, 4: np.float64}[prec]
         vals = np.zeros((nnzb, b, b), dt)
-        ex = np.zeros(n * b, np.int8) if prec >= 2 else None
+        ex = np.zeros(n * b, np.int8) if prec in (2, 3) else None
         _check(lib().mg_level_export(self.h, l, vals.ctypes.data, None if ex is None else ex.ctypes.data))
         return vals, ex
 

@@ -470,6 +470,8 @@ def test_dictionary_form_bitwise_equal(name):
         st = h.solve(dev(o.b), x)
         res.append((v, host(x), st["iters"]))
     assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1]) and res[0][2] == res[1][2]
+    with pytest.raises(mg.MGError, match="dictionary"):
+        hd.export(hd.n_levels - 1)
     _log(name, "dictionary form bitwise equal; distinct blocks per level", nd)
 
 
