@@ -489,6 +489,54 @@ def test_dictionary_form_with_chebyshev():
     assert np.array_equal(res[0][0], res[1][0]) and res[0][1] == res[1][1]
 
 
+@pytest.mark.parametrize("perturbed", [40000, "all"])
+def test_dictionary_form_large_and_refused_tables(perturbed):
+    """The finest elasticity operator with `perturbed` of its blocks (those between two
+    unconstrained nodes) scaled by distinct factors 1 + 1e-6 u: about 40,000 distinct
+    blocks still form a dictionary (a 2.9 MB table read through the caches), more than
+    65,535 leave that level's values plain while the coarser levels keep theirs.  Either
+    way every step and the solve are bitwise those of the plain FP64 handle on the same
+    operators."""
+    import dataclasses
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair("elast17")
+    levels = list(p.levels)
+    fin = levels[-1]
+    nnzb = len(fin.val)
+    # blocks coupling two unconstrained nodes (constrained rows and columns stay identity)
+    free = ~fin.mask.astype(bool).any(axis=1)
+    sel = np.flatnonzero(free[np.repeat(np.arange(fin.n), np.diff(fin.rowptr))] & free[fin.col])
+    sel = sel if perturbed == "all" else sel[:perturbed]
+    val = fin.val.copy()
+    val[sel] *= (1.0 + 1e-6 * _rand(1400, len(sel)))[:, None, None]
+    levels[-1] = dataclasses.replace(fin, val=val)
+    distinct = len(np.unique(val.reshape(nnzb, -1).view(np.uint64), axis=0))
+    assert (distinct > 65535) == (perturbed == "all"), distinct
+    hp = mg.Hierarchy(levels, mg.config_from(wl))
+    hd = mg.Hierarchy(levels, mg.config_from(wl, precision="fp64dict"))
+    nd = [hd.dictionary_blocks(l) for l in range(hd.n_levels)]
+    if perturbed == "all":
+        assert nd[-1] == 0, nd
+    else:
+        assert distinct <= nd[-1] <= distinct + 1, (nd, distinct)   # + the zero padding block
+    assert all(n > 0 for n in nd[1:-1]), nd
+    L = hd.n_levels - 1
+    x = dev(_rand(1401, fin.n * fin.block))
+    b = dev(_rand(1402, fin.n * fin.block))
+    outs = []
+    for h in (hp, hd):
+        y = torch.zeros_like(x)
+        h.spmv(L, x, y)
+        xo = torch.zeros_like(x)
+        h.sweep(L, b, x, xo)
+        z = torch.zeros_like(x)
+        st = h.solve(b, z)
+        outs.append((host(y), host(xo), host(z), st["iters"]))
+    for a, c in zip(outs[0], outs[1]):
+        assert np.array_equal(a, c)
+    _log("perturbed", perturbed, "distinct", distinct, "dictionary blocks per level", nd)
+
+
 def _drop_masked_prolongation_rows(levels):
     """The levels with every P~ row of a fully masked fine node emptied.  Such a row never
     reaches a result: the prolongation leaves masked DoFs unchanged and the V-cycle's fine
