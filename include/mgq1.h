@@ -230,8 +230,9 @@ int mg_level_tuning(const mg_handle* h, int32_t level, int32_t* slot_batch, int3
  * per weight of P~.  (2, 2, 1): the node form (one lane per node; 16-bit column offsets
  * from a per-slot base and the weight code w * 128 packed with the column mask bits into
  * 32 bits), used when every weight is a multiple of 1/128 up to 255/128 (the weights of
- * nested box meshes) and every slot's columns span less than 2^16; else 4-byte columns
- * and FP32 (4) or FP64 (8) weights.  Every form gives the same bits (Sec. 4.1:
+ * nested box meshes) and every slot's columns span less than 2^16; else, level by level,
+ * 4-byte columns and FP32 (4) weights when FP32 holds every weight exactly, FP64 (8)
+ * otherwise.  Every form gives the same bits (Sec. 4.1:
  * prolongation and restriction as sparse products).  Any output pointer may be NULL. */
 int mg_level_transfer_format(const mg_handle* h, int32_t level, int32_t* p_col_bytes, int32_t* r_col_bytes,
                              int32_t* weight_bytes);

@@ -439,6 +439,54 @@ def test_compact_transfers_bitwise_equal(name, prec, monkeypatch):
     _log(name, prec, "compact transfers bitwise equal; formats", compact)
 
 
+@pytest.mark.parametrize("change", ["off_grid", "not_fp32", "negative", "large"])
+@pytest.mark.parametrize("name", ["td_band", "elast17"])
+def test_transfers_fall_back_per_level(name, change, monkeypatch):
+    """One P~ weight of the finest level that the 8-bit code w * 128 in [0, 255] cannot
+    hold (w (1 + 2^-20), w (1 + 2^-40), -w, or 2.5): that level's transfers fall back by
+    themselves to the per-DoF form with 32-bit columns and FP32 weights (FP64 for
+    w (1 + 2^-40), which FP32 does not hold), the coarser levels keep the form they had,
+    and restriction, prolongation, V-cycle and a fixed-count solve are bitwise those of
+    the per-DoF form on every level."""
+    import dataclasses
+    from paper_2405_05047_amd import mg
+    wl, o, mgo, p, h64 = _pair(name)
+    levels = list(p.levels)
+    fin = levels[-1]
+    pv = fin.p_val.copy()
+    j = int(np.flatnonzero((pv > 0) & (pv < 1))[0])
+    pv[j] = {"off_grid": pv[j] * (1 + 2.0 ** -20), "not_fp32": pv[j] * (1 + 2.0 ** -40),
+             "negative": -pv[j], "large": 2.5}[change]
+    levels[-1] = dataclasses.replace(fin, p_val=pv)
+    before = [h64.transfer_format(l) for l in range(1, h64.n_levels)]
+    assert before[-1] == (2, 2, 1), before
+    outs = []
+    for plain in ("0", "1"):
+        monkeypatch.setenv("MGQ1_PLAIN_TRANSFERS", plain)
+        h = mg.Hierarchy(levels, mg.config_from(wl))
+        fmt = [h.transfer_format(l) for l in range(1, h.n_levels)]
+        if plain == "0":
+            wbytes = 8 if change == "not_fp32" else 4
+            assert fmt[:-1] == before[:-1] and fmt[-1] == (4, 4, wbytes), (fmt, before)
+        steps = []
+        for l in range(1, h.n_levels):
+            f, c = o.levels[l], o.levels[l - 1]
+            d = torch.zeros(c.ndof, dtype=torch.float64, device="cuda")
+            h.restrict(l, dev(_rand(1500 + l, f.ndof)), d)
+            xt = dev(_rand(1550 + l, f.ndof))
+            h.prolong(l, dev(_rand(1590 + l, c.ndof)), xt)
+            steps += [host(d), host(xt)]
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        h.vcycle(dev(o.b), x)
+        vc = host(x)
+        x = torch.zeros(len(o.b), dtype=torch.float64, device="cuda")
+        h.solve(dev(o.b), x, fixed=4)
+        outs.append((steps, vc, host(x)))
+    (s0, v0, x0), (s1, v1, x1) = outs
+    assert all(np.array_equal(a, b) for a, b in zip(s0, s1))
+    assert np.array_equal(v0, v1) and np.array_equal(x0, x1)
+
+
 @pytest.mark.parametrize("name", ["poisson33", "td_band", "elast17", "oseen17", "edge4", "oseen_tall"])
 def test_dictionary_form_bitwise_equal(name):
     """MG_PREC_FP64_DICT stores each level's distinct FP64 blocks once and a 16-bit index
